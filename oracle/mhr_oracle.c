@@ -1,0 +1,257 @@
+/*
+ * CPU oracle for exact three-hop top-K path search.  TEST INFRASTRUCTURE
+ * ONLY: the tests, the smoke check and the benchmark's CPU-baseline leg use
+ * it; the product path never calls it.  It shares no code with the GPU
+ * library.
+ *
+ * What it computes (the plain definition; every step in FP64):
+ *  - Canonical graph: the input triples (h, r, t) of the problem statement
+ *    (section 3.1, the three inputs) sorted and with identical triples
+ *    removed.  Edges are directed h -> t.
+ *  - Edge weight: the DistMult score x(u,r,v) = sum_i (X[u,i]*Y[r,i])*X[v,i],
+ *    summed in ascending i, passed through the log-sigmoid
+ *    w = min(x,0) - log1p(exp(-|x|)).  (The paper only says edge weights come
+ *    from learned vertex and relation embeddings, section 1; the DistMult +
+ *    log-sigmoid scorer is the reading this project takes.)
+ *  - Paths: every walk s -r1-> a -r2-> b -r3-> t of exactly three edges
+ *    (the three-hop query of section 3.1); a and b may repeat s, t or each
+ *    other.  Score S = (w1 + w2) + w3.
+ *  - Order: S descending, then a, b, r1, r2, r3 ascending (a total order);
+ *    the result is the first min(K, |P|) paths, the top-K ranked list the
+ *    generic algorithm (section 5) returns.
+ *
+ * Enumeration: for each out-edge (s, r1, a), each out-edge (a, r2, b), the
+ * out-edges of b with tail t are found by binary search in b's row (rows
+ * are sorted by (tail, relation)), and every r3 is emitted.  All paths of a
+ * query are collected and sorted; nothing is pruned.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    uint32_t n, R;
+    uint64_t m;          /* distinct triples */
+    uint64_t *rowptr;    /* n + 1 */
+    uint32_t *tail;      /* m, sorted by (tail, rel) within each row */
+    uint32_t *rel;       /* m */
+} og_graph;
+
+typedef struct {
+    double s;
+    uint32_t a, b, r1, r2, r3;
+} og_path;
+
+/* ------------------------------------------------------------------ */
+/* graph                                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct { uint32_t u, v, r; } og_triple;
+
+static int cmp_triple(const void *x, const void *y)
+{
+    const og_triple *p = (const og_triple *)x, *q = (const og_triple *)y;
+    if (p->u != q->u) return p->u < q->u ? -1 : 1;
+    if (p->v != q->v) return p->v < q->v ? -1 : 1;
+    if (p->r != q->r) return p->r < q->r ? -1 : 1;
+    return 0;
+}
+
+/* Returns the canonical graph, or NULL if an id is out of range or memory
+ * runs out. */
+og_graph *og_graph_build(uint32_t n, uint32_t R, uint64_t m,
+                         const uint32_t *head, const uint32_t *rel,
+                         const uint32_t *tail)
+{
+    og_triple *t = (og_triple *)malloc((m ? m : 1) * sizeof(og_triple));
+    if (!t) return NULL;
+    for (uint64_t i = 0; i < m; ++i) {
+        if (head[i] >= n || tail[i] >= n || rel[i] >= R) { free(t); return NULL; }
+        t[i].u = head[i]; t[i].v = tail[i]; t[i].r = rel[i];
+    }
+    qsort(t, m, sizeof(og_triple), cmp_triple);
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < m; ++i)
+        if (k == 0 || cmp_triple(&t[k - 1], &t[i]) != 0) t[k++] = t[i];
+
+    og_graph *g = (og_graph *)calloc(1, sizeof(og_graph));
+    g->n = n; g->R = R; g->m = k;
+    g->rowptr = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    g->tail = (uint32_t *)malloc((k ? k : 1) * sizeof(uint32_t));
+    g->rel = (uint32_t *)malloc((k ? k : 1) * sizeof(uint32_t));
+    if (!g->rowptr || !g->tail || !g->rel) { free(t); return NULL; }
+    for (uint64_t i = 0; i < k; ++i) {
+        g->rowptr[t[i].u + 1]++;
+        g->tail[i] = t[i].v;
+        g->rel[i] = t[i].r;
+    }
+    for (uint32_t u = 0; u < n; ++u) g->rowptr[u + 1] += g->rowptr[u];
+    free(t);
+    return g;
+}
+
+void og_graph_free(og_graph *g)
+{
+    if (!g) return;
+    free(g->rowptr); free(g->tail); free(g->rel); free(g);
+}
+
+uint64_t og_graph_edges(const og_graph *g) { return g->m; }
+
+/* Copies the canonical CSR out (rowptr n+1, tail m, rel m). */
+void og_graph_export(const og_graph *g, uint64_t *rowptr, uint32_t *tail, uint32_t *rel)
+{
+    memcpy(rowptr, g->rowptr, ((size_t)g->n + 1) * sizeof(uint64_t));
+    memcpy(tail, g->tail, g->m * sizeof(uint32_t));
+    memcpy(rel, g->rel, g->m * sizeof(uint32_t));
+}
+
+/* ------------------------------------------------------------------ */
+/* edge weight                                                          */
+/* ------------------------------------------------------------------ */
+
+double og_logsigmoid(double x)
+{
+    return fmin(x, 0.0) - log1p(exp(-fabs(x)));
+}
+
+/* DistMult score of (u, r, v): sum over i ascending of (X[u,i]*Y[r,i])*X[v,i]. */
+static double og_x(uint32_t d, const float *X, const float *Y,
+                   uint32_t u, uint32_t r, uint32_t v)
+{
+    const float *xu = X + (size_t)u * d, *yr = Y + (size_t)r * d, *xv = X + (size_t)v * d;
+    double acc = 0.0;
+    for (uint32_t i = 0; i < d; ++i)
+        acc += ((double)xu[i] * (double)yr[i]) * (double)xv[i];
+    return acc;
+}
+
+double og_edge_weight(uint32_t d, const float *X, const float *Y,
+                      uint32_t u, uint32_t r, uint32_t v)
+{
+    return og_logsigmoid(og_x(d, X, Y, u, r, v));
+}
+
+void og_edge_weights(uint32_t d, const float *X, const float *Y, uint64_t ne,
+                     const uint32_t *u, const uint32_t *r, const uint32_t *v,
+                     double *out_x, double *out_w)
+{
+    for (uint64_t i = 0; i < ne; ++i) {
+        double x = og_x(d, X, Y, u[i], r[i], v[i]);
+        if (out_x) out_x[i] = x;
+        out_w[i] = og_logsigmoid(x);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* top-K paths                                                          */
+/* ------------------------------------------------------------------ */
+
+/* The total order: score descending, then a, b, r1, r2, r3 ascending. */
+static int cmp_path(const void *x, const void *y)
+{
+    const og_path *p = (const og_path *)x, *q = (const og_path *)y;
+    if (p->s != q->s) return p->s > q->s ? -1 : 1;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    if (p->r1 != q->r1) return p->r1 < q->r1 ? -1 : 1;
+    if (p->r2 != q->r2) return p->r2 < q->r2 ? -1 : 1;
+    if (p->r3 != q->r3) return p->r3 < q->r3 ? -1 : 1;
+    return 0;
+}
+
+/* First index in [lo, hi) of row entries whose tail is >= key. */
+static uint64_t lower_tail(const uint32_t *tail, uint64_t lo, uint64_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (tail[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+typedef struct { og_path *p; uint64_t n, cap; int oom; } og_vec;
+
+static void vec_push(og_vec *v, og_path x)
+{
+    if (v->oom) return;
+    if (v->n == v->cap) {
+        uint64_t nc = v->cap ? v->cap * 2 : 1024;
+        og_path *np = (og_path *)realloc(v->p, nc * sizeof(og_path));
+        if (!np) { v->oom = 1; return; }
+        v->p = np; v->cap = nc;
+    }
+    v->p[v->n++] = x;
+}
+
+/* One query: all paths s -> a -> b -> t, sorted; keeps the first K.
+ * Returns the number of paths |P(s,t)|, or UINT64_MAX on allocation failure. */
+static uint64_t og_query(const og_graph *g, uint32_t d, const float *X, const float *Y,
+                         uint32_t s, uint32_t t, uint32_t K, og_path *out, uint32_t *count)
+{
+    og_vec v = {0};
+    for (uint64_t e1 = g->rowptr[s]; e1 < g->rowptr[s + 1]; ++e1) {
+        uint32_t a = g->tail[e1], r1 = g->rel[e1];
+        double w1 = og_edge_weight(d, X, Y, s, r1, a);
+        for (uint64_t e2 = g->rowptr[a]; e2 < g->rowptr[a + 1]; ++e2) {
+            uint32_t b = g->tail[e2], r2 = g->rel[e2];
+            uint64_t lo = lower_tail(g->tail, g->rowptr[b], g->rowptr[b + 1], t);
+            uint64_t e3 = lo;
+            if (e3 >= g->rowptr[b + 1] || g->tail[e3] != t) continue;
+            double w2 = og_edge_weight(d, X, Y, a, r2, b);
+            for (; e3 < g->rowptr[b + 1] && g->tail[e3] == t; ++e3) {
+                uint32_t r3 = g->rel[e3];
+                double w3 = og_edge_weight(d, X, Y, b, r3, t);
+                og_path p;
+                p.s = (w1 + w2) + w3;
+                p.a = a; p.b = b; p.r1 = r1; p.r2 = r2; p.r3 = r3;
+                vec_push(&v, p);
+            }
+        }
+    }
+    if (v.oom) { free(v.p); *count = 0; return UINT64_MAX; }
+    if (v.n) qsort(v.p, v.n, sizeof(og_path), cmp_path);
+    uint64_t keep = v.n < K ? v.n : K;
+    if (keep) memcpy(out, v.p, keep * sizeof(og_path));
+    *count = (uint32_t)keep;
+    uint64_t total = v.n;
+    free(v.p);
+    return total;
+}
+
+/* Batch of queries; OpenMP over queries (dynamic schedule).  out has
+ * nq * kmax records; k[q] <= kmax.  Returns 0, or -1 on a bad argument or
+ * allocation failure. */
+int og_topk(const og_graph *g, uint32_t d, const float *X, const float *Y,
+            uint32_t nq, const uint32_t *src, const uint32_t *dst,
+            const uint32_t *k, uint32_t kmax, int nthreads,
+            og_path *out, uint32_t *out_count, uint64_t *out_total)
+{
+    for (uint32_t q = 0; q < nq; ++q)
+        if (src[q] >= g->n || dst[q] >= g->n || k[q] == 0 || k[q] > kmax) return -1;
+    int fail = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < (int64_t)nq; ++q) {
+        uint64_t tot = og_query(g, d, X, Y, src[q], dst[q], k[q],
+                                out + (size_t)q * kmax, &out_count[q]);
+        if (tot == UINT64_MAX) fail = 1;
+        out_total[q] = tot;
+    }
+    return fail ? -1 : 0;
+}
+
+int og_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

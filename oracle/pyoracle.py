@@ -1,0 +1,46 @@
+"""Pure-Python oracle (tiny graphs only).  TEST INFRASTRUCTURE ONLY.
+
+The same definition as the C oracle, written independently: a dict-of-lists
+adjacency over the distinct triples, a literal triple loop over the edges
+s->a, a->b and b->t, math.log1p / math.exp for the log-sigmoid, and one full
+sort by the key tuple (-S, a, b, r1, r2, r3).  See ``oracle/__init__.py``
+for the definition; edge weights follow the DistMult + log-sigmoid reading,
+path scores the sum of the three weights of a three-hop walk (section 3.1).
+"""
+
+from __future__ import annotations
+
+import math
+from collections import defaultdict
+
+
+def logsigmoid(x: float) -> float:
+    return min(x, 0.0) - math.log1p(math.exp(-abs(x)))
+
+
+def edge_weight(X, Y, u, r, v) -> float:
+    acc = 0.0
+    for i in range(len(X[u])):
+        acc += (float(X[u][i]) * float(Y[r][i])) * float(X[v][i])
+    return logsigmoid(acc)
+
+
+def topk_paths(edges, X, Y, s, t, K):
+    """edges: iterable of (h, r, t) triples (duplicates allowed; they are
+    merged).  X, Y: nested sequences of floats.  Returns (paths, total) with
+    paths a list of (S, a, b, r1, r2, r3), best first."""
+    out = defaultdict(list)
+    for (h, r, v) in sorted(set((int(h), int(r), int(v)) for (h, r, v) in edges)):
+        out[h].append((r, v))
+    paths = []
+    for (r1, a) in out[s]:
+        w1 = edge_weight(X, Y, s, r1, a)
+        for (r2, b) in out[a]:
+            w2 = edge_weight(X, Y, a, r2, b)
+            for (r3, tt) in out[b]:
+                if tt != t:
+                    continue
+                w3 = edge_weight(X, Y, b, r3, t)
+                paths.append(((w1 + w2) + w3, a, b, r1, r2, r3))
+    paths.sort(key=lambda p: (-p[0], p[1], p[2], p[3], p[4], p[5]))
+    return paths[:K], len(paths)
