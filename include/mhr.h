@@ -1,0 +1,209 @@
+/*
+ * mhr.h - exact three-hop top-K path search over a typed knowledge graph,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper section 3.1 and the generic algorithm of section 5):
+ * given an edge list of typed directed edges (h, r, t), a relation
+ * embedding table and an entity embedding table, and queries (s, t, K),
+ * return the K best paths from s to t.  This library fixes the three-hop
+ * case: a path is a walk s -r1-> a -r2-> b -r3-> t of exactly three edges
+ * (a and b may repeat s, t or each other).  Edge weights come from the
+ * learned embeddings (section 1 leaves the function open; this library uses
+ * the DistMult score passed through a log-sigmoid):
+ *
+ *     x(u,r,v) = sum_i X[u][i] * Y[r][i] * X[v][i]
+ *     w(u,r,v) = logsigmoid(x) = min(x,0) - log1p(exp(-|x|))
+ *     S        = w(s,r1,a) + w(a,r2,b) + w(b,r3,t)
+ *
+ * Results are ranked by S descending, then a, b, r1, r2, r3 ascending (a
+ * total order; the paper returns a ranked heap, section 5), and are exact:
+ * the set and order equal those of an FP64 evaluation, up to pairs whose
+ * scores differ by less than the reported error bound (flagged).
+ *
+ * Conventions.
+ *  - Every function returns mhr_status.  No exception or abort crosses the
+ *    ABI.  Argument errors are detected on the host before anything is
+ *    enqueued; out-parameters are untouched on error.  The message of the
+ *    last error on the calling thread is available from mhr_last_error().
+ *  - Pointers documented as "device" point to device memory of the current
+ *    HIP device; the library never frees them.  Host pointers are read
+ *    before the call returns.
+ *  - "stream" is a hipStream_t (NULL = the null stream).  Query calls are
+ *    asynchronous on it; results are valid once the stream is synchronised.
+ *  - A graph handle may be queried concurrently from several streams, each
+ *    with its own workspace.
+ *  - Limits: num_relations <= 32; embedding dimension a power of two in
+ *    [8, 512]; K <= MHR_MAX_K.
+ */
+#ifndef MHR_H
+#define MHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mhr_status {
+    MHR_OK = 0,
+    MHR_ERR_INVALID_ARGUMENT = 1,
+    MHR_ERR_WORKSPACE_TOO_SMALL = 2,
+    MHR_ERR_UNSUPPORTED = 3,
+    MHR_ERR_OUT_OF_MEMORY = 4,
+    MHR_ERR_DEVICE = 5,
+    MHR_ERR_NO_EMBEDDINGS = 6,
+    MHR_ERR_BAD_EDGE = 7
+} mhr_status;
+
+typedef enum mhr_dtype {
+    MHR_DTYPE_F32 = 0,   /* IEEE binary32 */
+    MHR_DTYPE_BF16 = 1   /* bfloat16 bit patterns (uint16) */
+} mhr_dtype;
+
+#define MHR_MAX_K 224u
+#define MHR_MAX_RELATIONS 32u
+
+/* Per-query status word (out_status[q]); bits may combine. */
+#define MHR_Q_OK          0u
+#define MHR_Q_BAD_ID      1u   /* s or t >= num_vertices: count 0 */
+#define MHR_Q_BAD_K       2u   /* k == 0 or k > k_max: count 0 */
+#define MHR_Q_EXACT_PASS  4u   /* informational: the FP32 candidate band overflowed and
+                                  the exhaustive compensated pass produced the result */
+#define MHR_Q_OVERFLOW    8u   /* an internal capacity was exceeded: result incomplete */
+
+/* Per-path flags. */
+#define MHR_PATH_RESCORED       1u  /* score evaluated in compensated FP32 (float-float) */
+#define MHR_PATH_PRECISION_TIE  2u  /* the next path's score differs from this one by less
+                                       than the error bounds (their relative order is not
+                                       certified) */
+
+/* One ranked path s -r1-> a -r2-> b -r3-> t (24 bytes).  Unused slots of an
+ * output row hold a = b = 0xFFFFFFFF, score = -inf. */
+typedef struct mhr_path {
+    uint32_t a, b;
+    uint16_t r1, r2, r3, flags;
+    float score;      /* S rounded to FP32 */
+    float err_bound;  /* rigorous bound on |score - S| with S the exact real score
+                         (includes the final rounding to FP32) */
+} mhr_path;
+
+typedef struct mhr_graph mhr_graph;
+
+/* Edge list of the problem statement (section 3.1): triples (h, r, t).
+ * head/rel/tail: device arrays of num_edges uint32, read during
+ * mhr_graph_create only.  Identical triples are merged; h == t is allowed. */
+typedef struct mhr_graph_desc {
+    uint32_t num_vertices;
+    uint32_t num_relations;     /* 1 .. 32 */
+    uint64_t num_edges;         /* < 2^32 */
+    const uint32_t *head;
+    const uint32_t *rel;
+    const uint32_t *tail;
+} mhr_graph_desc;
+
+typedef struct mhr_graph_stats {
+    uint32_t num_vertices, num_relations;
+    uint64_t num_triples;        /* distinct (h, r, t) */
+    uint64_t num_pairs;          /* distinct (h, t); the length of each CSR */
+    uint32_t max_out_degree;     /* in distinct pairs */
+    uint32_t max_in_degree;
+    uint32_t dim;                /* 0 until embeddings are set */
+    uint32_t dtype;              /* mhr_dtype */
+    uint64_t device_bytes;       /* device memory held by the handle */
+    uint32_t heavy_rows_out, heavy_rows_in;  /* rows with a probe directory */
+} mhr_graph_stats;
+
+/* Builds the graph on the device (one-time ingest): forward CSR (rows =
+ * heads, entries = distinct tails ascending) and reverse CSR (rows = tails,
+ * entries = distinct heads ascending), each entry carrying the bitmask of
+ * relations joining the pair; plus bucket directories of long rows.  The
+ * handle owns the device memory it allocates (hipMalloc, here only).
+ * Synchronises `stream` before returning.  Errors: INVALID_ARGUMENT (null
+ * pointers, zero vertices, num_relations outside 1..32), BAD_EDGE (an id out
+ * of range), OUT_OF_MEMORY, DEVICE. */
+mhr_status mhr_graph_create(const mhr_graph_desc *desc, void *stream, mhr_graph **out);
+
+/* Attaches embeddings: entity[num_vertices][dim] and relation[num_relations][dim],
+ * row-major device arrays of `dtype`, BORROWED (they must stay valid and
+ * unchanged while the graph is queried), 16-byte aligned.  dim: power of two
+ * in [8, 512].  Enqueues nothing (`stream` is unused). */
+mhr_status mhr_graph_set_embeddings(mhr_graph *g, mhr_dtype dtype, uint32_t dim,
+                                    const void *entity, const void *relation, void *stream);
+
+mhr_status mhr_graph_get_stats(const mhr_graph *g, mhr_graph_stats *out);
+
+/* Copies one CSR into caller device buffers: row_ptr[num_vertices+1],
+ * col[num_pairs], rmask[num_pairs].  reverse = 0: forward, 1: reverse. */
+mhr_status mhr_graph_export_csr(const mhr_graph *g, int reverse, uint32_t *row_ptr,
+                                uint32_t *col, uint32_t *rmask, void *stream);
+
+mhr_status mhr_graph_destroy(mhr_graph *g);
+
+/* Query options.  Zero-initialise, then set what is needed. */
+typedef struct mhr_query_opts {
+    uint32_t k;            /* K for every query when the per-query array is NULL */
+    uint32_t tile_edges;   /* scan entries per work tile (0 = default) */
+    uint32_t grid_blocks;  /* persistent gather workgroups (0 = default) */
+    uint32_t hash_log2;    /* log2 of the LDS probe-table slots, 10..13 (0 = default) */
+    uint32_t reserved[8];  /* must be zero */
+} mhr_query_opts;
+
+/* Device workspace bytes needed by mhr_topk_paths for nq queries with
+ * K <= k_max.  Errors: INVALID_ARGUMENT, NO_EMBEDDINGS. */
+mhr_status mhr_workspace_size(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                              uint32_t k_max, size_t *bytes);
+
+/* Exact top-K three-hop paths for nq queries (src[q], dst[q], k[q]).
+ *   src, dst   device uint32[nq]
+ *   k          device uint32[nq], or NULL to use opts->k for every query
+ *   k_max      1..MHR_MAX_K; every k[q] must be <= k_max (else MHR_Q_BAD_K)
+ *   out        device mhr_path[nq][k_max]; row q holds out_count[q] paths, best first
+ *   out_count  device uint32[nq]: min(k[q], |P(s,t)|)
+ *   out_total  device uint64[nq] or NULL: |P(s,t)|, the number of paths scored
+ *   out_status device uint32[nq] or NULL: MHR_Q_* bits
+ *   workspace  device buffer of ws_bytes >= mhr_workspace_size(...)
+ * Asynchronous on `stream`; allocates nothing.  Errors: INVALID_ARGUMENT,
+ * WORKSPACE_TOO_SMALL, NO_EMBEDDINGS, DEVICE (launch failure). */
+mhr_status mhr_topk_paths(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                          const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                          uint32_t k_max, mhr_path *out, uint32_t *out_count,
+                          uint64_t *out_total, uint32_t *out_status,
+                          void *workspace, size_t ws_bytes, void *stream);
+
+/* Events recorded on `stream` around the phases of one mhr_topk_paths call,
+ * for timing the kernels on the stream they run on.  Each member is a
+ * hipEvent_t created by the caller, or NULL to skip it. */
+typedef struct mhr_phase_events {
+    void *begin;          /* before the planning kernel */
+    void *gather_begin;   /* before the gather kernel (after planning and scheduling) */
+    void *gather_end;     /* after the gather kernel */
+    void *end;            /* after the last kernel of the call */
+} mhr_phase_events;
+
+/* mhr_topk_paths with phase events (same arguments and semantics; ev may be
+ * NULL).  For benchmarks and profilers. */
+mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                                   const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                   uint32_t k_max, mhr_path *out, uint32_t *out_count,
+                                   uint64_t *out_total, uint32_t *out_status,
+                                   void *workspace, size_t ws_bytes, void *stream,
+                                   const mhr_phase_events *ev);
+
+/* Edge-weight kernel on its own (for checking the scorer):
+ * for each i < ne, the edge (u[i], r[i], v[i]) (it need not exist in the
+ * graph): w_f32[i] = FP32 log-sigmoid of the DistMult score and err_f32[i] a
+ * rigorous bound on its error; w_hi[i] + w_lo[i] = the compensated
+ * (float-float) value.  Any output pointer may be NULL.  Device arrays. */
+mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const uint32_t *u,
+                            const uint32_t *r, const uint32_t *v, float *w_f32,
+                            float *err_f32, float *w_hi, float *w_lo, void *stream);
+
+const char *mhr_status_string(mhr_status s);
+const char *mhr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHR_H */

@@ -15,8 +15,9 @@ Two independent implementations of the same plain definition:
 The definition (what both compute):
   edge weight  w(u,r,v) = logsigmoid( sum_i (X[u,i]*Y[r,i])*X[v,i] )  in FP64,
                logsigmoid(x) = min(x,0) - log1p(exp(-|x|));
-  path score   S = (w(s,r1,a) + w(a,r2,b)) + w(b,r3,t) over walks of exactly
-               three edges (the three-hop query of section 3.1);
+  path score   S = w(s,r1,a) + w(a,r2,b) + w(b,r3,t), the exact sum rounded
+               once to FP64, over walks of exactly three edges (the
+               three-hop query of section 3.1);
   order        S descending, then a, b, r1, r2, r3 ascending;
   result       the first min(K, |P(s,t)|) paths (a ranked top-K list, as the
                generic multi-hop algorithm of section 5 returns).
@@ -75,6 +76,8 @@ def _load():
         lib.og_topk.argtypes = [vp, u32, vp, vp, u32, vp, vp, vp, u32, ctypes.c_int,
                                 vp, vp, vp]
         lib.og_max_threads.restype = ctypes.c_int
+        lib.og_fsum.restype = ctypes.c_double
+        lib.og_fsum.argtypes = [vp, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -93,6 +96,14 @@ def as_f32_table(t: np.ndarray, dtype: str) -> np.ndarray:
 
 def logsigmoid(x: float) -> float:
     return _load().og_logsigmoid(float(x))
+
+
+def fsum(values) -> float:
+    """The C oracle's correctly rounded sum (used for path scores)."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    if len(v) > 8:
+        raise ValueError("at most 8 terms")
+    return _load().og_fsum(_ptr(v), len(v))
 
 
 class Graph:

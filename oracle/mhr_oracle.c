@@ -15,7 +15,8 @@
  *    log-sigmoid scorer is the reading this project takes.)
  *  - Paths: every walk s -r1-> a -r2-> b -r3-> t of exactly three edges
  *    (the three-hop query of section 3.1); a and b may repeat s, t or each
- *    other.  Score S = (w1 + w2) + w3.
+ *    other.  Score S = w1 + w2 + w3, the exact sum rounded once to FP64
+ *    (so two paths whose weights are the same multiset score equal).
  *  - Order: S descending, then a, b, r1, r2, r3 ascending (a total order);
  *    the result is the first min(K, |P|) paths, the top-K ranked list the
  *    generic algorithm (section 5) returns.
@@ -148,6 +149,61 @@ void og_edge_weights(uint32_t d, const float *X, const float *Y, uint64_t ne,
 }
 
 /* ------------------------------------------------------------------ */
+/* path score: the sum of three weights, correctly rounded              */
+/* ------------------------------------------------------------------ */
+
+/* Correctly rounded sum of n doubles (n small), after Shewchuk, "Adaptive
+ * Precision Floating-Point Arithmetic and Fast Robust Geometric Predicates"
+ * (1997): the running sum is kept as a list of non-overlapping partials
+ * built with error-free two-sums; the partials are then added from the
+ * largest, and a half-way case at the last step is settled by the sign of
+ * the next partial (round half to even on the exact sum).  The result
+ * depends only on the multiset of inputs, so paths whose weights are
+ * permutations of each other get bit-identical scores. */
+double og_fsum(const double *v, int n)
+{
+    double p[8];
+    int np = 0;
+    for (int k = 0; k < n; ++k) {
+        double x = v[k];
+        int i = 0;
+        for (int j = 0; j < np; ++j) {
+            double y = p[j];
+            if (fabs(x) < fabs(y)) { double t = x; x = y; y = t; }
+            double hi = x + y;
+            double lo = y - (hi - x);
+            if (lo != 0.0) p[i++] = lo;
+            x = hi;
+        }
+        p[i++] = x;
+        np = i;
+    }
+    if (np == 0) return 0.0;
+    int j = np - 1;
+    double hi = p[j], lo = 0.0;
+    while (j > 0) {
+        double x = hi, y = p[--j];
+        hi = x + y;
+        double yr = hi - x;
+        lo = y - yr;
+        if (lo != 0.0) break;
+    }
+    if (j > 0 && ((lo < 0.0 && p[j - 1] < 0.0) || (lo > 0.0 && p[j - 1] > 0.0))) {
+        double y = lo * 2.0;
+        double x = hi + y;
+        double yr = x - hi;
+        if (y == yr) hi = x;
+    }
+    return hi;
+}
+
+static double og_path_score(double w1, double w2, double w3)
+{
+    double v[3] = {w1, w2, w3};
+    return og_fsum(v, 3);
+}
+
+/* ------------------------------------------------------------------ */
 /* top-K paths                                                          */
 /* ------------------------------------------------------------------ */
 
@@ -207,7 +263,7 @@ static uint64_t og_query(const og_graph *g, uint32_t d, const float *X, const fl
                 uint32_t r3 = g->rel[e3];
                 double w3 = og_edge_weight(d, X, Y, b, r3, t);
                 og_path p;
-                p.s = (w1 + w2) + w3;
+                p.s = og_path_score(w1, w2, w3);
                 p.a = a; p.b = b; p.r1 = r1; p.r2 = r2; p.r3 = r3;
                 vec_push(&v, p);
             }

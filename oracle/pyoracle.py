@@ -3,7 +3,8 @@
 The same definition as the C oracle, written independently: a dict-of-lists
 adjacency over the distinct triples, a literal triple loop over the edges
 s->a, a->b and b->t, math.log1p / math.exp for the log-sigmoid, and one full
-sort by the key tuple (-S, a, b, r1, r2, r3).  See ``oracle/__init__.py``
+sort by the key tuple (-S, a, b, r1, r2, r3).  S is the correctly rounded
+sum of the three weights (math.fsum), so it depends only on their multiset.  See ``oracle/__init__.py``
 for the definition; edge weights follow the DistMult + log-sigmoid reading,
 path scores the sum of the three weights of a three-hop walk (section 3.1).
 """
@@ -41,6 +42,6 @@ def topk_paths(edges, X, Y, s, t, K):
                 if tt != t:
                     continue
                 w3 = edge_weight(X, Y, b, r3, t)
-                paths.append(((w1 + w2) + w3, a, b, r1, r2, r3))
+                paths.append((math.fsum((w1, w2, w3)), a, b, r1, r2, r3))
     paths.sort(key=lambda p: (-p[0], p[1], p[2], p[3], p[4], p[5]))
     return paths[:K], len(paths)

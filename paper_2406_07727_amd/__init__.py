@@ -1,0 +1,291 @@
+"""Exact three-hop top-K path search over a typed knowledge graph on MI355X.
+
+Thin Python binding of ``libmhr.so`` (the C ABI declared in
+``include/mhr.h``).  It only marshals arguments: device memory comes from
+torch tensors and the work is enqueued on torch's current HIP stream; every
+step of the search runs in the library's kernels.  There is no fallback: if
+the library is not built, importing this package raises ImportError.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2406_07727_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+# torch first: its bundled HIP runtime (soname libamdhip64.so.7) is then the
+# one libmhr.so's dependency resolves to, so device pointers and streams from
+# torch are valid in the library.  Loading libmhr.so first would pull a
+# second HIP runtime into the process.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MHR_OK = 0
+MHR_MAX_K = 224
+Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS, Q_OVERFLOW = 1, 2, 4, 8
+PATH_RESCORED, PATH_PRECISION_TIE = 1, 2
+DTYPE_F32, DTYPE_BF16 = 0, 1
+
+PATH_DTYPE = np.dtype([("a", np.uint32), ("b", np.uint32), ("r1", np.uint16), ("r2", np.uint16),
+                       ("r3", np.uint16), ("flags", np.uint16), ("score", np.float32),
+                       ("err_bound", np.float32)])
+assert PATH_DTYPE.itemsize == 24
+
+
+class _GraphDesc(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_uint32), ("num_relations", ctypes.c_uint32),
+                ("num_edges", ctypes.c_uint64), ("head", ctypes.c_void_p),
+                ("rel", ctypes.c_void_p), ("tail", ctypes.c_void_p)]
+
+
+class _GraphStats(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_uint32), ("num_relations", ctypes.c_uint32),
+                ("num_triples", ctypes.c_uint64), ("num_pairs", ctypes.c_uint64),
+                ("max_out_degree", ctypes.c_uint32), ("max_in_degree", ctypes.c_uint32),
+                ("dim", ctypes.c_uint32), ("dtype", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_uint64),
+                ("heavy_rows_out", ctypes.c_uint32), ("heavy_rows_in", ctypes.c_uint32)]
+
+
+class PhaseEvents(ctypes.Structure):
+    """hipEvent_t handles recorded around the phases of one query call."""
+    _fields_ = [("begin", ctypes.c_void_p), ("gather_begin", ctypes.c_void_p),
+                ("gather_end", ctypes.c_void_p), ("end", ctypes.c_void_p)]
+
+
+class QueryOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("tile_edges", ctypes.c_uint32),
+                ("grid_blocks", ctypes.c_uint32), ("hash_log2", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 8)]
+
+
+_vp, _u32, _u64, _i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_lib.mhr_graph_create.restype = _i
+_lib.mhr_graph_create.argtypes = [ctypes.POINTER(_GraphDesc), _vp, ctypes.POINTER(_vp)]
+_lib.mhr_graph_set_embeddings.restype = _i
+_lib.mhr_graph_set_embeddings.argtypes = [_vp, _i, _u32, _vp, _vp, _vp]
+_lib.mhr_graph_get_stats.restype = _i
+_lib.mhr_graph_get_stats.argtypes = [_vp, ctypes.POINTER(_GraphStats)]
+_lib.mhr_graph_export_csr.restype = _i
+_lib.mhr_graph_export_csr.argtypes = [_vp, _i, _vp, _vp, _vp, _vp]
+_lib.mhr_graph_destroy.restype = _i
+_lib.mhr_graph_destroy.argtypes = [_vp]
+_lib.mhr_workspace_size.restype = _i
+_lib.mhr_workspace_size.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_topk_paths.restype = _i
+_lib.mhr_topk_paths.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp,
+                                _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_topk_paths_profiled.restype = _i
+_lib.mhr_topk_paths_profiled.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp,
+                                         _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(PhaseEvents)]
+_lib.mhr_edge_weights.restype = _i
+_lib.mhr_edge_weights.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_status_string.restype = ctypes.c_char_p
+_lib.mhr_status_string.argtypes = [_i]
+_lib.mhr_last_error.restype = ctypes.c_char_p
+_lib.mhr_last_error.argtypes = []
+
+
+class MhrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.mhr_last_error().decode(errors="replace")
+        name = _lib.mhr_status_string(status).decode()
+        super().__init__(f"{where}: {name} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != MHR_OK:
+        raise MhrError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_u32(t):
+    """Contiguous 32-bit integer device tensor (int32 or uint32 storage)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t, dtype=np.int64).astype(np.uint32).view(np.int32))
+    if t.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        t = t.to(torch.int64).to(torch.int32)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class TopK:
+    """Result tensors (on the device) of one batched query."""
+    paths: "object"      # uint8 tensor [nq, k_max, 24] (mhr_path records)
+    count: "object"      # int32 tensor [nq]
+    total: "object"      # int64 tensor [nq]: |P(s,t)|
+    status: "object"     # int32 tensor [nq]
+    k_max: int
+
+    def to_numpy(self):
+        """(paths structured array [nq][k_max], count, total, status) on the host."""
+        p = self.paths.cpu().numpy().view(PATH_DTYPE).reshape(self.paths.shape[0], self.k_max)
+        return (p, self.count.cpu().numpy().view(np.uint32), self.total.cpu().numpy().view(np.uint64),
+                self.status.cpu().numpy().view(np.uint32))
+
+
+class Graph:
+    """A typed directed graph resident on the current HIP device.
+
+    head, rel, tail: integer device tensors (or host arrays) of one edge
+    list (h, r, t).  Identical triples are merged.  The device memory of the
+    handle is freed by ``close()`` or on garbage collection."""
+
+    def __init__(self, head, rel, tail, num_vertices: int, num_relations: int, stream=None):
+        torch = _torch()
+        h, r, t = _dev_u32(head), _dev_u32(rel), _dev_u32(tail)
+        if not (h.numel() == r.numel() == t.numel()):
+            raise ValueError("head, rel and tail must have the same length")
+        desc = _GraphDesc(int(num_vertices), int(num_relations), int(h.numel()),
+                          h.data_ptr(), r.data_ptr(), t.data_ptr())
+        handle = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(_lib.mhr_graph_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(handle)),
+               "mhr_graph_create")
+        self._h = handle
+        self.n = int(num_vertices)
+        self.R = int(num_relations)
+        self._emb = None
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.mhr_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_embeddings(self, entity, relation, dtype: Optional[str] = None, stream=None):
+        """entity [n][d], relation [R][d] device tensors: float32, bfloat16, or
+        int16/uint16 holding bfloat16 bit patterns.  The tensors are kept
+        alive by this object (the library borrows them)."""
+        torch = _torch()
+        if dtype is None:
+            dtype = "f32" if entity.dtype == torch.float32 else "bf16"
+        code = DTYPE_F32 if dtype == "f32" else DTYPE_BF16
+        X = entity.contiguous()
+        Y = relation.contiguous()
+        if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+            raise ValueError("embedding tables must be [n][d] and [R][d]")
+        if X.shape[0] != self.n or Y.shape[0] != self.R:
+            raise ValueError("embedding row counts must match the graph")
+        _check(_lib.mhr_graph_set_embeddings(self._h, code, int(X.shape[1]), X.data_ptr(), Y.data_ptr(),
+                                             _stream_ptr(stream)), "mhr_graph_set_embeddings")
+        self._emb = (X, Y)
+        self.dim = int(X.shape[1])
+
+    def stats(self) -> dict:
+        s = _GraphStats()
+        _check(_lib.mhr_graph_get_stats(self._h, ctypes.byref(s)), "mhr_graph_get_stats")
+        return {f: getattr(s, f) for f, _ in _GraphStats._fields_}
+
+    def export_csr(self, reverse: bool = False, stream=None):
+        """(row_ptr, col, rmask) int32 device tensors of the forward (or
+        reverse) CSR."""
+        torch = _torch()
+        st = self.stats()
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(1, st["num_pairs"]), dtype=torch.int32, device="cuda")
+        rm = torch.empty(max(1, st["num_pairs"]), dtype=torch.int32, device="cuda")
+        _check(_lib.mhr_graph_export_csr(self._h, int(reverse), rp.data_ptr(), col.data_ptr(), rm.data_ptr(),
+                                         _stream_ptr(stream)), "mhr_graph_export_csr")
+        return rp, col[:st["num_pairs"]], rm[:st["num_pairs"]]
+
+    def workspace_bytes(self, nq: int, k_max: int, opts: Optional[QueryOpts] = None) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.mhr_workspace_size(self._h, ctypes.byref(opts) if opts else None, int(nq), int(k_max),
+                                       ctypes.byref(n)), "mhr_workspace_size")
+        return int(n.value)
+
+    def topk(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
+             out: Optional[TopK] = None, stream=None, events: Optional[PhaseEvents] = None) -> TopK:
+        """Exact top-K three-hop paths for each (src[q], dst[q]).  k: an int
+        (same K for all) or a per-query integer tensor (then k_max bounds
+        it).  Asynchronous on the current stream."""
+        torch = _torch()
+        s, d = _dev_u32(src), _dev_u32(dst)
+        nq = s.numel()
+        o = QueryOpts() if opts is None else opts
+        kt = None
+        if k is None or isinstance(k, (int, np.integer)):
+            kk = int(k if k is not None else o.k)
+            o = QueryOpts(kk, o.tile_edges, o.grid_blocks, o.hash_log2)
+            if k_max is None:
+                k_max = kk
+        else:
+            kt = _dev_u32(k)
+            if k_max is None:
+                k_max = int(kt.max().item()) if nq else 1
+        k_max = int(k_max)
+        need = self.workspace_bytes(nq, k_max, o)
+        ws = self._ws.get("buf")
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+            self._ws["buf"] = ws
+        if out is None:
+            out = TopK(torch.empty((nq, k_max, 24), dtype=torch.uint8, device="cuda"),
+                       torch.empty(nq, dtype=torch.int32, device="cuda"),
+                       torch.empty(nq, dtype=torch.int64, device="cuda"),
+                       torch.empty(nq, dtype=torch.int32, device="cuda"), k_max)
+        if events is None:
+            _check(_lib.mhr_topk_paths(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
+                                       _ptr(out.paths), _ptr(out.count), _ptr(out.total), _ptr(out.status),
+                                       _ptr(ws), ws.numel(), _stream_ptr(stream)), "mhr_topk_paths")
+        else:
+            _check(_lib.mhr_topk_paths_profiled(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
+                                                _ptr(out.paths), _ptr(out.count), _ptr(out.total),
+                                                _ptr(out.status), _ptr(ws), ws.numel(), _stream_ptr(stream),
+                                                ctypes.byref(events)), "mhr_topk_paths_profiled")
+        out._keep = (s, d, kt)
+        return out
+
+    def edge_weights(self, u, r, v, stream=None):
+        """FP32 log-sigmoid DistMult weights with their error bounds, and the
+        compensated (hi, lo) values, for arbitrary (u, r, v) triples."""
+        torch = _torch()
+        U, Rr, V = _dev_u32(u), _dev_u32(r), _dev_u32(v)
+        ne = U.numel()
+        w = torch.empty(ne, dtype=torch.float32, device="cuda")
+        e = torch.empty_like(w)
+        hi = torch.empty_like(w)
+        lo = torch.empty_like(w)
+        _check(_lib.mhr_edge_weights(self._h, ne, _ptr(U), _ptr(Rr), _ptr(V), _ptr(w), _ptr(e), _ptr(hi),
+                                     _ptr(lo), _stream_ptr(stream)), "mhr_edge_weights")
+        return w, e, hi, lo
+
+
+__all__ = ["Graph", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+           "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]

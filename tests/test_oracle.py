@@ -103,6 +103,46 @@ def test_handworked_fixture_py_oracle():
             assert abs(p[0] - sum(dec_logsigmoid(x) for x in e["x"])) < 1e-14
 
 
+def test_fsum_is_correctly_rounded(oracle_lib):
+    """The path-score sum against Python's math.fsum (an independent
+    correctly rounded summation) on adversarial and random triples."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    cases = [(1.0, 1e-16, 1e-16), (1e16, 1.0, -1e16), (-0.6931471805599453,) * 3,
+             (1.0, 2.0 ** -53, 2.0 ** -106), (0.1, 0.2, 0.3), (-1e-300, 1e-300, 5e-324)]
+    cases += [tuple(rng.standard_normal(3) * 10.0 ** rng.integers(-20, 20, 3)) for _ in range(2000)]
+    cases += [tuple(-0.69 + rng.standard_normal(3) * 1e-3) for _ in range(2000)]
+    for c in cases:
+        assert oracle_lib.fsum(c) == math.fsum(c), c
+        # a function of the multiset only
+        assert oracle_lib.fsum(c[::-1]) == oracle_lib.fsum(c) == oracle_lib.fsum((c[1], c[2], c[0]))
+
+
+def test_permuted_weights_tie(oracle_lib):
+    """When a = t, DistMult symmetry makes the paths (r2, r3) = (x, y) and
+    (y, x) through the same b carry the same three weights in another
+    order: their scores are equal and the ids break the tie."""
+    n, R, d = 6, 2, 8
+    rng = np.random.Generator(np.random.PCG64(12))
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Y = rng.standard_normal((R, d)).astype(np.float32)
+    s, t, b = 0, 3, 4
+    edges = [(s, 0, t), (t, 0, b), (t, 1, b), (b, 0, t), (b, 1, t)]
+    h = np.array([e[0] for e in edges], np.uint32)
+    r = np.array([e[1] for e in edges], np.uint32)
+    tt = np.array([e[2] for e in edges], np.uint32)
+    g = oracle_lib.Graph(n, R, h, r, tt)
+    out, cnt, tot = g.topk(X, Y, [s], [t], 8)
+    got = out[0][:cnt[0]]
+    key = {(p["r2"], p["r3"]): p["s"] for p in got}
+    assert key[(0, 1)] == key[(1, 0)]
+    i01 = [i for i, p in enumerate(got) if (p["r2"], p["r3"]) == (0, 1)][0]
+    i10 = [i for i, p in enumerate(got) if (p["r2"], p["r3"]) == (1, 0)][0]
+    assert i01 < i10
+    paths, _ = pyoracle.topk_paths(edges, X.tolist(), Y.tolist(), s, t, 8)
+    assert [p[1:] for p in paths] == list(zip(got["a"].tolist(), got["b"].tolist(), got["r1"].tolist(),
+                                               got["r2"].tolist(), got["r3"].tolist()))
+
+
 @pytest.mark.parametrize("name", ["tiny", "dense_tiny", "hub_tiny"])
 def test_count_equals_adjacency_cube(oracle_lib, name):
     cfg, (h, r, t), X, Y, (s, d, k) = small_graph(name)
@@ -153,7 +193,7 @@ def test_all_zero_embeddings_tie_break(oracle_lib):
     Z = np.zeros_like(X)
     ZY = np.zeros_like(Y)
     out, cnt, tot = g.topk(Z, ZY, s[:6], d[:6], 25)
-    three = (-LN2 + -LN2) + -LN2
+    three = math.fsum([-LN2] * 3)
     for q in range(6):
         walks = _all_walks_numpy(n, h, r, t, int(s[q]), int(d[q]))
         assert len(walks) == int(tot[q])
