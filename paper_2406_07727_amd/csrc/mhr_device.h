@@ -196,9 +196,32 @@ __device__ __forceinline__ float load1(const void *base, size_t idx) {
     return static_cast<const float *>(base)[idx];
 }
 
-// Reduction over an aligned group of G lanes (G a power of two <= 64).
+// Cross-lane moves within rows of 16 lanes (DPP; no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Maximum over each row of 16 lanes (every lane of the row receives it).
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));
+    v = fmaxf(v, dpp_f<0x4E>(v));
+    v = fmaxf(v, dpp_f<0x141>(v));
+    v = fmaxf(v, dpp_f<0x140>(v));
+    return v;
+}
+
+// Sum over an aligned group of G lanes (G a power of two, 4..64); every lane
+// of the group receives the total.  Within a row: lane^1 and lane^2 by quad
+// permutes, then the other quad of each half-row (half mirror), then the
+// other half of the row (mirror); across rows: lane^16, lane^32.
 __device__ __forceinline__ float group_sum(float v, int G) {
-    for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    v += dpp_f<0xB1>(v);                      // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);                      // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_f<0x141>(v);         // row_half_mirror
+    if (G >= 16) v += dpp_f<0x140>(v);        // row_mirror
+    if (G >= 32) v += __shfl_xor(v, 16, kWave);
+    if (G >= 64) v += __shfl_xor(v, 32, kWave);
     return v;
 }
 

@@ -38,12 +38,12 @@ namespace mhr {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kEPT = 8;                   // scan entries per thread per chunk
+constexpr int kBlock = 512;
+constexpr int kEPT = 4;                   // scan entries per thread per chunk
 constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
 constexpr int kSlab = 1024;               // scored edge values per sub-batch
-constexpr int kStage = 512;               // staged candidates before a merge
+constexpr int kStage = 768;               // staged candidates before a merge
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kDefaultTileEdges = 32768;
 constexpr uint32_t kDefaultHashLog2 = 12;
@@ -60,10 +60,14 @@ struct GArgs {
     TileHeader *hdr;
     Cand *cands;
     uint32_t *exact_list;
-    uint32_t maxt, hash_log2, nq, kc;
+    uint32_t tcap, hash_log2, nq, kc, tile_edges;
 };
 
-__host__ __device__ inline uint32_t max_tiles_for(uint32_t kc) { return 2048u / kc; }
+constexpr uint32_t kMaxTilesPerQuery = 4096;
+constexpr uint32_t kMergeSlots = 2048;      // LDS candidates per merge step
+
+// Tiles the workspace holds for nq queries.
+__host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
 
 __device__ inline uint32_t nth_bit(uint32_t m, uint32_t k) {
     for (uint32_t i = 0; i < k; ++i) m &= m - 1;
@@ -122,8 +126,7 @@ __device__ inline T block_incl_scan(T v, T *lds, T *total) {
 // plan
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *src, const uint32_t *dst,
-                                                      const uint32_t *kq, uint32_t kdef, uint32_t kmax,
-                                                      uint32_t tile_edges) {
+                                                      const uint32_t *kq, uint32_t kdef, uint32_t kmax) {
     __shared__ uint64_t red64[kBlock / kWave];
     const uint32_t q = blockIdx.x;
     QueryPlan P{};
@@ -166,61 +169,65 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
     P.list_len = fwd ? lf_len : lb_len;
     P.probe_beg = fwd ? A.in_rp[P.t] : A.out_rp[P.s];
     P.probe_len = fwd ? (A.in_rp[P.t + 1] - P.probe_beg) : (A.out_rp[P.s + 1] - P.probe_beg);
-    uint32_t ntiles = 0;
-    if (P.cost > 0 && P.probe_len > 0) {
-        uint64_t nt = (P.cost + tile_edges - 1) / tile_edges;
-        ntiles = static_cast<uint32_t>(nt < A.maxt ? nt : A.maxt);
-    }
-    P.ntiles = ntiles;
-    if (ntiles > 0) {
-        // tile j starts at concatenated position j * L: record (row, offset)
-        const uint64_t L = (P.cost + ntiles - 1) / ntiles;
-        ntiles = static_cast<uint32_t>((P.cost + L - 1) / L);  // every start j*L < cost
-        P.ntiles = ntiles;
-        const uint32_t *rp = fwd ? A.out_rp : A.in_rp;
-        const uint32_t *col = fwd ? A.out_col : A.in_col;
-        uint64_t run = 0;
-        for (uint32_t base = 0; base < P.list_len; base += kBlock) {
-            uint32_t i = base + threadIdx.x;
-            uint64_t deg = 0;
-            if (i < P.list_len) {
-                uint32_t x = col[P.list_beg + i];
-                deg = rp[x + 1] - rp[x];
-            }
-            uint64_t tot;
-            uint64_t incl = block_incl_scan<uint64_t>(deg, red64, &tot);
-            uint64_t p0 = run + incl - deg;
-            if (deg > 0) {
-                uint64_t jlo = (p0 + L - 1) / L;
-                uint64_t jhi = (p0 + deg - 1) / L;
-                for (uint64_t j = jlo; j <= jhi && j < ntiles; ++j)
-                    A.tile_start[static_cast<uint64_t>(q) * A.maxt + j] =
-                        make_uint2(i, static_cast<uint32_t>(j * L - p0));
-            }
-            run += tot;
-        }
-    }
+    // tile count from the scan cost; the schedule may coarsen it to fit the
+    // workspace
+    P.ntiles = (P.cost > 0 && P.probe_len > 0) ? 1u : 0u;
     if (threadIdx.x == 0) A.plans[q] = P;
 }
 
 // ---------------------------------------------------------------------------
 // schedule (one workgroup)
 // ---------------------------------------------------------------------------
+// Tile length for a query: about `tile` scan entries, at most
+// kMaxTilesPerQuery tiles.  The tile count is then ceil(cost / length), so
+// every tile start j * length lies below cost.
+__device__ inline uint64_t tile_len_for(uint64_t cost, uint64_t tile) {
+    uint64_t nt = (cost + tile - 1) / tile;
+    if (nt > kMaxTilesPerQuery) nt = kMaxTilesPerQuery;
+    return (cost + nt - 1) / nt;
+}
+
+__device__ inline uint32_t tiles_for(uint64_t cost, uint64_t tile) {
+    if (cost == 0) return 0u;
+    const uint64_t L = tile_len_for(cost, tile);
+    return static_cast<uint32_t>((cost + L - 1) / L);
+}
+
+// One workgroup: per-query tile counts (tile size doubled until the batch
+// fits the workspace's tile capacity), their prefix and the tile -> query map.
 __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
     __shared__ uint32_t red[kBlock / kWave];
+    __shared__ uint64_t red64[kBlock / kWave];
     __shared__ uint32_t carry;
+    uint64_t tile = A.tile_edges;
+    for (;;) {
+        uint64_t part = 0;
+        for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
+            const QueryPlan &P = A.plans[q];
+            if (P.status == 0 && P.ntiles) part += tiles_for(P.cost, tile);
+        }
+        const uint64_t tot = block_sum<uint64_t>(part, red64);
+        if (tot <= A.tcap) break;
+        tile *= 2;
+    }
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (uint32_t base = 0; base < A.nq; base += kBlock) {
-        uint32_t q = base + threadIdx.x;
-        uint32_t nt = q < A.nq ? A.plans[q].ntiles : 0u;
-        uint32_t tot;
-        uint32_t incl = block_incl_scan<uint32_t>(nt, red, &tot);
-        uint32_t c = carry;
+        const uint32_t q = base + threadIdx.x;
+        uint32_t nt = 0;
         if (q < A.nq) {
-            uint32_t tb = c + incl - nt;
+            const QueryPlan &P = A.plans[q];
+            if (P.status == 0 && P.ntiles) nt = tiles_for(P.cost, tile);
+        }
+        uint32_t tot;
+        const uint32_t incl = block_incl_scan<uint32_t>(nt, red, &tot);
+        const uint32_t c = carry;
+        if (q < A.nq) {
+            const uint32_t tb = c + incl - nt;
+            A.plans[q].ntiles = nt;
             A.plans[q].tile_base = tb;
             A.plans[q].flags = 0;
+            A.plans[q].pad[0] = nt ? static_cast<uint32_t>(tile_len_for(A.plans[q].cost, tile)) : 0u;  // tile length
             for (uint32_t j = 0; j < nt; ++j) A.tile_q[tb + j] = q;
         }
         __syncthreads();
@@ -232,6 +239,38 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
         A.ctrl->gather_ctr = 0;
         A.ctrl->exact_ctr = 0;
         A.ctrl->exact_n = 0;
+    }
+}
+
+// One workgroup per query: tile j starts at position j * L of the
+// concatenation of the query's scanned rows; record (row, offset).
+__global__ __launch_bounds__(kBlock) void tile_starts_kernel(GArgs A) {
+    __shared__ uint64_t red64[kBlock / kWave];
+    const uint32_t q = blockIdx.x;
+    const QueryPlan P = A.plans[q];
+    if (P.status != 0 || P.ntiles == 0) return;
+    const uint64_t L = P.pad[0];
+    const bool fwd = P.dir != 0;
+    const uint32_t *rp = fwd ? A.out_rp : A.in_rp;
+    const uint32_t *col = fwd ? A.out_col : A.in_col;
+    uint64_t run = 0;
+    for (uint32_t base = 0; base < P.list_len; base += kBlock) {
+        const uint32_t i = base + threadIdx.x;
+        uint64_t deg = 0;
+        if (i < P.list_len) {
+            const uint32_t x = col[P.list_beg + i];
+            deg = rp[x + 1] - rp[x];
+        }
+        uint64_t tot;
+        const uint64_t incl = block_incl_scan<uint64_t>(deg, red64, &tot);
+        const uint64_t p0 = run + incl - deg;
+        if (deg > 0) {
+            const uint64_t jlo = (p0 + L - 1) / L;
+            const uint64_t jhi = (p0 + deg - 1) / L;
+            for (uint64_t j = jlo; j <= jhi && j < P.ntiles; ++j)
+                A.tile_start[P.tile_base + j] = make_uint2(i, static_cast<uint32_t>(j * L - p0));
+        }
+        run += tot;
     }
 }
 
@@ -295,6 +334,7 @@ __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint3
 // ---------------------------------------------------------------------------
 struct RowInfo {
     uint32_t x, mask, beg, len, pref, vbase;
+    float fmax, famax, emax;   // largest centred weight, |weight| and error bound of the row's list edges
 };
 
 struct GatherShared {
@@ -303,12 +343,9 @@ struct GatherShared {
     uint32_t stage_n;
     uint32_t list_n;
     uint32_t truncated;
-    uint32_t nrows;
     uint32_t E;           // entries in the current row batch
-    uint32_t nsub, nc;
     uint32_t rowvals;
-    float eps_max;
-    uint32_t pad;
+    uint32_t pad[3];
     Cand thr;             // current worst kept candidate (sentinel until the list fills)
     uint64_t red64[kBlock / kWave];
     uint32_t red32[kBlock / kWave];
@@ -318,9 +355,11 @@ struct GatherShared {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 struct GatherLayout {
-    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, queue_pos, queue_mp, sub_info, slab, slab_eps,
-        list, stage, shared, total;
+    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, qy, sub, slab, slab_eps, list, stage,
+        ymax, rowrel, slab_rel, agg, shared, total;
 };
+
+constexpr int kSubFields = 6;  // pos, y, mp, mm, row, voff
 
 __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32_t R, uint32_t d, uint32_t kc) {
     GatherLayout L{};
@@ -328,25 +367,30 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     const size_t slots = size_t(1) << hash_log2;
     L.hkeys = o; o = align16(o + slots * 4);
     L.hvals = o; o = align16(o + slots * 4);
-    L.Y = o; o = align16(o + size_t(R) * d * 4);
+    L.Y = o; o = align16(o + size_t(R) * (d + 4) * 4);
     L.anc_p = o; o = align16(o + size_t(d) * 4);
     L.anc_l = o; o = align16(o + size_t(d) * 4);
     L.rows = o; o = align16(o + kRowBatch * sizeof(RowInfo));
     L.rowval = o; o = align16(o + size_t(kRowBatch) * R * 4);
     L.roweps = o; o = align16(o + size_t(kRowBatch) * R * 4);
-    L.queue_pos = o; o = align16(o + kChunk * 4);
-    L.queue_mp = o; o = align16(o + kChunk * 4);
-    L.sub_info = o; o = align16(o + kBlock * 6 * 4);
+    L.qpos = o; o = align16(o + kChunk * 4);
+    L.qmp = o; o = align16(o + kChunk * 4);
+    L.qy = o; o = align16(o + kChunk * 4);
+    L.sub = o; o = align16(o + kBlock * kSubFields * 4);
+    L.agg = o; o = align16(o + kBlock * 6 * 4);
     L.slab = o; o = align16(o + kSlab * 4);
     L.slab_eps = o; o = align16(o + kSlab * 4);
     L.list = o; o = align16(o + size_t(kc) * sizeof(Cand));
     L.stage = o; o = align16(o + size_t(next_pow2(kStage + kc)) * sizeof(Cand));
+    L.ymax = o; o = align16(o + size_t(R) * 4);
+    L.rowrel = o; o = align16(o + size_t(kRowBatch) * R);
+    L.slab_rel = o; o = align16(o + kSlab);
     L.shared = o; o = align16(o + sizeof(GatherShared));
     L.total = o;
     return L;
 }
 
-// Elements per lane and lanes per edge for dimension d.
+// Lanes per scored edge and elements per lane for dimension d.
 __device__ __forceinline__ int lanes_per_edge(uint32_t d) {
     int g = static_cast<int>(d / 8);
     return g < 4 ? 4 : (g > 64 ? 64 : g);
@@ -358,20 +402,71 @@ __device__ __forceinline__ void load_lane(const void *base, size_t row, uint32_t
     if (epl == 8) {
         load8<BF16>(base, row, d, off, v);
     } else {
-        for (int l = 0; l < epl; ++l) v[l] = load1<BF16>(base, row * d + off + l);
-        for (int l = epl; l < 8; ++l) v[l] = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) v[l] = (l < epl) ? load1<BF16>(base, row * d + off + l) : 0.0f;
     }
 }
 
-// Centred weight of a scored edge and its error bound, from the lane
-// partial sums of one group.
-__device__ __forceinline__ void finish_edge(float part, float apart, int G, int epl, float *f, float *eps) {
-    float x = group_sum(part, G);
-    float as = group_sum(apart, G);
-    int lg = 31 - __clz(G);
-    float fx = centred_logsigmoid(x);
-    *f = fx;
-    *eps = gamma_n(epl + lg + 2) * as + centred_logsigmoid_err(fx);
+// Scores the edges of one match held by a group of G lanes (lane glane
+// owns elements [glane*epl, glane*epl + epl) of the d-vectors).  For each
+// relation r in maskA the value is x = sum_i a[i] Y[r][i], then for each r
+// in maskB x = sum_i b[i] Y[r][i]; the centred log-sigmoid of x goes to
+// out[k] (k = value index: maskA bits ascending, then maskB bits) with its
+// error bound in out_eps[k].  Values are produced four at a time: four
+// independent accumulators and reductions keep the lanes busy, and lane j
+// of the group evaluates the transcendental of value j.
+//
+// Error bound: each product a[i]*Y carries one rounding beyond the rounding
+// of a[i] itself and the sum adds epl - 1 + log2 G more, so
+// |x_fp32 - x| <= gamma_{epl + log2 G + 4} sum_i |a_i Y_ri|
+//              <= gamma_{...} max_i |Y_ri| * sum_i |a_i| (ymax, suma).
+__device__ inline void score_values(const float (&a)[8], float suma, uint32_t maskA, const float (&b)[8], float sumb,
+                                    uint32_t maskB, const float *Ys, const float *ymax, uint32_t ys, int G, int epl,
+                                    int glane, float *out, float *out_eps, uint8_t *out_rel) {
+    const int lg = 31 - __clz(G);
+    const float gam = gamma_n(epl + lg + 4) * 1.001f;
+    const uint32_t na = __popc(maskA), nv = na + __popc(maskB);
+    uint32_t ra = maskA, rb = maskB;
+    const int off = glane * epl;
+    for (uint32_t c = 0; c < nv; c += 4) {
+        float part[4];
+        uint32_t rel[4];
+        bool isa[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t v = c + j;
+            part[j] = 0.0f;
+            rel[j] = 0;
+            isa[j] = false;
+            if (v < nv) {
+                if (v < na) {
+                    rel[j] = static_cast<uint32_t>(__ffs(ra) - 1);
+                    ra &= ra - 1;
+                    isa[j] = true;
+                } else {
+                    rel[j] = static_cast<uint32_t>(__ffs(rb) - 1);
+                    rb &= rb - 1;
+                }
+                const float *yr = Ys + rel[j] * ys + off;
+                float acc = 0.0f;
+#pragma unroll
+                for (int l = 0; l < 8; ++l)
+                    if (l < epl) acc = __builtin_fmaf(isa[j] ? a[l] : b[l], yr[l], acc);
+                part[j] = acc;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] = group_sum(part[j], G);
+        if (glane < 4 && c + glane < nv) {
+            const float x = glane == 0 ? part[0] : glane == 1 ? part[1] : glane == 2 ? part[2] : part[3];
+            const uint32_t r = glane == 0 ? rel[0] : glane == 1 ? rel[1] : glane == 2 ? rel[2] : rel[3];
+            const bool ia = glane == 0 ? isa[0] : glane == 1 ? isa[1] : glane == 2 ? isa[2] : isa[3];
+            const float f = centred_logsigmoid(x);
+            out[c + glane] = f;
+            out_eps[c + glane] = gam * ymax[r] * (ia ? suma : sumb) + centred_logsigmoid_err(f);
+            out_rel[c + glane] = static_cast<uint8_t>(r);
+        }
+    }
 }
 
 // Merge the staged candidates into the kept list (whole block).
@@ -386,10 +481,9 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh) {
     }
     __syncthreads();
     block_sort_cands(stage, static_cast<int>(n2));
-    // entries past KC that are real candidates are dropped
     if (threadIdx.x == 0) {
         Cand c = stage[KC];
-        if (c.a != 0xFFFFFFFFu) sh->truncated = 1;
+        if (c.a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
         uint32_t cnt = sh->list_n + ns;
         sh->list_n = cnt < static_cast<uint32_t>(KC) ? cnt : KC;
         sh->stage_n = 0;
@@ -397,6 +491,56 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh) {
     }
     for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) list[i] = stage[i];
     __syncthreads();
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Up to 32 consecutive elements [off, off + n) of an embedding row (zeros
+// past n, or everywhere when !valid).  n is a multiple of 2 and off of n's
+// alignment: the loads are 16-byte vectors when n >= 4 (FP32) / 8 (BF16).
+template <bool BF16>
+__device__ __forceinline__ void load_span32(const void *base, uint32_t row, uint32_t d, uint32_t off, uint32_t n,
+                                            bool valid, float (&v)[32]) {
+#pragma unroll
+    for (int l = 0; l < 32; ++l) v[l] = 0.0f;
+    if (!valid) return;
+    if (n == 32) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float t[8];
+            load8<BF16>(base, row, d, off + 8 * c, t);
+#pragma unroll
+            for (int l = 0; l < 8; ++l) v[8 * c + l] = t[l];
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < 32; ++l)
+            if (static_cast<uint32_t>(l) < n) v[l] = load1<BF16>(base, static_cast<size_t>(row) * d + off + l);
+    }
+}
+
+// Insertion sort of n (<= 32) values into descending order, carrying their
+// relation ids.  Equal values keep their relation order.
+__device__ inline void sort_desc(float *v, uint8_t *rel, uint32_t n) {
+    for (uint32_t i = 1; i < n; ++i) {
+        const float x = v[i];
+        const uint8_t rx = rel[i];
+        uint32_t j = i;
+        while (j > 0 && v[j - 1] < x) {
+            v[j] = v[j - 1];
+            rel[j] = rel[j - 1];
+            --j;
+        }
+        v[j] = x;
+        rel[j] = rx;
+    }
+}
+
+// Partial sums used for the path score and its pruning bounds.  The same
+// association is used for a bound and for the score it bounds, so FP32
+// rounding (monotone) keeps every bound >= the scores below it.
+__device__ __forceinline__ float combine3(bool fwd, float fp, float fm, float fl) {
+    return fwd ? (fl + fm) + fp : (fp + fm) + fl;
 }
 
 template <bool BF16, bool EXACT, int KC>
@@ -411,17 +555,21 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     RowInfo *rows = reinterpret_cast<RowInfo *>(smem + Lo.rows);
     float *rowval = reinterpret_cast<float *>(smem + Lo.rowval);
     float *roweps = reinterpret_cast<float *>(smem + Lo.roweps);
-    uint32_t *qpos = reinterpret_cast<uint32_t *>(smem + Lo.queue_pos);
-    uint32_t *qmp = reinterpret_cast<uint32_t *>(smem + Lo.queue_mp);
-    uint32_t *sub = reinterpret_cast<uint32_t *>(smem + Lo.sub_info);
+    uint32_t *qpos = reinterpret_cast<uint32_t *>(smem + Lo.qpos);
+    uint32_t *qmp = reinterpret_cast<uint32_t *>(smem + Lo.qmp);
+    uint32_t *qy = reinterpret_cast<uint32_t *>(smem + Lo.qy);
+    uint32_t *sub = reinterpret_cast<uint32_t *>(smem + Lo.sub);
     float *slab = reinterpret_cast<float *>(smem + Lo.slab);
     float *slab_eps = reinterpret_cast<float *>(smem + Lo.slab_eps);
     Cand *list = reinterpret_cast<Cand *>(smem + Lo.list);
     Cand *stage = reinterpret_cast<Cand *>(smem + Lo.stage);
     GatherShared *sh = reinterpret_cast<GatherShared *>(smem + Lo.shared);
-    // per sub-batch match info (one match per thread)
-    uint32_t *sub_pos = sub, *sub_mp = sub + kBlock, *sub_mm = sub + 2 * kBlock, *sub_row = sub + 3 * kBlock,
-             *sub_voff = sub + 4 * kBlock, *sub_coff = sub + 5 * kBlock;
+    float *ymax = reinterpret_cast<float *>(smem + Lo.ymax);
+    float *agg = reinterpret_cast<float *>(smem + Lo.agg);  // per match: max f, max |f|, max eps (probe, mid)
+    uint8_t *rowrel = reinterpret_cast<uint8_t *>(smem + Lo.rowrel);
+    uint8_t *slab_rel = reinterpret_cast<uint8_t *>(smem + Lo.slab_rel);
+    uint32_t *sub_pos = sub, *sub_y = sub + kBlock, *sub_mp = sub + 2 * kBlock, *sub_mm = sub + 3 * kBlock,
+             *sub_row = sub + 4 * kBlock, *sub_voff = sub + 5 * kBlock;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t d = A.d, R = A.R;
@@ -432,20 +580,29 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     const int gid = static_cast<int>(tid) / G, glane = static_cast<int>(tid) % G;
     const int ngroups = kBlock / G;
 
-    for (uint32_t i = tid; i < R * d; i += kBlock) Ys[i] = load1<BF16>(A.Y, i);
+    const uint32_t ystr = d + 4;  // padded row stride of the relation table in LDS
+    for (uint32_t i = tid; i < R * d; i += kBlock) Ys[(i / d) * ystr + i % d] = load1<BF16>(A.Y, i);
+    __syncthreads();
+    for (uint32_t r = tid; r < R; r += kBlock) {
+        float m = 0.0f;
+        for (uint32_t i = 0; i < d; ++i) m = fmaxf(m, fabsf(Ys[r * ystr + i]));
+        ymax[r] = m;
+    }
 
     for (;;) {
         __syncthreads();
         if (tid == 0) {
             uint32_t t;
             if (EXACT) {
-                // items enumerate (marked query, tile) pairs
-                for (;;) {
-                    uint32_t item = atomicAdd(&A.ctrl->exact_ctr, 1u);
-                    uint32_t qi = item / A.maxt, j = item % A.maxt;
-                    if (qi >= A.ctrl->exact_n) { t = kEmpty; break; }
-                    uint32_t q = A.exact_list[qi];
-                    if (j < A.plans[q].ntiles) { t = A.plans[q].tile_base + j; sh->q = q; sh->j = j; break; }
+                // only the tiles of queries the merge marked
+                t = kEmpty;
+                if (A.ctrl->exact_n > 0) {
+                    for (;;) {
+                        const uint32_t u = atomicAdd(&A.ctrl->exact_ctr, 1u);
+                        if (u >= A.ctrl->total_tiles) break;
+                        const uint32_t q = A.tile_q[u];
+                        if (A.plans[q].flags & kNeedExact) { t = u; sh->q = q; sh->j = u - A.plans[q].tile_base; break; }
+                    }
                 }
             } else {
                 t = atomicAdd(&A.ctrl->gather_ctr, 1u);
@@ -489,7 +646,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             sh->stage_n = 0;
             sh->list_n = 0;
             sh->truncated = 0;
-            sh->eps_max = 0.0f;
             sh->thr = cand_sentinel();
         }
         __syncthreads();
@@ -512,9 +668,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             uint32_t nb = next_pow2(P.probe_len) / 2;
             dsh = static_cast<int>(A.id_bits) - (31 - __clz(nb));
         }
-        const uint2 ts = A.tile_start[static_cast<uint64_t>(q) * A.maxt + j];
-        const uint2 te = (j + 1 < P.ntiles) ? A.tile_start[static_cast<uint64_t>(q) * A.maxt + j + 1]
-                                           : make_uint2(P.list_len, 0u);
+        const uint2 ts = A.tile_start[tile];
+        const uint2 te = (j + 1 < P.ntiles) ? A.tile_start[tile + 1] : make_uint2(P.list_len, 0u);
         uint64_t npaths = 0;
         float eps_local = 0.0f;
         __syncthreads();
@@ -523,61 +678,61 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         const uint32_t row_end = (te.y > 0) ? te.x + 1 : te.x;  // exclusive
         for (uint32_t rb = ts.x; rb < row_end; rb += kRowBatch) {
             const uint32_t nrows = min(static_cast<uint32_t>(kRowBatch), row_end - rb);
-            // row info: scan range clipped to the tile
-            uint32_t len = 0;
+            uint32_t len = 0, nv = 0;
             if (tid < nrows) {
                 uint32_t i = rb + tid;
                 uint32_t x = Lcol[P.list_beg + i];
+                uint32_t mask = Lmask[P.list_beg + i];
                 uint32_t beg = Lrp[x], end = Lrp[x + 1];
                 if (i == ts.x) beg += ts.y;
                 if (i == te.x) end = Lrp[x] + te.y;
                 len = end > beg ? end - beg : 0u;
+                nv = __popc(mask);
                 rows[tid].x = x;
-                rows[tid].mask = Lmask[P.list_beg + i];
+                rows[tid].mask = mask;
                 rows[tid].beg = beg;
                 rows[tid].len = len;
             }
-            // prefix over the batch (wave 0 holds all kRowBatch rows)
-            if (tid < kWave) {
-                uint32_t v = len;
-                uint32_t nv = (tid < nrows) ? __popc(Lmask[P.list_beg + rb + tid]) : 0u;
+            if (tid < kWave) {  // prefix over the batch (kRowBatch <= one wave)
+                uint32_t v = len, w = nv;
                 for (int off = 1; off < kWave; off <<= 1) {
                     uint32_t t1 = __shfl_up(v, off, kWave);
-                    uint32_t t2 = __shfl_up(nv, off, kWave);
-                    if (static_cast<int>(tid) >= off) { v += t1; nv += t2; }
+                    uint32_t t2 = __shfl_up(w, off, kWave);
+                    if (static_cast<int>(tid) >= off) { v += t1; w += t2; }
                 }
                 if (tid < nrows) {
                     rows[tid].pref = v - len;
-                    rows[tid].vbase = nv - ((tid < nrows) ? __popc(Lmask[P.list_beg + rb + tid]) : 0u);
+                    rows[tid].vbase = w - nv;
                 }
-                if (tid == nrows - 1) { sh->E = v; sh->rowvals = nv; }
+                if (tid == nrows - 1) { sh->E = v; sh->rowvals = w; }
             }
             __syncthreads();
-            // list-edge weights: one group per (row, relation) pair
-            const uint32_t nrv = sh->rowvals;
-            for (uint32_t base = 0; base < nrv; base += ngroups) {
-                uint32_t vi = base + gid;
-                bool act = vi < nrv;
-                uint32_t r = 0, k = 0;
-                if (act) {
-                    while (r + 1 < nrows && rows[r + 1].vbase <= vi) ++r;
-                    k = vi - rows[r].vbase;
+            // list-edge weights: one group per row, all of its relations
+            for (uint32_t r = gid; r < nrows; r += ngroups) {
+                float ex[8], z[8];
+                load_lane<BF16>(A.X, rows[r].x, d, glane * epl, epl, ex);
+                float sz = 0.0f;
+#pragma unroll
+                for (int l = 0; l < 8; ++l) {
+                    z[l] = (l < epl) ? ex[l] * anc_l[glane * epl + l] : 0.0f;
+                    sz += fabsf(z[l]);
                 }
-                float part = 0.0f, apart = 0.0f;
-                if (act) {
-                    uint32_t rel = nth_bit(rows[r].mask, k);
-                    float ex[8];
-                    load_lane<BF16>(A.X, rows[r].x, d, glane * epl, epl, ex);
-                    for (int l = 0; l < epl; ++l) {
-                        uint32_t e = glane * epl + l;
-                        float z = anc_l[e] * Ys[rel * d + e];
-                        part = __builtin_fmaf(z, ex[l], part);
-                        apart += fabsf(z * ex[l]);
-                    }
+                sz = group_sum(sz, G);
+                score_values(z, sz, rows[r].mask, z, sz, 0u, Ys, ymax, ystr, G, epl, glane, rowval + rows[r].vbase,
+                             roweps + rows[r].vbase, rowrel + rows[r].vbase);
+            }
+            __syncthreads();
+            if (tid < nrows) {
+                float fa = 0.0f, em = 0.0f;
+                const uint32_t vb = rows[tid].vbase, nvr = __popc(rows[tid].mask);
+                for (uint32_t k = 0; k < nvr; ++k) {
+                    fa = fmaxf(fa, fabsf(rowval[vb + k]));
+                    em = fmaxf(em, roweps[vb + k]);
                 }
-                float f, eps;
-                finish_edge(part, apart, G, epl, &f, &eps);
-                if (act && glane == 0) { rowval[vi] = f; roweps[vi] = eps; }
+                sort_desc(rowval + vb, rowrel + vb, nvr);
+                rows[tid].fmax = rowval[vb];
+                rows[tid].famax = fa;
+                rows[tid].emax = em;
             }
             __syncthreads();
             const uint32_t E = sh->E;
@@ -586,12 +741,12 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             for (uint32_t cb = 0; cb < E; cb += kChunk) {
                 if (tid == 0) sh->qcount = 0;
                 __syncthreads();
-                uint32_t ys[kEPT], ps[kEPT];
+                uint32_t ys[kEPT], ps[kEPT], mps[kEPT];
+                bool hits[kEPT];
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
                     uint32_t e = cb + k * kBlock + tid;
                     ps[k] = kEmpty;
-                    ys[k] = kEmpty;
                     if (e < E) {
                         uint32_t lo = 0, hi = nrows;  // last row with pref <= e
                         while (hi - lo > 1) {
@@ -602,56 +757,59 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < kEPT; ++k)
-                    if (ps[k] != kEmpty) ys[k] = Lcol[ps[k]];
+                for (int k = 0; k < kEPT; ++k) ys[k] = (ps[k] != kEmpty) ? Lcol[ps[k]] : kEmpty;
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
-                    bool hit = false;
-                    uint32_t mp = 0;
-                    if (ps[k] != kEmpty) {
-                        const uint32_t y = ys[k];
-                        if (!heavy) {
-                            uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
-                            for (;;) {
-                                uint32_t key = hkeys[slot];
-                                if (key == y) { hit = true; mp = hvals[slot]; break; }
-                                if (key == kEmpty) break;
-                                slot = (slot + 1) & smask;
-                            }
-                        } else {
-                            uint32_t bk = y >> dsh;
-                            uint32_t lo = dir[bk], hi = dir[bk + 1];
-                            for (uint32_t i = lo; i < hi; ++i) {
-                                uint32_t c = Pcol[P.probe_beg + i];
-                                if (c == y) { hit = true; mp = Pmask[P.probe_beg + i]; break; }
-                                if (c > y) break;
-                            }
+                    hits[k] = false;
+                    mps[k] = 0;
+                    if (ps[k] == kEmpty) continue;
+                    const uint32_t y = ys[k];
+                    if (!heavy) {
+                        uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
+                        for (;;) {
+                            uint32_t key = hkeys[slot];
+                            if (key == y) { hits[k] = true; mps[k] = hvals[slot]; break; }
+                            if (key == kEmpty) break;
+                            slot = (slot + 1) & smask;
+                        }
+                    } else {
+                        uint32_t bk = y >> dsh;
+                        uint32_t lo = dir[bk], hi = dir[bk + 1];
+                        for (uint32_t i = lo; i < hi; ++i) {
+                            uint32_t c = Pcol[P.probe_beg + i];
+                            if (c == y) { hits[k] = true; mps[k] = Pmask[P.probe_beg + i]; break; }
+                            if (c > y) break;
                         }
                     }
-                    uint64_t bal = __ballot(hit);
+                }
+                const int lane = tid & (kWave - 1);
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) {
+                    uint64_t bal = __ballot(hits[k]);
                     if (bal) {
-                        const int lane = tid & (kWave - 1);
                         uint32_t base = 0;
                         if (lane == 0) base = atomicAdd(&sh->qcount, static_cast<uint32_t>(__popcll(bal)));
                         base = __shfl(base, 0, kWave);
-                        if (hit) {
+                        if (hits[k]) {
                             uint64_t lt = lane ? (bal & (~0ull >> (kWave - lane))) : 0ull;
                             uint32_t slotq = base + __popcll(lt);
                             qpos[slotq] = ps[k];
-                            qmp[slotq] = mp;
+                            qmp[slotq] = mps[k];
+                            qy[slotq] = ys[k];
                         }
                     }
                 }
                 __syncthreads();
                 const uint32_t nmatch = sh->qcount;
 
-                // ---- sub-batches of at most kBlock matches
+                // ---- sub-batches of at most kBlock matches (value slab permitting)
                 for (uint32_t m0 = 0; m0 < nmatch;) {
-                    uint32_t mi = m0 + tid;
-                    uint32_t pos = 0, mp = 0, mm = 0, row = 0, nv = 0, nc = 0;
+                    const uint32_t mi = m0 + tid;
+                    uint32_t pos = 0, y = 0, mp = 0, mm = 0, row = 0, nv2 = 0;
                     if (mi < nmatch) {
                         pos = qpos[mi];
                         mp = qmp[mi];
+                        y = qy[mi];
                         mm = Lmask[pos];
                         uint32_t lo = 0, hi = nrows;  // row holding pos
                         while (hi - lo > 1) {
@@ -659,121 +817,235 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             if (rows[mid].beg <= pos) lo = mid; else hi = mid;
                         }
                         row = lo;
-                        uint32_t np = __popc(mp), nm = __popc(mm), nl = __popc(rows[row].mask);
-                        nv = np + nm;
-                        nc = np * nm * nl;
+                        nv2 = __popc(mp) + __popc(mm);
                     }
                     uint32_t vtot;
-                    uint32_t vincl = block_incl_scan<uint32_t>(nv, sh->red32, &vtot);
-                    bool take = (mi < nmatch) && vincl <= static_cast<uint32_t>(kSlab);
-                    uint32_t ncnt = block_sum<uint32_t>(take ? 1u : 0u, sh->red32);
-                    uint32_t ctot;
-                    uint32_t cincl = block_incl_scan<uint32_t>(take ? nc : 0u, sh->red32, &ctot);
+                    const uint32_t vincl = block_incl_scan<uint32_t>(nv2, sh->red32, &vtot);
+                    const bool take = (mi < nmatch) && vincl <= static_cast<uint32_t>(kSlab);
+                    const uint32_t ncnt = block_sum<uint32_t>(take ? 1u : 0u, sh->red32);
                     if (take) {
                         sub_pos[tid] = pos;
+                        sub_y[tid] = y;
                         sub_mp[tid] = mp;
                         sub_mm[tid] = mm;
                         sub_row[tid] = row;
-                        sub_voff[tid] = vincl - nv;
-                        sub_coff[tid] = cincl - nc;
+                        sub_voff[tid] = vincl - nv2;
                     }
                     __syncthreads();
-                    // scoring: one group of G lanes per match
-                    for (uint32_t s = gid; s < ncnt; s += ngroups) {
-                        const uint32_t spos = sub_pos[s], smp = sub_mp[s], smm = sub_mm[s];
-                        const RowInfo &ri = rows[sub_row[s]];
-                        const uint32_t y = Lcol[spos];
-                        float ey[8], ex[8];
-                        load_lane<BF16>(A.X, y, d, glane * epl, epl, ey);
-                        load_lane<BF16>(A.X, ri.x, d, glane * epl, epl, ex);
-                        uint32_t vo = sub_voff[s];
-                        uint32_t np = __popc(smp);
-                        for (uint32_t k = 0; k < np; ++k) {
-                            uint32_t rel = nth_bit(smp, k);
-                            float part = 0.0f, apart = 0.0f;
-                            for (int l = 0; l < epl; ++l) {
-                                uint32_t e = glane * epl + l;
-                                float z = anc_p[e] * Ys[rel * d + e];
-                                part = __builtin_fmaf(z, ey[l], part);
-                                apart += fabsf(z * ey[l]);
+                    // scoring on the matrix cores: a wave takes 16 matches at a time.
+                    // Lane (row m = lane & 15, k-quarter kq = lane >> 4) holds the
+                    // d/4 elements [kq*d/4, (kq+1)*d/4) of match m's vectors
+                    //   up = e_y * e_anchor_p   (the probe-side edge y -- anchor)
+                    //   um = e_y * e_x          (the middle edge y -- x)
+                    // and the same slice of relation row 16*rb + m; each MFMA step
+                    // multiplies a 16x4 slice of [up | um] by a 4x16 slice of Y^T,
+                    // so after d/4 steps D[m][r] = sum_k up[m][k] Y[r][k].  The
+                    // same products with |up| and |Y| give sum_k |up Y|, the scale
+                    // of the rounding error (the K-reduction inside the MFMA takes
+                    // at most d + 3 roundings per output).
+                    {
+                        const int lane = static_cast<int>(tid) & (kWave - 1), wv = static_cast<int>(tid) / kWave;
+                        const int mrow = lane & 15, kq = lane >> 4;
+                        const uint32_t KCH = d >> 2;
+                        const uint32_t nrb = (R + 15) / 16;
+                        const float gam = gamma_n(static_cast<int>(d) + 3) * 1.001f;
+                        for (uint32_t t0 = static_cast<uint32_t>(wv) * 16; t0 < ncnt; t0 += (kBlock / kWave) * 16) {
+                            const uint32_t mi = t0 + mrow;
+                            const bool mval = mi < ncnt;
+                            const uint32_t yrow = mval ? sub_y[mi] : 0u;
+                            const uint32_t xrow = mval ? rows[sub_row[mi]].x : 0u;
+                            f4 aP[2], aM[2], aPa[2], aMa[2];
+#pragma unroll
+                            for (int rb = 0; rb < 2; ++rb) {
+                                aP[rb] = f4{0.f, 0.f, 0.f, 0.f};
+                                aM[rb] = aP[rb];
+                                aPa[rb] = aP[rb];
+                                aMa[rb] = aP[rb];
                             }
-                            float f, eps;
-                            finish_edge(part, apart, G, epl, &f, &eps);
-                            if (glane == 0) { slab[vo + k] = f; slab_eps[vo + k] = eps; }
-                        }
-                        uint32_t nm = __popc(smm);
-                        for (uint32_t k = 0; k < nm; ++k) {
-                            uint32_t rel = nth_bit(smm, k);
-                            float part = 0.0f, apart = 0.0f;
-                            for (int l = 0; l < epl; ++l) {
-                                uint32_t e = glane * epl + l;
-                                float z = ey[l] * Ys[rel * d + e];
-                                part = __builtin_fmaf(z, ex[l], part);
-                                apart += fabsf(z * ex[l]);
+                            for (uint32_t kb = 0; kb < KCH; kb += 32) {
+                                const uint32_t off = static_cast<uint32_t>(kq) * KCH + kb;
+                                const uint32_t kn = KCH - kb < 32 ? KCH - kb : 32;
+                                float ey[32], ex[32];
+                                load_span32<BF16>(A.X, yrow, d, off, kn, mval, ey);
+                                load_span32<BF16>(A.X, xrow, d, off, kn, mval, ex);
+#pragma unroll
+                                for (uint32_t j = 0; j < 32; ++j) {
+                                    if (j < kn) {
+                                        const float up = ey[j] * anc_p[off + j];
+                                        const float um = ey[j] * ex[j];
+#pragma unroll
+                                        for (uint32_t rb = 0; rb < 2; ++rb) {
+                                            if (rb < nrb) {
+                                                const uint32_t rr = rb * 16 + static_cast<uint32_t>(mrow);
+                                                const float yv = rr < R ? Ys[rr * ystr + off + j] : 0.0f;
+                                                aP[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(up, yv, aP[rb], 0, 0, 0);
+                                                aM[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(um, yv, aM[rb], 0, 0, 0);
+                                                aPa[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(up), fabsf(yv), aPa[rb], 0, 0, 0);
+                                                aMa[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(um), fabsf(yv), aMa[rb], 0, 0, 0);
+                                            }
+                                        }
+                                    }
+                                }
                             }
-                            float f, eps;
-                            finish_edge(part, apart, G, epl, &f, &eps);
-                            if (glane == 0) { slab[vo + np + k] = f; slab_eps[vo + np + k] = eps; }
+                            // lane holds D[4*kq + i][mrow] of each relation block: match
+                            // t0 + 4*kq + i, relation 16*rb + mrow.  Keep the relations
+                            // in the match's masks; reduce per-match maxima over the 16
+                            // lanes of the row.
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const uint32_t m = t0 + 4 * static_cast<uint32_t>(kq) + static_cast<uint32_t>(i);
+                                const bool mv = m < ncnt;
+                                const uint32_t smp = mv ? sub_mp[m] : 0u, smm = mv ? sub_mm[m] : 0u;
+                                const uint32_t vo = mv ? sub_voff[m] : 0u, np = __popc(smp);
+                                float mxp = -__builtin_huge_valf(), axp = 0.0f, exp_ = 0.0f;
+                                float mxm = -__builtin_huge_valf(), axm = 0.0f, exm = 0.0f;
+#pragma unroll
+                                for (uint32_t rb = 0; rb < 2; ++rb) {
+                                    if (rb < nrb) {
+                                        const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
+                                        const uint32_t below = (1u << r) - 1u;
+                                        if (mv && r < R && ((smp >> r) & 1u)) {
+                                            const float f = centred_logsigmoid(aP[rb][i]);
+                                            const float e = gam * aPa[rb][i] + centred_logsigmoid_err(f);
+                                            const uint32_t idx = vo + __popc(smp & below);
+                                            slab[idx] = f;
+                                            slab_rel[idx] = static_cast<uint8_t>(r);
+                                            mxp = fmaxf(mxp, f);
+                                            axp = fmaxf(axp, fabsf(f));
+                                            exp_ = fmaxf(exp_, e);
+                                        }
+                                        if (mv && r < R && ((smm >> r) & 1u)) {
+                                            const float f = centred_logsigmoid(aM[rb][i]);
+                                            const float e = gam * aMa[rb][i] + centred_logsigmoid_err(f);
+                                            const uint32_t idx = vo + np + __popc(smm & below);
+                                            slab[idx] = f;
+                                            slab_rel[idx] = static_cast<uint8_t>(r);
+                                            mxm = fmaxf(mxm, f);
+                                            axm = fmaxf(axm, fabsf(f));
+                                            exm = fmaxf(exm, e);
+                                        }
+                                    }
+                                }
+                                mxp = row16_max(mxp);
+                                axp = row16_max(axp);
+                                exp_ = row16_max(exp_);
+                                mxm = row16_max(mxm);
+                                axm = row16_max(axm);
+                                exm = row16_max(exm);
+                                if (mv && mrow == 0) {
+                                    agg[m] = mxp;
+                                    agg[kBlock + m] = axp;
+                                    agg[2 * kBlock + m] = exp_;
+                                    agg[3 * kBlock + m] = mxm;
+                                    agg[4 * kBlock + m] = axm;
+                                    agg[5 * kBlock + m] = exm;
+                                }
+                            }
                         }
                     }
                     __syncthreads();
-                    // candidates: one per thread per round
-                    for (uint32_t c0 = 0; c0 < ctot; c0 += kBlock) {
-                        const uint32_t c = c0 + tid;
-                        bool pass = false;
-                        Cand cd;
-                        if (c < ctot) {
-                            uint32_t lo = 0, hi = ncnt;  // match holding candidate c
-                            while (hi - lo > 1) {
-                                uint32_t mid = (lo + hi) >> 1;
-                                if (sub_coff[mid] <= c) lo = mid; else hi = mid;
+
+                    // ---- path enumeration: thread tid owns match tid of the sub-batch.
+                    // Each edge's relation values are sorted descending, so combinations
+                    // are visited best-first along every axis and a loop stops at the
+                    // first bound below the kept K-th score (the bound uses the score's
+                    // own association, so FP32 rounding keeps it >= every score it
+                    // covers).  Skipped paths are counted, not listed.
+                    uint32_t np = 0, nm = 0, nl = 0, vo = 0, sy = 0, sx = 0, lb = 0;
+                    uint32_t ip = 0, im = 0, il = 0;
+                    bool done = !take, sorted = false;
+                    float maxp = 0.0f, maxm = 0.0f;
+                    if (take) {
+                        const RowInfo &ri = rows[sub_row[tid]];
+                        const uint32_t smp = sub_mp[tid], smm = sub_mm[tid];
+                        sy = sub_y[tid];
+                        sx = ri.x;
+                        lb = ri.vbase;
+                        np = __popc(smp);
+                        nm = __popc(smm);
+                        nl = __popc(ri.mask);
+                        vo = sub_voff[tid];
+                        const float ap = agg[kBlock + tid], ep = agg[2 * kBlock + tid];
+                        const float am = agg[4 * kBlock + tid], em = agg[5 * kBlock + tid];
+                        eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (ap + am + ri.famax));
+                        npaths += static_cast<uint64_t>(np) * nm * nl;
+                        maxp = agg[tid];
+                        maxm = agg[3 * kBlock + tid];
+                    }
+                    int active = __syncthreads_count(!done);
+                    while (active > 0) {
+                        // the free stage slots are shared by the threads still
+                        // enumerating (at least one each), so a lone match with
+                        // many relation combinations fills the stage in one round
+                        if (sh->stage_n + static_cast<uint32_t>(active) > static_cast<uint32_t>(kStage))
+                            merge_stage<KC>(list, stage, sh);
+                        const uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
+                        const Cand thr = sh->thr;
+                        const float tS = EXACT ? thr_exact : thr.s;
+                        uint32_t emitted = 0;
+                        bool dropped = false;
+                        if (!done && !sorted) {
+                            // sort only matches whose best path can still be kept
+                            if (combine3(fwd, maxp, maxm, rowval[lb]) < tS) {
+                                dropped = true;
+                                done = true;
+                            } else {
+                                sort_desc(slab + vo, slab_rel + vo, np);
+                                sort_desc(slab + vo + np, slab_rel + vo + np, nm);
+                                sorted = true;
                             }
-                            const uint32_t s = lo;
-                            const uint32_t local = c - sub_coff[s];
-                            const uint32_t smp = sub_mp[s], smm = sub_mm[s];
-                            const RowInfo &ri = rows[sub_row[s]];
-                            const uint32_t np = __popc(smp), nm = __popc(smm), nl = __popc(ri.mask);
-                            const uint32_t il = local % nl, im = (local / nl) % nm, ip = local / (nl * nm);
-                            const uint32_t vo = sub_voff[s];
-                            const float fp = slab[vo + ip], fm = slab[vo + np + im];
-                            const float fl = rowval[ri.vbase + il];
-                            const float ep = slab_eps[vo + ip], em = slab_eps[vo + np + im];
-                            const float el = roweps[ri.vbase + il];
-                            const float S = fwd ? (fl + fm) + fp : (fp + fm) + fl;
-                            const float eS = ep + em + el + 2.01f * kUnit * (fabsf(fp) + fabsf(fm) + fabsf(fl));
-                            const uint32_t rp_ = nth_bit(smp, ip), rm_ = nth_bit(smm, im), rl_ = nth_bit(ri.mask, il);
-                            const uint32_t y = Lcol[sub_pos[s]];
-                            cd.a = fwd ? ri.x : y;
-                            cd.b = fwd ? y : ri.x;
+                        }
+                        while (!done && emitted < quota) {
+                            if (ip >= np) { done = true; break; }
+                            const float fp = slab[vo + ip];
+                            if (im == 0 && il == 0 && combine3(fwd, fp, slab[vo + np], rowval[lb]) < tS) {
+                                dropped = true;   // this and every later probe value
+                                done = true;
+                                break;
+                            }
+                            if (im >= nm) { ++ip; im = 0; il = 0; continue; }
+                            const float fm = slab[vo + np + im];
+                            if (il == 0 && combine3(fwd, fp, fm, rowval[lb]) < tS) {
+                                dropped = true;   // this and every later mid value
+                                ++ip; im = 0;
+                                continue;
+                            }
+                            if (il >= nl) { ++im; il = 0; continue; }
+                            const float fl = rowval[lb + il];
+                            const float S = combine3(fwd, fp, fm, fl);
+                            if (S < tS) {
+                                dropped = true;   // this and every later list value
+                                ++im; il = 0;
+                                continue;
+                            }
+                            const uint32_t rp_ = slab_rel[vo + ip], rm_ = slab_rel[vo + np + im],
+                                           rl_ = rowrel[lb + il];
+                            ++il;
+                            Cand cd;
+                            cd.a = fwd ? sx : sy;
+                            cd.b = fwd ? sy : sx;
                             const uint32_t r1 = fwd ? rl_ : rp_, r3 = fwd ? rp_ : rl_;
                             cd.rel = (r1 << 16) | (rm_ << 8) | r3;
                             cd.s = S;
                             cd.s_lo = 0.0f;
-                            cd.eps = eS;
-                            eps_local = fmaxf(eps_local, eS);
-                            npaths += 1;
-                            bool consider = true;
+                            cd.eps = 0.0f;
                             if (EXACT) {
-                                consider = S >= thr_exact;
-                                if (consider) {
-                                    float e2;
-                                    ff sc = path_score_ff<BF16>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
-                                    cd.s = sc.hi;
-                                    cd.s_lo = sc.lo;
-                                    cd.eps = e2;
-                                }
+                                float e2;
+                                ff sc = path_score_ff<BF16>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
+                                cd.s = sc.hi;
+                                cd.s_lo = sc.lo;
+                                cd.eps = e2;
                             }
-                            if (consider) {
-                                if (cand_better(cd, sh->thr)) pass = true;
-                                else sh->truncated = 1;
+                            if (cand_better(cd, thr)) {
+                                uint32_t slot = atomicAdd(&sh->stage_n, 1u);
+                                stage[slot] = cd;
+                                ++emitted;
+                            } else {
+                                dropped = true;
                             }
                         }
-                        if (pass) {
-                            uint32_t slot = atomicAdd(&sh->stage_n, 1u);
-                            stage[slot] = cd;
-                        }
-                        __syncthreads();
-                        if (sh->stage_n > static_cast<uint32_t>(kStage - kBlock)) merge_stage<KC>(list, stage, sh);
+                        if (dropped) sh->truncated = 1;
+                        active = __syncthreads_count(!done);
                     }
                     m0 += ncnt;
                     __syncthreads();
@@ -799,7 +1071,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
     }
 }
-
 // ---------------------------------------------------------------------------
 // merge
 // ---------------------------------------------------------------------------
@@ -839,16 +1110,44 @@ __device__ inline void write_result(mhr_path *row, const Cand *c, uint32_t nc, u
     write_sentinels(row, kk, kmax);
 }
 
+// Streams the query's tile lists through LDS (kMergeSlots candidates at a
+// time) and leaves the best KC by the total order, sorted, in c[0..KC).
+// Also returns, through shared memory, the best key that fell off the
+// running list (its score, or -inf when nothing real was dropped).
+template <int KC>
+__device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, float *s_drop) {
+    constexpr uint32_t per = (kMergeSlots - KC) / KC;  // tile lists per step
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) c[i] = cand_sentinel();
+    if (threadIdx.x == 0) *s_drop = -__builtin_huge_valf();
+    __syncthreads();
+    for (uint32_t j0 = 0; j0 < P.ntiles; j0 += per) {
+        const uint32_t nt = min(per, P.ntiles - j0);
+        for (uint32_t i = threadIdx.x; i < kMergeSlots - KC; i += blockDim.x) {
+            const uint32_t jt = i / KC, k = i % KC;
+            Cand x = cand_sentinel();
+            if (jt < nt) {
+                const uint32_t tile = P.tile_base + j0 + jt;
+                if (k < A.hdr[tile].count) x = A.cands[static_cast<uint64_t>(tile) * KC + k];
+            }
+            c[KC + i] = x;
+        }
+        __syncthreads();
+        block_sort_cands(c, static_cast<int>(kMergeSlots));
+        if (threadIdx.x == 0 && c[KC].a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, c[KC].s);
+        __syncthreads();
+    }
+}
+
 template <bool BF16, int KC>
 __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, uint32_t *out_count,
                                                        uint64_t *out_total, uint32_t *out_status, uint32_t kmax) {
     extern __shared__ __align__(16) unsigned char smem[];
     Cand *c = reinterpret_cast<Cand *>(smem);
     __shared__ uint32_t s_n, s_over, s_nb;
-    __shared__ float s_eps;
+    __shared__ float s_eps, s_drop;
     __shared__ uint64_t s_tot;
     const uint32_t q = blockIdx.x;
-    QueryPlan P = A.plans[q];
+    const QueryPlan P = A.plans[q];
     mhr_path *row = out + static_cast<uint64_t>(q) * kmax;
     if (P.status != 0 || P.ntiles == 0) {
         if (threadIdx.x == 0) {
@@ -873,19 +1172,9 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
         s_eps = eps;
         s_tot = tot;
     }
-    __syncthreads();
-    // compact the tile lists into LDS
-    const uint32_t ntot = P.ntiles * KC;
-    for (uint32_t i = threadIdx.x; i < ntot; i += blockDim.x) {
-        uint32_t jt = i / KC, k = i % KC;
-        const TileHeader &h = A.hdr[P.tile_base + jt];
-        c[i] = (k < h.count) ? A.cands[static_cast<uint64_t>(P.tile_base + jt) * KC + k] : cand_sentinel();
-    }
-    const uint32_t n2 = next_pow2(ntot);
-    for (uint32_t i = ntot + threadIdx.x; i < n2; i += blockDim.x) c[i] = cand_sentinel();
-    __syncthreads();
-    block_sort_cands(c, static_cast<int>(n2));
+    collect_top<KC>(A, P, c, &s_drop);
     const uint32_t cnt = s_n;
+    const uint32_t kept = min(cnt, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, cnt);
     if (kk == 0) {
         if (threadIdx.x == 0) {
@@ -901,13 +1190,13 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
     // band threshold, rounded down generously
     const float thr = (theta - 2.0f * eps) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
     if (threadIdx.x == 0) {
-        uint32_t over = 0;
-        for (uint32_t j = 0; j < P.ntiles; ++j) {
+        uint32_t over = s_drop >= thr ? 1u : 0u;
+        for (uint32_t j = 0; j < P.ntiles && !over; ++j) {
             const TileHeader &h = A.hdr[P.tile_base + j];
             if (h.truncated && h.cutoff >= thr) over = 1;
         }
         uint32_t nb = 0;
-        while (nb < cnt && c[nb].s >= thr) ++nb;
+        while (nb < kept && c[nb].s >= thr) ++nb;
         s_over = over;
         s_nb = nb;
     }
@@ -917,8 +1206,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
             A.plans[q].flags = kNeedExact;
             A.plans[q].thr = thr;
             A.plans[q].total = s_tot;
-            uint32_t slot = atomicAdd(&A.ctrl->exact_n, 1u);
-            A.exact_list[slot] = q;
+            atomicAdd(&A.ctrl->exact_n, 1u);
         }
         return;
     }
@@ -954,6 +1242,7 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
     extern __shared__ __align__(16) unsigned char smem[];
     Cand *c = reinterpret_cast<Cand *>(smem);
     __shared__ uint32_t s_n;
+    __shared__ float s_drop;
     const uint32_t q = blockIdx.x;
     const QueryPlan P = A.plans[q];
     if (P.status != 0 || !(P.flags & kNeedExact)) return;
@@ -963,18 +1252,10 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
         for (uint32_t j = 0; j < P.ntiles; ++j) n += A.hdr[P.tile_base + j].count;
         s_n = n;
     }
-    const uint32_t ntot = P.ntiles * KC;
-    for (uint32_t i = threadIdx.x; i < ntot; i += blockDim.x) {
-        uint32_t jt = i / KC, k = i % KC;
-        const TileHeader &h = A.hdr[P.tile_base + jt];
-        c[i] = (k < h.count) ? A.cands[static_cast<uint64_t>(P.tile_base + jt) * KC + k] : cand_sentinel();
-    }
-    const uint32_t n2 = next_pow2(ntot);
-    for (uint32_t i = ntot + threadIdx.x; i < n2; i += blockDim.x) c[i] = cand_sentinel();
-    __syncthreads();
-    block_sort_cands(c, static_cast<int>(n2));
-    const uint32_t kk = min(P.k, s_n);
-    write_result(row, c, s_n, kk, kmax);
+    collect_top<KC>(A, P, c, &s_drop);
+    const uint32_t kept = min(s_n, static_cast<uint32_t>(KC));
+    const uint32_t kk = min(P.k, kept);
+    write_result(row, c, kept, kk, kmax);
     if (threadIdx.x == 0) {
         out_count[q] = kk;
         if (out_total) out_total[q] = P.total;
@@ -1036,17 +1317,17 @@ uint32_t kc_for(uint32_t kmax) {
 }
 
 WsLayout ws_layout(uint32_t nq, uint32_t kc) {
-    const uint32_t maxt = max_tiles_for(kc);
+    const uint32_t tcap = tile_capacity(nq);
     WsLayout W{};
     size_t o = 0;
     auto al = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
     W.ctrl = o; o = al(o + sizeof(Control));
     W.plans = o; o = al(o + size_t(nq) * sizeof(QueryPlan));
-    W.tile_start = o; o = al(o + size_t(nq) * maxt * sizeof(uint2));
-    W.tile_q = o; o = al(o + size_t(nq) * maxt * sizeof(uint32_t));
+    W.tile_start = o; o = al(o + size_t(tcap) * sizeof(uint2));
+    W.tile_q = o; o = al(o + size_t(tcap) * sizeof(uint32_t));
     W.exact_list = o; o = al(o + size_t(nq) * sizeof(uint32_t));
-    W.hdr = o; o = al(o + size_t(nq) * maxt * sizeof(TileHeader));
-    W.cands = o; o = al(o + size_t(nq) * maxt * kc * sizeof(Cand));
+    W.hdr = o; o = al(o + size_t(tcap) * sizeof(TileHeader));
+    W.cands = o; o = al(o + size_t(tcap) * kc * sizeof(Cand));
     W.total = o;
     return W;
 }
@@ -1071,30 +1352,42 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     A.exact_list = reinterpret_cast<uint32_t *>(base + W.exact_list);
     A.hdr = reinterpret_cast<TileHeader *>(base + W.hdr);
     A.cands = reinterpret_cast<Cand *>(base + W.cands);
-    A.maxt = max_tiles_for(KC);
+    A.tcap = tile_capacity(nq);
     A.nq = nq;
     A.kc = KC;
     A.hash_log2 = (o && o->hash_log2) ? o->hash_log2 : kDefaultHashLog2;
     const uint32_t tile_edges = (o && o->tile_edges) ? o->tile_edges : kDefaultTileEdges;
+    A.tile_edges = tile_edges;
     if (g_num_cus == 0) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) g_num_cus = prop.multiProcessorCount;
         if (g_num_cus <= 0) g_num_cus = 256;
     }
     const GatherLayout GL = gather_layout(A.hash_log2, A.R, A.d, KC);
-    const uint32_t grid = (o && o->grid_blocks) ? o->grid_blocks : static_cast<uint32_t>(g_num_cus) * 2;
+    uint32_t grid = (o && o->grid_blocks) ? o->grid_blocks : 0u;
+    if (grid == 0) {
+        // persistent: as many workgroups as can be resident at once
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(
+                                                             gather_kernel<BF16, false, KC>),
+                                                         kBlock, GL.total) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        grid = static_cast<uint32_t>(g_num_cus * per_cu);
+    }
     const uint32_t kdef = o ? o->k : 0u;
 
     MHR_HIP_TRY(rec(ev ? ev->begin : nullptr));
-    hipLaunchKernelGGL(plan_kernel, dim3(nq), dim3(kBlock), 0, st, A, src, dst, k, kdef, kmax, tile_edges);
+    hipLaunchKernelGGL(plan_kernel, dim3(nq), dim3(kBlock), 0, st, A, src, dst, k, kdef, kmax);
     hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(tile_starts_kernel, dim3(nq), dim3(kBlock), 0, st, A);
     auto gk = gather_kernel<BF16, false, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(gk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(GL.total)));
     MHR_HIP_TRY(rec(ev ? ev->gather_begin : nullptr));
     hipLaunchKernelGGL(gk, dim3(grid), dim3(kBlock), GL.total, st, A);
     MHR_HIP_TRY(rec(ev ? ev->gather_end : nullptr));
-    const size_t msmem = size_t(next_pow2(max_tiles_for(KC) * KC)) * sizeof(Cand);
+    const size_t msmem = size_t(kMergeSlots) * sizeof(Cand);
     auto mk = merge_kernel<BF16, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(mk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem)));
