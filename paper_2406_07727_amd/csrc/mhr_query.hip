@@ -44,6 +44,7 @@ constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
 constexpr int kSlab = 1024;               // scored edge values per sub-batch
 constexpr int kStage = 768;               // staged candidates before a merge
+constexpr uint32_t kMaxQuota = 8;         // candidates a thread stages per round
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kDefaultTileEdges = 32768;
 constexpr uint32_t kDefaultHashLog2 = 12;
@@ -854,14 +855,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             const bool mval = mi < ncnt;
                             const uint32_t yrow = mval ? sub_y[mi] : 0u;
                             const uint32_t xrow = mval ? rows[sub_row[mi]].x : 0u;
-                            f4 aP[2], aM[2], aPa[2], aMa[2];
+                            f4 aP[2], aM[2];
 #pragma unroll
                             for (int rb = 0; rb < 2; ++rb) {
                                 aP[rb] = f4{0.f, 0.f, 0.f, 0.f};
                                 aM[rb] = aP[rb];
-                                aPa[rb] = aP[rb];
-                                aMa[rb] = aP[rb];
                             }
+                            float sup = 0.0f, sum_ = 0.0f;  // sum_k |up|, sum_k |um| over this lane's slice
                             for (uint32_t kb = 0; kb < KCH; kb += 32) {
                                 const uint32_t off = static_cast<uint32_t>(kq) * KCH + kb;
                                 const uint32_t kn = KCH - kb < 32 ? KCH - kb : 32;
@@ -873,6 +873,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     if (j < kn) {
                                         const float up = ey[j] * anc_p[off + j];
                                         const float um = ey[j] * ex[j];
+                                        sup += fabsf(up);
+                                        sum_ += fabsf(um);
 #pragma unroll
                                         for (uint32_t rb = 0; rb < 2; ++rb) {
                                             if (rb < nrb) {
@@ -880,49 +882,92 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                                 const float yv = rr < R ? Ys[rr * ystr + off + j] : 0.0f;
                                                 aP[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(up, yv, aP[rb], 0, 0, 0);
                                                 aM[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(um, yv, aM[rb], 0, 0, 0);
-                                                aPa[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(up), fabsf(yv), aPa[rb], 0, 0, 0);
-                                                aMa[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fabsf(um), fabsf(yv), aMa[rb], 0, 0, 0);
                                             }
                                         }
                                     }
                                 }
                             }
+                            // sum over the four k-quarters of each match (lanes m, m+16, m+32, m+48)
+                            sup += __shfl_xor(sup, 16, kWave);
+                            sup += __shfl_xor(sup, 32, kWave);
+                            sum_ += __shfl_xor(sum_, 16, kWave);
+                            sum_ += __shfl_xor(sum_, 32, kWave);
+                            // does any match of this wave tile carry several relations of a kind?
+                            const bool multi = __any(mval && (__popc(sub_mp[mi]) > 1 || __popc(sub_mm[mi]) > 1));
                             // lane holds D[4*kq + i][mrow] of each relation block: match
-                            // t0 + 4*kq + i, relation 16*rb + mrow.  Keep the relations
-                            // in the match's masks; reduce per-match maxima over the 16
-                            // lanes of the row.
+                            // t0 + 4*kq + i, relation 16*rb + mrow.  Keep the relations in
+                            // the match's masks, each written at its rank (descending value,
+                            // then relation id) among the match's values of its kind, so the
+                            // enumeration reads them best-first; reduce per-match maxima over
+                            // the 16 lanes of the row.
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const uint32_t m = t0 + 4 * static_cast<uint32_t>(kq) + static_cast<uint32_t>(i);
                                 const bool mv = m < ncnt;
                                 const uint32_t smp = mv ? sub_mp[m] : 0u, smm = mv ? sub_mm[m] : 0u;
                                 const uint32_t vo = mv ? sub_voff[m] : 0u, np = __popc(smp);
+                                // |up| and |um| sums of match 4*kq + i live in lane 4*kq + i
+                                const float su_p = __shfl(sup, 4 * kq + i, kWave);
+                                const float su_m = __shfl(sum_, 4 * kq + i, kWave);
+                                float fP[2], fM[2], eP[2], eM[2];
+#pragma unroll
+                                for (uint32_t rb = 0; rb < 2; ++rb) {
+                                    fP[rb] = -__builtin_huge_valf();
+                                    fM[rb] = -__builtin_huge_valf();
+                                    eP[rb] = 0.0f;
+                                    eM[rb] = 0.0f;
+                                    const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
+                                    if (rb < nrb && mv && r < R) {
+                                        if ((smp >> r) & 1u) {
+                                            fP[rb] = centred_logsigmoid(aP[rb][i]);
+                                            eP[rb] = gam * ymax[r] * su_p + centred_logsigmoid_err(fP[rb]);
+                                        }
+                                        if ((smm >> r) & 1u) {
+                                            fM[rb] = centred_logsigmoid(aM[rb][i]);
+                                            eM[rb] = gam * ymax[r] * su_m + centred_logsigmoid_err(fM[rb]);
+                                        }
+                                    }
+                                }
+                                uint32_t rkP[2] = {0u, 0u}, rkM[2] = {0u, 0u};
+                                if (!multi) {   // one relation per kind: rank = 0
+                                } else {
+                                const int rowbase = lane & ~15;
+#pragma unroll
+                                for (uint32_t rb2 = 0; rb2 < 2; ++rb2) {
+                                    if (rb2 < nrb) {
+                                        for (int sl = 0; sl < 16; ++sl) {
+                                            const float gp = __shfl(fP[rb2], rowbase | sl, kWave);
+                                            const float gm = __shfl(fM[rb2], rowbase | sl, kWave);
+                                            const uint32_t rs = rb2 * 16 + static_cast<uint32_t>(sl);
+#pragma unroll
+                                            for (uint32_t rb = 0; rb < 2; ++rb) {
+                                                const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
+                                                rkP[rb] += (gp > fP[rb] || (gp == fP[rb] && rs < r)) ? 1u : 0u;
+                                                rkM[rb] += (gm > fM[rb] || (gm == fM[rb] && rs < r)) ? 1u : 0u;
+                                            }
+                                        }
+                                    }
+                                }
+                                }
                                 float mxp = -__builtin_huge_valf(), axp = 0.0f, exp_ = 0.0f;
                                 float mxm = -__builtin_huge_valf(), axm = 0.0f, exm = 0.0f;
 #pragma unroll
                                 for (uint32_t rb = 0; rb < 2; ++rb) {
-                                    if (rb < nrb) {
-                                        const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
-                                        const uint32_t below = (1u << r) - 1u;
-                                        if (mv && r < R && ((smp >> r) & 1u)) {
-                                            const float f = centred_logsigmoid(aP[rb][i]);
-                                            const float e = gam * aPa[rb][i] + centred_logsigmoid_err(f);
-                                            const uint32_t idx = vo + __popc(smp & below);
-                                            slab[idx] = f;
-                                            slab_rel[idx] = static_cast<uint8_t>(r);
-                                            mxp = fmaxf(mxp, f);
-                                            axp = fmaxf(axp, fabsf(f));
-                                            exp_ = fmaxf(exp_, e);
+                                    const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
+                                    if (rb < nrb && mv && r < R) {
+                                        if ((smp >> r) & 1u) {
+                                            slab[vo + rkP[rb]] = fP[rb];
+                                            slab_rel[vo + rkP[rb]] = static_cast<uint8_t>(r);
+                                            mxp = fmaxf(mxp, fP[rb]);
+                                            axp = fmaxf(axp, fabsf(fP[rb]));
+                                            exp_ = fmaxf(exp_, eP[rb]);
                                         }
-                                        if (mv && r < R && ((smm >> r) & 1u)) {
-                                            const float f = centred_logsigmoid(aM[rb][i]);
-                                            const float e = gam * aMa[rb][i] + centred_logsigmoid_err(f);
-                                            const uint32_t idx = vo + np + __popc(smm & below);
-                                            slab[idx] = f;
-                                            slab_rel[idx] = static_cast<uint8_t>(r);
-                                            mxm = fmaxf(mxm, f);
-                                            axm = fmaxf(axm, fabsf(f));
-                                            exm = fmaxf(exm, e);
+                                        if ((smm >> r) & 1u) {
+                                            slab[vo + np + rkM[rb]] = fM[rb];
+                                            slab_rel[vo + np + rkM[rb]] = static_cast<uint8_t>(r);
+                                            mxm = fmaxf(mxm, fM[rb]);
+                                            axm = fmaxf(axm, fabsf(fM[rb]));
+                                            exm = fmaxf(exm, eM[rb]);
                                         }
                                     }
                                 }
@@ -953,8 +998,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     // covers).  Skipped paths are counted, not listed.
                     uint32_t np = 0, nm = 0, nl = 0, vo = 0, sy = 0, sx = 0, lb = 0;
                     uint32_t ip = 0, im = 0, il = 0;
-                    bool done = !take, sorted = false;
-                    float maxp = 0.0f, maxm = 0.0f;
+                    bool done = !take;
                     if (take) {
                         const RowInfo &ri = rows[sub_row[tid]];
                         const uint32_t smp = sub_mp[tid], smm = sub_mm[tid];
@@ -969,8 +1013,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         const float am = agg[4 * kBlock + tid], em = agg[5 * kBlock + tid];
                         eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (ap + am + ri.famax));
                         npaths += static_cast<uint64_t>(np) * nm * nl;
-                        maxp = agg[tid];
-                        maxm = agg[3 * kBlock + tid];
                     }
                     int active = __syncthreads_count(!done);
                     while (active > 0) {
@@ -979,33 +1021,25 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         // many relation combinations fills the stage in one round
                         if (sh->stage_n + static_cast<uint32_t>(active) > static_cast<uint32_t>(kStage))
                             merge_stage<KC>(list, stage, sh);
-                        const uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
+                        uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
+                        if (quota > kMaxQuota) quota = kMaxQuota;
                         const Cand thr = sh->thr;
                         const float tS = EXACT ? thr_exact : thr.s;
                         uint32_t emitted = 0;
                         bool dropped = false;
-                        if (!done && !sorted) {
-                            // sort only matches whose best path can still be kept
-                            if (combine3(fwd, maxp, maxm, rowval[lb]) < tS) {
-                                dropped = true;
-                                done = true;
-                            } else {
-                                sort_desc(slab + vo, slab_rel + vo, np);
-                                sort_desc(slab + vo + np, slab_rel + vo + np, nm);
-                                sorted = true;
-                            }
-                        }
+                        const float fl0 = (!done) ? rowval[lb] : 0.0f;
+                        const float fm0 = (!done) ? slab[vo + np] : 0.0f;
                         while (!done && emitted < quota) {
                             if (ip >= np) { done = true; break; }
                             const float fp = slab[vo + ip];
-                            if (im == 0 && il == 0 && combine3(fwd, fp, slab[vo + np], rowval[lb]) < tS) {
+                            if (im == 0 && il == 0 && combine3(fwd, fp, fm0, fl0) < tS) {
                                 dropped = true;   // this and every later probe value
                                 done = true;
                                 break;
                             }
                             if (im >= nm) { ++ip; im = 0; il = 0; continue; }
                             const float fm = slab[vo + np + im];
-                            if (il == 0 && combine3(fwd, fp, fm, rowval[lb]) < tS) {
+                            if (il == 0 && combine3(fwd, fp, fm, fl0) < tS) {
                                 dropped = true;   // this and every later mid value
                                 ++ip; im = 0;
                                 continue;
