@@ -123,6 +123,19 @@ def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample):
                       f"OpenMP over queries; {dt:.1f} s; {int(tot.sum())} paths; queries/s {nsample / dt:.2f}"}
 
 
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size (torch's copy kernel, nbytes read and
+    nbytes written per launch): the reference that scales the FETCH_SIZE and
+    WRITE_SIZE counters of a profiled run into bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,11 +145,17 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bytes", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(queries would shard by query across GPUs; see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     import kgsynth

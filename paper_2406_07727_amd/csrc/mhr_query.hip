@@ -360,7 +360,7 @@ struct GatherLayout {
         ymax, rowrel, slab_rel, agg, shared, total;
 };
 
-constexpr int kSubFields = 6;  // pos, y, mp, mm, row, voff
+constexpr int kSubFields = 7;  // pos, y, mp, mm, row, voff, first item
 
 __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32_t R, uint32_t d, uint32_t kc) {
     GatherLayout L{};
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     uint8_t *rowrel = reinterpret_cast<uint8_t *>(smem + Lo.rowrel);
     uint8_t *slab_rel = reinterpret_cast<uint8_t *>(smem + Lo.slab_rel);
     uint32_t *sub_pos = sub, *sub_y = sub + kBlock, *sub_mp = sub + 2 * kBlock, *sub_mm = sub + 3 * kBlock,
-             *sub_row = sub + 4 * kBlock, *sub_voff = sub + 5 * kBlock;
+             *sub_row = sub + 4 * kBlock, *sub_voff = sub + 5 * kBlock, *sub_item = sub + 6 * kBlock;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t d = A.d, R = A.R;
@@ -892,14 +892,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             sup += __shfl_xor(sup, 32, kWave);
                             sum_ += __shfl_xor(sum_, 16, kWave);
                             sum_ += __shfl_xor(sum_, 32, kWave);
-                            // does any match of this wave tile carry several relations of a kind?
-                            const bool multi = __any(mval && (__popc(sub_mp[mi]) > 1 || __popc(sub_mm[mi]) > 1));
                             // lane holds D[4*kq + i][mrow] of each relation block: match
                             // t0 + 4*kq + i, relation 16*rb + mrow.  Keep the relations in
-                            // the match's masks, each written at its rank (descending value,
-                            // then relation id) among the match's values of its kind, so the
-                            // enumeration reads them best-first; reduce per-match maxima over
-                            // the 16 lanes of the row.
+                            // the match's masks (in relation order) and reduce per-match
+                            // maxima over the 16 lanes of the row.
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const uint32_t m = t0 + 4 * static_cast<uint32_t>(kq) + static_cast<uint32_t>(i);
@@ -928,43 +924,25 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                         }
                                     }
                                 }
-                                uint32_t rkP[2] = {0u, 0u}, rkM[2] = {0u, 0u};
-                                if (!multi) {   // one relation per kind: rank = 0
-                                } else {
-                                const int rowbase = lane & ~15;
-#pragma unroll
-                                for (uint32_t rb2 = 0; rb2 < 2; ++rb2) {
-                                    if (rb2 < nrb) {
-                                        for (int sl = 0; sl < 16; ++sl) {
-                                            const float gp = __shfl(fP[rb2], rowbase | sl, kWave);
-                                            const float gm = __shfl(fM[rb2], rowbase | sl, kWave);
-                                            const uint32_t rs = rb2 * 16 + static_cast<uint32_t>(sl);
-#pragma unroll
-                                            for (uint32_t rb = 0; rb < 2; ++rb) {
-                                                const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
-                                                rkP[rb] += (gp > fP[rb] || (gp == fP[rb] && rs < r)) ? 1u : 0u;
-                                                rkM[rb] += (gm > fM[rb] || (gm == fM[rb] && rs < r)) ? 1u : 0u;
-                                            }
-                                        }
-                                    }
-                                }
-                                }
                                 float mxp = -__builtin_huge_valf(), axp = 0.0f, exp_ = 0.0f;
                                 float mxm = -__builtin_huge_valf(), axm = 0.0f, exm = 0.0f;
 #pragma unroll
                                 for (uint32_t rb = 0; rb < 2; ++rb) {
                                     const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
                                     if (rb < nrb && mv && r < R) {
+                                        const uint32_t below = (1u << r) - 1u;   // relations before r
                                         if ((smp >> r) & 1u) {
-                                            slab[vo + rkP[rb]] = fP[rb];
-                                            slab_rel[vo + rkP[rb]] = static_cast<uint8_t>(r);
+                                            const uint32_t ix = vo + __popc(smp & below);
+                                            slab[ix] = fP[rb];
+                                            slab_rel[ix] = static_cast<uint8_t>(r);
                                             mxp = fmaxf(mxp, fP[rb]);
                                             axp = fmaxf(axp, fabsf(fP[rb]));
                                             exp_ = fmaxf(exp_, eP[rb]);
                                         }
                                         if ((smm >> r) & 1u) {
-                                            slab[vo + np + rkM[rb]] = fM[rb];
-                                            slab_rel[vo + np + rkM[rb]] = static_cast<uint8_t>(r);
+                                            const uint32_t ix = vo + np + __popc(smm & below);
+                                            slab[ix] = fM[rb];
+                                            slab_rel[ix] = static_cast<uint8_t>(r);
                                             mxm = fmaxf(mxm, fM[rb]);
                                             axm = fmaxf(axm, fabsf(fM[rb]));
                                             exm = fmaxf(exm, eM[rb]);
@@ -990,96 +968,116 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     }
                     __syncthreads();
 
-                    // ---- path enumeration: thread tid owns match tid of the sub-batch.
-                    // Each edge's relation values are sorted descending, so combinations
-                    // are visited best-first along every axis and a loop stops at the
-                    // first bound below the kept K-th score (the bound uses the score's
-                    // own association, so FP32 rounding keeps it >= every score it
-                    // covers).  Skipped paths are counted, not listed.
-                    uint32_t np = 0, nm = 0, nl = 0, vo = 0, sy = 0, sx = 0, lb = 0;
-                    uint32_t ip = 0, im = 0, il = 0;
-                    bool done = !take;
-                    if (take) {
-                        const RowInfo &ri = rows[sub_row[tid]];
-                        const uint32_t smp = sub_mp[tid], smm = sub_mm[tid];
-                        sy = sub_y[tid];
-                        sx = ri.x;
-                        lb = ri.vbase;
-                        np = __popc(smp);
-                        nm = __popc(smm);
-                        nl = __popc(ri.mask);
-                        vo = sub_voff[tid];
-                        const float ap = agg[kBlock + tid], ep = agg[2 * kBlock + tid];
-                        const float am = agg[4 * kBlock + tid], em = agg[5 * kBlock + tid];
-                        eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (ap + am + ri.famax));
-                        npaths += static_cast<uint64_t>(np) * nm * nl;
-                    }
-                    int active = __syncthreads_count(!done);
-                    while (active > 0) {
-                        // the free stage slots are shared by the threads still
-                        // enumerating (at least one each), so a lone match with
-                        // many relation combinations fills the stage in one round
-                        if (sh->stage_n + static_cast<uint32_t>(active) > static_cast<uint32_t>(kStage))
-                            merge_stage<KC>(list, stage, sh);
-                        uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
-                        if (quota > kMaxQuota) quota = kMaxQuota;
-                        const Cand thr = sh->thr;
-                        const float tS = EXACT ? thr_exact : thr.s;
-                        uint32_t emitted = 0;
-                        bool dropped = false;
-                        const float fl0 = (!done) ? rowval[lb] : 0.0f;
-                        const float fm0 = (!done) ? slab[vo + np] : 0.0f;
-                        while (!done && emitted < quota) {
-                            if (ip >= np) { done = true; break; }
-                            const float fp = slab[vo + ip];
-                            if (im == 0 && il == 0 && combine3(fwd, fp, fm0, fl0) < tS) {
-                                dropped = true;   // this and every later probe value
-                                done = true;
-                                break;
+                    // ---- path enumeration.  A work item is one (match, probe value,
+                    // mid value) triple; items are spread over the block so that a
+                    // match with many relation combinations does not hold up the
+                    // rest.  Each item walks the list row's values, which are sorted
+                    // descending, and stops at the first path below the kept K-th
+                    // score.  Every skip rests on a bound that uses the score's own
+                    // association with the per-edge maxima in place of the values not
+                    // yet fixed (FP32 addition is monotone, so the bound is >= every
+                    // score it covers).  Skipped paths are counted, not listed.
+                    {
+                        uint32_t nitems = 0;
+                        if (take) {
+                            const RowInfo &ri = rows[sub_row[tid]];
+                            const uint32_t np = __popc(sub_mp[tid]), nm = __popc(sub_mm[tid]);
+                            const float ap = agg[kBlock + tid], ep = agg[2 * kBlock + tid];
+                            const float am = agg[4 * kBlock + tid], em = agg[5 * kBlock + tid];
+                            eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (ap + am + ri.famax));
+                            npaths += static_cast<uint64_t>(np) * nm * __popc(ri.mask);
+                            const float tS0 = EXACT ? thr_exact : sh->thr.s;
+                            if (combine3(fwd, agg[tid], agg[3 * kBlock + tid], ri.fmax) >= tS0)
+                                nitems = np * nm;
+                            else
+                                sh->truncated = 1;   // no path through this match can be kept
+                        }
+                        uint32_t ntot;
+                        const uint32_t iincl = block_incl_scan<uint32_t>(nitems, sh->red32, &ntot);
+                        sub_item[tid] = iincl - nitems;
+                        __syncthreads();
+                        for (uint32_t w0 = 0; w0 < ntot; w0 += kBlock) {
+                            const uint32_t it = w0 + tid;
+                            bool done = it >= ntot;
+                            uint32_t il = 0, nl = 0, lb = 0, sx = 0, sy = 0, rp_ = 0, rm_ = 0;
+                            float fp = 0.0f, fm = 0.0f;
+                            if (!done) {
+                                // the last match whose items start at or before `it`
+                                uint32_t lo = 0, hi = ncnt;
+                                while (hi - lo > 1) {
+                                    const uint32_t mid = (lo + hi) >> 1;
+                                    if (sub_item[mid] <= it) lo = mid; else hi = mid;
+                                }
+                                const uint32_t m = lo;
+                                const uint32_t np = __popc(sub_mp[m]), nm = __popc(sub_mm[m]);
+                                const uint32_t l = it - sub_item[m];
+                                const uint32_t ip = l / nm, im = l - ip * nm;
+                                const uint32_t vo = sub_voff[m];
+                                fp = slab[vo + ip];
+                                fm = slab[vo + np + im];
+                                rp_ = slab_rel[vo + ip];
+                                rm_ = slab_rel[vo + np + im];
+                                const RowInfo &ri = rows[sub_row[m]];
+                                lb = ri.vbase;
+                                nl = __popc(ri.mask);
+                                sx = ri.x;
+                                sy = sub_y[m];
+                                const float tS0 = EXACT ? thr_exact : sh->thr.s;
+                                if (combine3(fwd, fp, fm, ri.fmax) < tS0) {
+                                    done = true;   // every path of this pair of values
+                                    sh->truncated = 1;
+                                }
                             }
-                            if (im >= nm) { ++ip; im = 0; il = 0; continue; }
-                            const float fm = slab[vo + np + im];
-                            if (il == 0 && combine3(fwd, fp, fm, fl0) < tS) {
-                                dropped = true;   // this and every later mid value
-                                ++ip; im = 0;
-                                continue;
-                            }
-                            if (il >= nl) { ++im; il = 0; continue; }
-                            const float fl = rowval[lb + il];
-                            const float S = combine3(fwd, fp, fm, fl);
-                            if (S < tS) {
-                                dropped = true;   // this and every later list value
-                                ++im; il = 0;
-                                continue;
-                            }
-                            const uint32_t rp_ = slab_rel[vo + ip], rm_ = slab_rel[vo + np + im],
-                                           rl_ = rowrel[lb + il];
-                            ++il;
-                            Cand cd;
-                            cd.a = fwd ? sx : sy;
-                            cd.b = fwd ? sy : sx;
-                            const uint32_t r1 = fwd ? rl_ : rp_, r3 = fwd ? rp_ : rl_;
-                            cd.rel = (r1 << 16) | (rm_ << 8) | r3;
-                            cd.s = S;
-                            cd.s_lo = 0.0f;
-                            cd.eps = 0.0f;
-                            if (EXACT) {
-                                float e2;
-                                ff sc = path_score_ff<BF16>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
-                                cd.s = sc.hi;
-                                cd.s_lo = sc.lo;
-                                cd.eps = e2;
-                            }
-                            if (cand_better(cd, thr)) {
-                                uint32_t slot = atomicAdd(&sh->stage_n, 1u);
-                                stage[slot] = cd;
-                                ++emitted;
-                            } else {
-                                dropped = true;
+                            int active = __syncthreads_count(!done);
+                            while (active > 0) {
+                                // the free stage slots are shared by the items still
+                                // walking (at least one each)
+                                if (sh->stage_n + static_cast<uint32_t>(active) > static_cast<uint32_t>(kStage))
+                                    merge_stage<KC>(list, stage, sh);
+                                uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
+                                if (quota > kMaxQuota) quota = kMaxQuota;
+                                const Cand thr = sh->thr;
+                                const float tS = EXACT ? thr_exact : thr.s;
+                                uint32_t emitted = 0;
+                                bool dropped = false;
+                                while (!done && emitted < quota) {
+                                    if (il >= nl) { done = true; break; }
+                                    const float fl = rowval[lb + il];
+                                    const float S = combine3(fwd, fp, fm, fl);
+                                    if (S < tS) {
+                                        dropped = true;   // this and every later list value
+                                        done = true;
+                                        break;
+                                    }
+                                    const uint32_t rl_ = rowrel[lb + il];
+                                    ++il;
+                                    Cand cd;
+                                    cd.a = fwd ? sx : sy;
+                                    cd.b = fwd ? sy : sx;
+                                    const uint32_t r1 = fwd ? rl_ : rp_, r3 = fwd ? rp_ : rl_;
+                                    cd.rel = (r1 << 16) | (rm_ << 8) | r3;
+                                    cd.s = S;
+                                    cd.s_lo = 0.0f;
+                                    cd.eps = 0.0f;
+                                    if (EXACT) {
+                                        float e2;
+                                        ff sc = path_score_ff<BF16>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
+                                        cd.s = sc.hi;
+                                        cd.s_lo = sc.lo;
+                                        cd.eps = e2;
+                                    }
+                                    if (cand_better(cd, thr)) {
+                                        uint32_t slot = atomicAdd(&sh->stage_n, 1u);
+                                        stage[slot] = cd;
+                                        ++emitted;
+                                    } else {
+                                        dropped = true;
+                                    }
+                                }
+                                if (dropped) sh->truncated = 1;
+                                active = __syncthreads_count(!done);
                             }
                         }
-                        if (dropped) sh->truncated = 1;
-                        active = __syncthreads_count(!done);
                     }
                     m0 += ncnt;
                     __syncthreads();
