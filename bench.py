@@ -31,6 +31,39 @@ sys.path.insert(0, ROOT)
 METRIC = "scored 3-hop paths/s and queries/s at K=32 (exact top-K vs FP64 oracle)"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one gather launch on the realistic workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this
+# script, each scaled by what the same counter reads for a plain 1 GiB device
+# copy (bench.py --calibrate-copy): FETCH_SIZE read 524302 KiB for 1048576 KiB
+# fetched (scale 2.0), WRITE_SIZE read 1048576 KiB (scale 1.0).  Valid only
+# for the kernel sources they were taken on (sha256 over the query sources).
+TRAFFIC = {
+    "sources_sha256": "8be38f94cb087c9d158f1b5a5d76e69a3a50afde6ba844a7a2e850b856083670",
+    "fetch_kib": 457324.9,
+    "write_kib": 3020.4,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+KERNEL_SOURCES = ("paper_2406_07727_amd/csrc/mhr_query.hip", "paper_2406_07727_amd/csrc/mhr_device.h",
+                  "paper_2406_07727_amd/csrc/mhr_internal.h")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config):
+    """HBM bytes per gather launch from the committed counter run, or None
+    when the kernel sources changed since (or for another workload)."""
+    if config != "realistic" or TRAFFIC["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return int(TRAFFIC["fetch_kib"] * 1024 * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * 1024 * TRAFFIC["write_scale"])
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -142,7 +175,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="realistic")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bytes", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -224,7 +257,7 @@ def main():
         nbytes += cfg.graph.R * cfg.emb.d * elem
         achieved = nbytes / (gather_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
                 "kernel": "gather_kernel", "bytes_per_launch": int(nbytes), "kernel_ms": round(gather_avg, 4)}
         log(f"gather algorithmic bytes {nbytes / 1e6:.1f} MB ({matches} matched middle pairs) "
             f"in {time.perf_counter() - t1:.1f} s")
