@@ -278,19 +278,55 @@ __global__ __launch_bounds__(kBlock) void tile_starts_kernel(GArgs A) {
 // ---------------------------------------------------------------------------
 // float-float scoring of one path (rescoring and the exhaustive pass)
 // ---------------------------------------------------------------------------
+// One term X[u,i]*Y[r,i]*X[v,i] in float-float: the relation factor times
+// the smaller entity factor exactly (TwoProduct), then times the larger.
+// Taking the entity factors in value order makes the term, and so the edge
+// weight, bit-identical for (u,r,v) and (v,r,u), as the DistMult score is.
+__device__ __forceinline__ ff distmult_term_ff(float xu, float yr, float xv, float *abs_t) {
+    const float lo = fminf(xu, xv), hi = fmaxf(xu, xv);
+    const ff p = two_prod(lo, yr);
+    *abs_t = fabsf(p.hi * hi);
+    return ff_mul_f(p, hi);
+}
+
 template <bool BF16>
 __device__ inline ff edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
     ff acc = {0.0f, 0.0f};
     float as = 0.0f;
     const size_t d = A.d;
     for (uint32_t i = 0; i < A.d; ++i) {
-        float xu = load1<BF16>(A.X, u * d + i);
-        float yr = load1<BF16>(A.Y, r * d + i);
-        float xv = load1<BF16>(A.X, v * d + i);
-        ff p = two_prod(xu, yr);
-        ff t = ff_mul_f(p, xv);
+        float at;
+        const ff t = distmult_term_ff(load1<BF16>(A.X, u * d + i), load1<BF16>(A.Y, r * d + i),
+                                      load1<BF16>(A.X, v * d + i), &at);
         acc = ff_add(acc, t);
-        as += fabsf(p.hi * xv);
+        as += at;
+    }
+    *abs_sum = as;
+    return acc;
+}
+
+// The same sum computed by one wave: lane l takes the terms l, l + 64, ...,
+// and a butterfly combines the lane sums (ff_add is symmetric in its
+// operands, so every lane ends with the same bits).  No term passes through
+// more than d float-float additions, so the error bound of the sequential
+// sum holds.
+template <bool BF16>
+__device__ inline ff wave_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
+    ff acc = {0.0f, 0.0f};
+    float as = 0.0f;
+    const size_t d = A.d;
+    for (uint32_t i = threadIdx.x & (kWave - 1); i < A.d; i += kWave) {
+        float at;
+        const ff t = distmult_term_ff(load1<BF16>(A.X, u * d + i), load1<BF16>(A.Y, r * d + i),
+                                      load1<BF16>(A.X, v * d + i), &at);
+        acc = ff_add(acc, t);
+        as += at;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const ff w = {__shfl_xor(acc.hi, o, kWave), __shfl_xor(acc.lo, o, kWave)};
+        acc = ff_add(acc, w);
+        as += __shfl_xor(as, o, kWave);
     }
     *abs_sum = as;
     return acc;
@@ -299,14 +335,24 @@ __device__ inline ff edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t 
 // S = w(s,r1,a) + w(a,r2,b) + w(b,r3,t) in float-float, with a bound on
 // its error: per edge, the dot product (about 4 d u^2 sum|t|) plus the
 // log-sigmoid; then the two additions.
-template <bool BF16>
+template <bool BF16, bool WAVE>
 __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint32_t b, uint32_t t, uint32_t r1,
                                    uint32_t r2, uint32_t r3, float *eps) {
     const float u2 = kUnit * kUnit;
     float as1, as2, as3;
-    ff w1 = ff_logsigmoid(edge_x_ff<BF16>(A, s, r1, a, &as1));
-    ff w2 = ff_logsigmoid(edge_x_ff<BF16>(A, a, r2, b, &as2));
-    ff w3 = ff_logsigmoid(edge_x_ff<BF16>(A, b, r3, t, &as3));
+    ff x1, x2, x3;
+    if (WAVE) {
+        x1 = wave_edge_x_ff<BF16>(A, s, r1, a, &as1);
+        x2 = wave_edge_x_ff<BF16>(A, a, r2, b, &as2);
+        x3 = wave_edge_x_ff<BF16>(A, b, r3, t, &as3);
+    } else {
+        x1 = edge_x_ff<BF16>(A, s, r1, a, &as1);
+        x2 = edge_x_ff<BF16>(A, a, r2, b, &as2);
+        x3 = edge_x_ff<BF16>(A, b, r3, t, &as3);
+    }
+    ff w1 = ff_logsigmoid(x1);
+    ff w2 = ff_logsigmoid(x2);
+    ff w3 = ff_logsigmoid(x3);
     // Sum in a canonical order (descending) so that the result depends only
     // on the multiset of weights: paths whose weights are permutations of
     // each other (DistMult is symmetric) then tie exactly, as their real
@@ -1061,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     cd.eps = 0.0f;
                                     if (EXACT) {
                                         float e2;
-                                        ff sc = path_score_ff<BF16>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
+                                        ff sc = path_score_ff<BF16, false>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
                                         cd.s = sc.hi;
                                         cd.s_lo = sc.lo;
                                         cd.eps = e2;
@@ -1149,12 +1195,20 @@ __device__ inline void write_result(mhr_path *row, const Cand *c, uint32_t nc, u
 template <int KC>
 __device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, float *s_drop) {
     constexpr uint32_t per = (kMergeSlots - KC) / KC;  // tile lists per step
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) c[i] = cand_sentinel();
     if (threadIdx.x == 0) *s_drop = -__builtin_huge_valf();
+    if (P.ntiles == 1) {   // one tile: its list is already sorted and complete
+        const uint32_t cnt = A.hdr[P.tile_base].count;
+        for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x)
+            c[i] = i < cnt ? A.cands[static_cast<uint64_t>(P.tile_base) * KC + i] : cand_sentinel();
+        __syncthreads();
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) c[i] = cand_sentinel();
     __syncthreads();
     for (uint32_t j0 = 0; j0 < P.ntiles; j0 += per) {
         const uint32_t nt = min(per, P.ntiles - j0);
-        for (uint32_t i = threadIdx.x; i < kMergeSlots - KC; i += blockDim.x) {
+        const uint32_t n = next_pow2((nt + 1) * static_cast<uint32_t>(KC));   // <= kMergeSlots
+        for (uint32_t i = threadIdx.x; i < n - KC; i += blockDim.x) {
             const uint32_t jt = i / KC, k = i % KC;
             Cand x = cand_sentinel();
             if (jt < nt) {
@@ -1164,7 +1218,7 @@ __device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, 
             c[KC + i] = x;
         }
         __syncthreads();
-        block_sort_cands(c, static_cast<int>(kMergeSlots));
+        block_sort_cands(c, static_cast<int>(n));
         if (threadIdx.x == 0 && c[KC].a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, c[KC].s);
         __syncthreads();
     }
@@ -1243,15 +1297,16 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
         return;
     }
     const uint32_t nb = s_nb;
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+    // one wave rescores one band candidate
+    for (uint32_t i = threadIdx.x / kWave; i < nb; i += blockDim.x / kWave) {
         Cand x = c[i];
         const uint32_t r1 = (x.rel >> 16) & 0xFF, r2 = (x.rel >> 8) & 0xFF, r3 = x.rel & 0xFF;
         float e;
-        ff sc = path_score_ff<BF16>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
+        ff sc = path_score_ff<BF16, true>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
         x.s = sc.hi;
         x.s_lo = sc.lo;
         x.eps = e;
-        c[i] = x;
+        if ((threadIdx.x & (kWave - 1)) == 0) c[i] = x;
     }
     const uint32_t nb2 = next_pow2(nb);
     for (uint32_t i = nb + threadIdx.x; i < nb2; i += blockDim.x) c[i] = cand_sentinel();
