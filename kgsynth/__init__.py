@@ -108,6 +108,23 @@ CONFIGS = {
         GraphSpec("chunglu", 3000, 4, 30000, seed=31, wmax=600.0),
         EmbSpec(16, "f32", seed=32),
         QuerySpec(48, "degree", 16, seed=33)),
+    # bfloat16 storage at test sizes: d = 8 and 16 (short per-lane slices),
+    # and d = 64 with 32 relations (two relation blocks per match)
+    "dense_tiny_bf16": Workload(
+        "dense_tiny_bf16",
+        GraphSpec("uniform", 64, 4, 2000, seed=21),
+        EmbSpec(8, "bf16", seed=24),
+        QuerySpec(32, "uniform", 10, seed=23)),
+    "hub_tiny_bf16": Workload(
+        "hub_tiny_bf16",
+        GraphSpec("chunglu", 3000, 4, 30000, seed=31, wmax=600.0),
+        EmbSpec(16, "bf16", seed=34),
+        QuerySpec(48, "degree", 16, seed=33)),
+    "hub_r32_bf16": Workload(
+        "hub_r32_bf16",
+        GraphSpec("chunglu", 4000, 32, 60000, seed=41, wmax=800.0),
+        EmbSpec(64, "bf16", seed=42),
+        QuerySpec(48, "degree", 32, seed=43)),
 }
 
 

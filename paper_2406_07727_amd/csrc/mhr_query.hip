@@ -541,6 +541,18 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh) {
 }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A product of two bfloat16 values (16 significant bits, exact in FP32)
+// split into two bfloat16 halves whose sum is exact: the leading 8
+// significant bits (truncation, so both halves carry the sign of v) and the
+// remaining at most 8 bits.  Returned as bit patterns.
+__device__ __forceinline__ void split_bf16(float v, uint32_t &hi, uint32_t &lo) {
+    const uint32_t b = __float_as_uint(v);
+    hi = b >> 16;
+    lo = __float_as_uint(v - __uint_as_float(b & 0xFFFF0000u)) >> 16;
+}
 
 // Up to 32 consecutive elements [off, off + n) of an embedding row (zeros
 // past n, or everywhere when !valid).  n is a multiple of 2 and off of n's
@@ -884,18 +896,24 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     // d/4 elements [kq*d/4, (kq+1)*d/4) of match m's vectors
                     //   up = e_y * e_anchor_p   (the probe-side edge y -- anchor)
                     //   um = e_y * e_x          (the middle edge y -- x)
-                    // and the same slice of relation row 16*rb + m; each MFMA step
-                    // multiplies a 16x4 slice of [up | um] by a 4x16 slice of Y^T,
-                    // so after d/4 steps D[m][r] = sum_k up[m][k] Y[r][k].  The
-                    // same products with |up| and |Y| give sum_k |up Y|, the scale
-                    // of the rounding error (the K-reduction inside the MFMA takes
-                    // at most d + 3 roundings per output).
+                    // and the same slice of relation row 16*rb + m.  FP32 tables: each
+                    // v_mfma_f32_16x16x4f32 multiplies a 16x4 slice of up (or um) by a
+                    // 4x16 slice of Y^T, so after d/4 steps D[m][r] = sum_k up[m][k]
+                    // Y[r][k].  bfloat16 tables: up and um are exact in FP32 (16
+                    // significant bits); each is split into two bfloat16 halves and
+                    // v_mfma_f32_16x16x32_bf16 takes four elements of both halves per
+                    // lane against the same four elements of Y twice, so every product
+                    // is exact and only the FP32 accumulation rounds.  The rounding
+                    // error is at most gamma_n sum_k |up_k Y_rk| <= gamma_n max_k |Y_rk|
+                    // sum_k |up_k|, with n = d + 3 (FP32) or 2d + 3 (bfloat16).
                     {
                         const int lane = static_cast<int>(tid) & (kWave - 1), wv = static_cast<int>(tid) / kWave;
                         const int mrow = lane & 15, kq = lane >> 4;
                         const uint32_t KCH = d >> 2;
                         const uint32_t nrb = (R + 15) / 16;
-                        const float gam = gamma_n(static_cast<int>(d) + 3) * 1.001f;
+                        // FP32 operands: d products, each rounded once, then the sum.
+                        // bfloat16 operands: 2d exact products (hi and lo halves), then the sum.
+                        const float gam = gamma_n(static_cast<int>(BF16 ? 2 * d : d) + 3) * 1.001f;
                         for (uint32_t t0 = static_cast<uint32_t>(wv) * 16; t0 < ncnt; t0 += (kBlock / kWave) * 16) {
                             const uint32_t mi = t0 + mrow;
                             const bool mval = mi < ncnt;
@@ -914,6 +932,56 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 float ey[32], ex[32];
                                 load_span32<BF16>(A.X, yrow, d, off, kn, mval, ey);
                                 load_span32<BF16>(A.X, xrow, d, off, kn, mval, ex);
+                                if constexpr (BF16) {
+                                    // four elements per lane per step: A = [hi(u) | lo(u)] and
+                                    // B = [y | y] as 8 bfloat16 each, K = 32 per instruction
+#pragma unroll
+                                    for (uint32_t j = 0; j < 32; j += 4) {
+                                        if (j < kn) {
+                                            u32x4 wp, wm;
+#pragma unroll
+                                            for (uint32_t e = 0; e < 4; e += 2) {
+                                                uint32_t ph[2], pl[2], mh[2], ml[2];
+#pragma unroll
+                                                for (uint32_t h = 0; h < 2; ++h) {
+                                                    const bool ok = j + e + h < kn;
+                                                    const float up = ok ? ey[j + e + h] * anc_p[off + j + e + h] : 0.0f;
+                                                    const float um = ok ? ey[j + e + h] * ex[j + e + h] : 0.0f;
+                                                    sup += fabsf(up);
+                                                    sum_ += fabsf(um);
+                                                    split_bf16(up, ph[h], pl[h]);
+                                                    split_bf16(um, mh[h], ml[h]);
+                                                }
+                                                wp[e / 2] = ph[0] | (ph[1] << 16);
+                                                wp[2 + e / 2] = pl[0] | (pl[1] << 16);
+                                                wm[e / 2] = mh[0] | (mh[1] << 16);
+                                                wm[2 + e / 2] = ml[0] | (ml[1] << 16);
+                                            }
+                                            const bf16x8 ap = __builtin_bit_cast(bf16x8, wp);
+                                            const bf16x8 am = __builtin_bit_cast(bf16x8, wm);
+#pragma unroll
+                                            for (uint32_t rb = 0; rb < 2; ++rb) {
+                                                if (rb < nrb) {
+                                                    const uint32_t rr = rb * 16 + static_cast<uint32_t>(mrow);
+                                                    uint32_t yb[4];
+#pragma unroll
+                                                    for (uint32_t e = 0; e < 4; ++e)
+                                                        yb[e] = (rr < R && j + e < kn)
+                                                                    ? __float_as_uint(Ys[rr * ystr + off + j + e]) >> 16
+                                                                    : 0u;
+                                                    u32x4 wy;
+                                                    wy[0] = yb[0] | (yb[1] << 16);
+                                                    wy[1] = yb[2] | (yb[3] << 16);
+                                                    wy[2] = wy[0];
+                                                    wy[3] = wy[1];
+                                                    const bf16x8 bv = __builtin_bit_cast(bf16x8, wy);
+                                                    aP[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap, bv, aP[rb], 0, 0, 0);
+                                                    aM[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bv, aM[rb], 0, 0, 0);
+                                                }
+                                            }
+                                        }
+                                    }
+                                } else {
 #pragma unroll
                                 for (uint32_t j = 0; j < 32; ++j) {
                                     if (j < kn) {
@@ -931,6 +999,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                             }
                                         }
                                     }
+                                }
                                 }
                             }
                             // sum over the four k-quarters of each match (lanes m, m+16, m+32, m+48)
@@ -1421,6 +1490,18 @@ WsLayout ws_layout(uint32_t nq, uint32_t kc) {
 
 int g_num_cus = 0;
 
+constexpr size_t kLdsBytes = 160 * 1024;
+
+// The probe-table size: the caller's choice, else the largest table of at
+// most 2^kDefaultHashLog2 slots whose gather workgroup fits in LDS (large
+// embedding dimensions and relation counts leave less room for it).
+uint32_t hash_log2_for(const mhr_graph *g, const mhr_query_opts *o, uint32_t kmax) {
+    if (o && o->hash_log2) return o->hash_log2;
+    uint32_t h = kDefaultHashLog2;
+    while (h > 10 && gather_layout(h, g->R, g->dim, kc_for(kmax)).total > kLdsBytes) --h;
+    return h;
+}
+
 template <bool BF16, int KC>
 mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, const uint32_t *src,
                       const uint32_t *dst, const uint32_t *k, uint32_t kmax, mhr_path *out, uint32_t *out_count,
@@ -1442,7 +1523,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     A.tcap = tile_capacity(nq);
     A.nq = nq;
     A.kc = KC;
-    A.hash_log2 = (o && o->hash_log2) ? o->hash_log2 : kDefaultHashLog2;
+    A.hash_log2 = hash_log2_for(g, o, kmax);
     const uint32_t tile_edges = (o && o->tile_edges) ? o->tile_edges : kDefaultTileEdges;
     A.tile_edges = tile_edges;
     if (g_num_cus == 0) {
@@ -1495,7 +1576,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
 }  // namespace
 
 size_t gather_lds_bytes(const mhr_graph *g, uint32_t hash_log2, uint32_t kmax) {
-    return gather_layout(hash_log2 ? hash_log2 : kDefaultHashLog2, g->R, g->dim, kc_for(kmax)).total;
+    return gather_layout(hash_log2, g->R, g->dim, kc_for(kmax)).total;
 }
 
 }  // namespace mhr
@@ -1547,8 +1628,8 @@ extern "C" mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_quer
         set_error("workspace too small: need " + std::to_string(need) + " bytes");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
     }
-    const size_t lds = gather_lds_bytes(g, o ? o->hash_log2 : 0, kmax);
-    if (lds > 160 * 1024) {
+    const size_t lds = gather_lds_bytes(g, hash_log2_for(g, o, kmax), kmax);
+    if (lds > kLdsBytes) {
         set_error("LDS demand " + std::to_string(lds) + " exceeds 160 KiB (reduce hash_log2)");
         return MHR_ERR_UNSUPPORTED;
     }

@@ -68,7 +68,8 @@ def test_handworked_fixture():
             assert abs(float(got["score"]) - ref) <= float(got["err_bound"]) + 1e-13
 
 
-@pytest.mark.parametrize("name", ["tiny", "dense_tiny", "hub_tiny"])
+@pytest.mark.parametrize("name", ["tiny", "dense_tiny", "hub_tiny", "dense_tiny_bf16", "hub_tiny_bf16",
+                                  "hub_r32_bf16"])
 def test_small_workloads(name):
     gpu, orc = _small(name)
     compare(gpu, orc)
@@ -247,6 +248,36 @@ def test_edge_weights_against_oracle(name):
         assert np.all(errff <= 1e-12 * (1 + np.abs(w64))), errff.max()
 
 
+@pytest.mark.parametrize("k", [1, 16, 64])
+def test_bf16_two_relation_blocks_k(k):
+    gpu, orc = _small("hub_r32_bf16", k=k)
+    compare(gpu, orc)
+
+
+def test_bf16_edge_weights_against_oracle():
+    cfg, (h, r, t), (Xb, Yb), _ = workload("hub_r32_bf16")
+    n, R = cfg.graph.n, cfg.graph.R
+    rng = np.random.Generator(np.random.PCG64(12))
+    m = 4096
+    u = rng.integers(0, n, m).astype(np.uint32)
+    rr = rng.integers(0, R, m).astype(np.uint32)
+    v = rng.integers(0, n, m).astype(np.uint32)
+    X = oracle.as_f32_table(Xb, "bf16")
+    for scale in (1.0, 16.0):   # power-of-two scaling keeps the values bfloat16
+        Xs = (X * np.float32(scale)).astype(np.float32)
+        Xsb = kgsynth.f32_to_bf16_bits(Xs)
+        assert np.array_equal(kgsynth.bf16_bits_to_f32(Xsb), Xs)
+        say(f"case bf16 edge weights scale={scale}")
+        g = gpu_graph(n, R, h, r, t, Xsb, Yb, "bf16")
+        w, e, hi, lo = (x.cpu().numpy() for x in g.edge_weights(u, rr, v))
+        og = oracle.Graph(n, R, h, r, t)
+        _, w64 = og.edge_weights(Xs, oracle.as_f32_table(Yb, "bf16"), u, rr, v)
+        err32 = np.abs(w.astype(np.float64) - w64)
+        assert np.all(err32 <= e.astype(np.float64) + 1e-15), err32.max()
+        errff = np.abs(hi.astype(np.float64) + lo.astype(np.float64) - w64)
+        assert np.all(errff <= 1e-12 * (1 + np.abs(w64))), errff.max()
+
+
 def test_realistic_full_size_sample():
     """The 1M-vertex / 20M-edge graph, d=128, K=32, in the launch the
     benchmark times (all 1,024 queries); 24 sampled queries are checked
@@ -263,4 +294,23 @@ def test_realistic_full_size_sample():
     compare(gpu, orc, queries=list(sample))
     p, c, tot, st = gpu
     assert np.all(st == 0)
+    assert np.all(c == np.minimum(32, tot))
+
+
+def test_precision_full_size_sample():
+    """The 4M-vertex / 64M-edge graph with d=256 bfloat16 embeddings and 32
+    relations, all 4,096 queries at K=32 in one launch (bfloat16 MFMA
+    scoring); 16 sampled queries are checked against the oracle."""
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("precision")
+    n, R = cfg.graph.n, cfg.graph.R
+    say("case precision full batch")
+    g = gpu_graph(n, R, h, r, t, X, Y, "bf16")
+    gpu = run_gpu(g, s, d, 32)
+    rng = np.random.Generator(np.random.PCG64(19))
+    sample = np.sort(rng.choice(len(s), 16, replace=False))
+    say("oracle on sample")
+    orc = run_oracle(n, R, h, r, t, X, Y, s[sample], d[sample], 32, "bf16")
+    compare(gpu, orc, queries=list(sample))
+    p, c, tot, st = gpu
+    assert np.all((st & ~np.uint32(4)) == 0)
     assert np.all(c == np.minimum(32, tot))
