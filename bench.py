@@ -79,6 +79,7 @@ class HipEvents:
         self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
         self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 
     def create(self):
         e = ctypes.c_void_p()
@@ -222,33 +223,69 @@ def main():
     kk = kd if per_query_k else int(k[0])
 
     ev = HipEvents()
-    res = g.topk(sd, dd, kk, k_max=k_max)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        g.topk(sd, dd, kk, k_max=k_max, out=res)
-    torch.cuda.synchronize()
+    batched = {}
+    if args.config == "batched":
+        # the batched form: autotuned settings, one captured plan per batch
+        t1 = time.perf_counter()
+        tuned, tuned_ms = g.autotune(sd, dd, kk, k_max=k_max, reps=2)
+        batched["autotune"] = {"tile_edges": tuned.tile_edges, "hash_log2": tuned.hash_log2,
+                               "ms_per_call": round(tuned_ms, 4), "seconds": round(time.perf_counter() - t1, 1)}
+        log(f"autotuned: {batched['autotune']}")
+        plan = g.plan(sd, dd, kk, k_max=k_max, opts=tuned)
+        for _ in range(max(1, args.warmup)):
+            plan.launch()
+        torch.cuda.synchronize()
+        e0, e1 = ev.create(), ev.create()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        w0 = time.perf_counter()
+        assert ev.hip.hipEventRecord(e0, stream) == 0
+        for _ in range(args.steps):
+            plan.launch()
+        assert ev.hip.hipEventRecord(e1, stream) == 0
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        step_ms = ev.elapsed_ms(e0, e1) / args.steps
+        res = plan.out
+        # the same batch as one non-captured call per query (bounded sample)
+        nper = min(512, len(s))
+        out1 = g.topk(sd[:1], dd[:1], kd[:1], k_max=k_max)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for q in range(nper):
+            g.topk(sd[q:q + 1], dd[q:q + 1], kd[q:q + 1], k_max=k_max, out=out1)
+        torch.cuda.synchronize()
+        per_query_s = (time.perf_counter() - p0) / nper
+        batched["per_query_launch_queries_per_s"] = 1.0 / per_query_s
+        batched["per_query_launch_sample"] = nper
+        gather_avg = None
+    else:
+        res = g.topk(sd, dd, kk, k_max=k_max)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            g.topk(sd, dd, kk, k_max=k_max, out=res)
+        torch.cuda.synchronize()
 
-    evs = [mhr.PhaseEvents(ev.create().value, ev.create().value, ev.create().value, ev.create().value)
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for i in range(args.steps):
-        g.topk(sd, dd, kk, k_max=k_max, out=res, events=evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    step_ms = ev.elapsed_ms(ctypes.c_void_p(evs[0].begin), ctypes.c_void_p(evs[-1].end)) / args.steps
-    gather_ms = [ev.elapsed_ms(ctypes.c_void_p(e.gather_begin), ctypes.c_void_p(e.gather_end)) for e in evs]
-    gather_avg = float(np.mean(gather_ms))
+        evs = [mhr.PhaseEvents(ev.create().value, ev.create().value, ev.create().value, ev.create().value)
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(args.steps):
+            g.topk(sd, dd, kk, k_max=k_max, out=res, events=evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        step_ms = ev.elapsed_ms(ctypes.c_void_p(evs[0].begin), ctypes.c_void_p(evs[-1].end)) / args.steps
+        gather_ms = [ev.elapsed_ms(ctypes.c_void_p(e.gather_begin), ctypes.c_void_p(e.gather_end)) for e in evs]
+        gather_avg = float(np.mean(gather_ms))
 
     p, cnt, tot, st = res.to_numpy()
     paths = int(tot.sum())
     exact_pass = int(np.sum((st & mhr.Q_EXACT_PASS) != 0))
     bad = int(np.sum((st & ~np.uint32(mhr.Q_EXACT_PASS)) != 0))
-    log(f"step {step_ms:.3f} ms (host wall {1e3 * wall / args.steps:.3f} ms/step), gather {gather_avg:.3f} ms, "
+    log(f"step {step_ms:.3f} ms (host wall {1e3 * wall / args.steps:.3f} ms/step), gather {gather_avg} ms, "
         f"paths/batch {paths}, exact-pass queries {exact_pass}, bad statuses {bad}")
 
     roof = None
-    if not args.no_bytes:
+    if not args.no_bytes and gather_avg is not None:
         t1 = time.perf_counter()
         csr_out = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=False))
         csr_in = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=True))
@@ -290,6 +327,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if batched:
+        out["batched"] = batched
     print(json.dumps(out), flush=True)
 
 

@@ -53,7 +53,8 @@ typedef enum mhr_status {
     MHR_ERR_OUT_OF_MEMORY = 4,
     MHR_ERR_DEVICE = 5,
     MHR_ERR_NO_EMBEDDINGS = 6,
-    MHR_ERR_BAD_EDGE = 7
+    MHR_ERR_BAD_EDGE = 7,
+    MHR_ERR_INTERNAL = 8          /* an internal consistency check failed */
 } mhr_status;
 
 typedef enum mhr_dtype {
@@ -190,6 +191,54 @@ mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *opt
                                    uint64_t *out_total, uint32_t *out_status,
                                    void *workspace, size_t ws_bytes, void *stream,
                                    const mhr_phase_events *ev);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: one captured launch for a fixed batch shape.
+ *
+ * Many queries with uneven frontiers already run as one persistent gather
+ * launch inside mhr_topk_paths (tiles of bounded work pulled from a device
+ * counter).  A plan additionally captures the whole call (planning,
+ * scheduling, gather, merge, and the exhaustive pass) into a HIP graph once,
+ * so that a serving loop replays it with a single launch.
+ * ------------------------------------------------------------------------- */
+typedef struct mhr_plan mhr_plan;
+
+/* Captures mhr_topk_paths(g, opts, nq, src, dst, k, k_max, out, out_count,
+ * out_total, out_status, workspace, ws_bytes) into a HIP graph.  The
+ * pointers are fixed in the plan; their contents are read at each launch, so
+ * the caller may write a new batch of nq queries into src/dst/k between
+ * launches.  stream: the stream captured on (NULL = a private stream the call
+ * creates and destroys); nothing runs during the call.  The plan holds
+ * references to g and the buffers: they must outlive it.  Errors: those of
+ * mhr_topk_paths (checked before capture), DEVICE (capture/instantiation). */
+mhr_status mhr_plan_create(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                           const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                           uint32_t k_max, mhr_path *out, uint32_t *out_count,
+                           uint64_t *out_total, uint32_t *out_status,
+                           void *workspace, size_t ws_bytes, void *stream, mhr_plan **plan);
+
+/* Launches the captured call on `stream` (asynchronous; one graph launch).
+ * Launches of one plan must not overlap (they share the workspace). */
+mhr_status mhr_plan_launch(mhr_plan *plan, void *stream);
+
+mhr_status mhr_plan_destroy(mhr_plan *plan);
+
+/* Autotuner.  Times mhr_topk_paths on the given batch for candidate values of
+ * tile_edges and hash_log2 (the other fields of *base are kept), `reps` timed
+ * runs each after one untimed run, and writes the fastest setting to *tuned
+ * and its mean time per call (ms) to *best_ms (may be NULL).  Tuning never
+ * changes results: every candidate's outputs (out, out_count, out_total,
+ * out_status) are compared byte for byte with the first candidate's, and a
+ * difference returns MHR_ERR_INTERNAL.  Blocks the calling thread (it
+ * synchronises `stream` and copies outputs to host memory); not for the
+ * query path.  The output buffers hold the last candidate's results on
+ * return.  Errors: those of mhr_topk_paths, INTERNAL. */
+mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t nq,
+                        const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                        uint32_t k_max, mhr_path *out, uint32_t *out_count,
+                        uint64_t *out_total, uint32_t *out_status,
+                        void *workspace, size_t ws_bytes, void *stream, uint32_t reps,
+                        mhr_query_opts *tuned, float *best_ms);
 
 /* Edge-weight kernel on its own (for checking the scorer):
  * for each i < ne, the edge (u[i], r[i], v[i]) (it need not exist in the

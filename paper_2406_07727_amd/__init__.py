@@ -91,6 +91,16 @@ _lib.mhr_topk_paths_profiled.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _
                                          _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(PhaseEvents)]
 _lib.mhr_edge_weights.restype = _i
 _lib.mhr_edge_weights.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_plan_create.restype = _i
+_lib.mhr_plan_create.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                 _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+_lib.mhr_plan_launch.restype = _i
+_lib.mhr_plan_launch.argtypes = [_vp, _vp]
+_lib.mhr_plan_destroy.restype = _i
+_lib.mhr_plan_destroy.argtypes = [_vp]
+_lib.mhr_autotune.restype = _i
+_lib.mhr_autotune.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp,
+                              ctypes.c_size_t, _vp, _u32, ctypes.POINTER(QueryOpts), ctypes.POINTER(ctypes.c_float)]
 _lib.mhr_status_string.restype = ctypes.c_char_p
 _lib.mhr_status_string.argtypes = [_i]
 _lib.mhr_last_error.restype = ctypes.c_char_p
@@ -230,12 +240,8 @@ class Graph:
                                        ctypes.byref(n)), "mhr_workspace_size")
         return int(n.value)
 
-    def topk(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
-             out: Optional[TopK] = None, stream=None, events: Optional[PhaseEvents] = None) -> TopK:
-        """Exact top-K three-hop paths for each (src[q], dst[q]).  k: an int
-        (same K for all) or a per-query integer tensor (then k_max bounds
-        it).  Asynchronous on the current stream."""
-        torch = _torch()
+    @staticmethod
+    def _queries(src, dst, k, k_max, opts):
         s, d = _dev_u32(src), _dev_u32(dst)
         nq = s.numel()
         o = QueryOpts() if opts is None else opts
@@ -249,17 +255,30 @@ class Graph:
             kt = _dev_u32(k)
             if k_max is None:
                 k_max = int(kt.max().item()) if nq else 1
-        k_max = int(k_max)
+        return s, d, kt, nq, o, int(k_max)
+
+    @staticmethod
+    def _new_out(nq, k_max):
+        torch = _torch()
+        return TopK(torch.empty((nq, k_max, 24), dtype=torch.uint8, device="cuda"),
+                    torch.empty(nq, dtype=torch.int32, device="cuda"),
+                    torch.empty(nq, dtype=torch.int64, device="cuda"),
+                    torch.empty(nq, dtype=torch.int32, device="cuda"), k_max)
+
+    def topk(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
+             out: Optional[TopK] = None, stream=None, events: Optional[PhaseEvents] = None) -> TopK:
+        """Exact top-K three-hop paths for each (src[q], dst[q]).  k: an int
+        (same K for all) or a per-query integer tensor (then k_max bounds
+        it).  Asynchronous on the current stream."""
+        torch = _torch()
+        s, d, kt, nq, o, k_max = self._queries(src, dst, k, k_max, opts)
         need = self.workspace_bytes(nq, k_max, o)
         ws = self._ws.get("buf")
         if ws is None or ws.numel() < need:
             ws = torch.empty(need, dtype=torch.uint8, device="cuda")
             self._ws["buf"] = ws
         if out is None:
-            out = TopK(torch.empty((nq, k_max, 24), dtype=torch.uint8, device="cuda"),
-                       torch.empty(nq, dtype=torch.int32, device="cuda"),
-                       torch.empty(nq, dtype=torch.int64, device="cuda"),
-                       torch.empty(nq, dtype=torch.int32, device="cuda"), k_max)
+            out = self._new_out(nq, k_max)
         if events is None:
             _check(_lib.mhr_topk_paths(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
                                        _ptr(out.paths), _ptr(out.count), _ptr(out.total), _ptr(out.status),
@@ -271,6 +290,28 @@ class Graph:
                                                 ctypes.byref(events)), "mhr_topk_paths_profiled")
         out._keep = (s, d, kt)
         return out
+
+    def autotune(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
+                 reps: int = 3, stream=None):
+        """Fastest (tile_edges, hash_log2) for this batch, by timing each
+        candidate; the library checks that every candidate gives identical
+        results.  Returns (QueryOpts, ms per call).  Synchronises."""
+        torch = _torch()
+        s, d, kt, nq, o, k_max = self._queries(src, dst, k, k_max, opts)
+        ws = torch.empty(self.workspace_bytes(nq, k_max, o), dtype=torch.uint8, device="cuda")
+        out = self._new_out(nq, k_max)
+        tuned = QueryOpts()
+        ms = ctypes.c_float()
+        _check(_lib.mhr_autotune(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
+                                 _ptr(out.paths), _ptr(out.count), _ptr(out.total), _ptr(out.status),
+                                 _ptr(ws), ws.numel(), _stream_ptr(stream), int(reps), ctypes.byref(tuned),
+                                 ctypes.byref(ms)), "mhr_autotune")
+        return tuned, float(ms.value)
+
+    def plan(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
+             stream=None) -> "Plan":
+        """Captures one batched query call into a HIP graph (see Plan)."""
+        return Plan(self, src, dst, k, k_max, opts, stream)
 
     def edge_weights(self, u, r, v, stream=None):
         """FP32 log-sigmoid DistMult weights with their error bounds, and the
@@ -287,5 +328,56 @@ class Graph:
         return w, e, hi, lo
 
 
-__all__ = ["Graph", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+class Plan:
+    """A batched query call captured once into a HIP graph and replayed with
+    one launch.  The plan owns fixed device buffers for the queries
+    (``src``, ``dst``, ``k``), the workspace and the results (``out``);
+    ``set_queries`` copies a new batch of the same size into them."""
+
+    def __init__(self, graph: Graph, src, dst, k, k_max, opts, stream):
+        torch = _torch()
+        s, d, kt, nq, o, k_max = Graph._queries(src, dst, k, k_max, opts)
+        self.graph = graph
+        self.nq, self.k_max, self.opts = nq, k_max, o
+        self.src, self.dst = s.clone(), d.clone()
+        self.k = kt.clone() if kt is not None else None
+        self.ws = torch.empty(graph.workspace_bytes(nq, k_max, o), dtype=torch.uint8, device="cuda")
+        self.out = Graph._new_out(nq, k_max)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(_lib.mhr_plan_create(graph._h, ctypes.byref(o), nq, _ptr(self.src), _ptr(self.dst), _ptr(self.k),
+                                    k_max, _ptr(self.out.paths), _ptr(self.out.count), _ptr(self.out.total),
+                                    _ptr(self.out.status), _ptr(self.ws), self.ws.numel(),
+                                    _stream_ptr(stream), ctypes.byref(h)), "mhr_plan_create")
+        self._h = h
+
+    def set_queries(self, src, dst, k=None):
+        """Writes a new batch (same size) into the plan's query buffers."""
+        s, d = _dev_u32(src), _dev_u32(dst)
+        if s.numel() != self.nq or d.numel() != self.nq:
+            raise ValueError("a plan's batch size is fixed")
+        self.src.copy_(s)
+        self.dst.copy_(d)
+        if k is not None:
+            if self.k is None:
+                raise ValueError("this plan was captured with one K for all queries")
+            self.k.copy_(_dev_u32(k))
+
+    def launch(self, stream=None) -> TopK:
+        _check(_lib.mhr_plan_launch(self._h, _stream_ptr(stream)), "mhr_plan_launch")
+        return self.out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.mhr_plan_destroy(self._h), "mhr_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Graph", "Plan", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
            "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]

@@ -24,6 +24,7 @@ extern "C" const char *mhr_status_string(mhr_status s) {
         case MHR_ERR_DEVICE: return "device error";
         case MHR_ERR_NO_EMBEDDINGS: return "embeddings not set";
         case MHR_ERR_BAD_EDGE: return "edge id out of range";
+        case MHR_ERR_INTERNAL: return "internal consistency check failed";
     }
     return "unknown status";
 }

@@ -314,3 +314,71 @@ def test_precision_full_size_sample():
     p, c, tot, st = gpu
     assert np.all((st & ~np.uint32(4)) == 0)
     assert np.all(c == np.minimum(32, tot))
+
+
+def test_plan_replays_match_eager():
+    """A captured plan replayed several times, with eager calls and
+    synchronisations between the replays, returns the eager results each
+    time; a new batch written into its buffers is answered too."""
+    import torch
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    say("case plan replays")
+    g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y)
+    kq = (np.arange(len(s)) % 3 * 7 + 1).astype(np.uint32)   # K in {1, 8, 15}
+    ref = run_gpu(g, s, d, kq, k_max=16)
+    rs, rd = s[::-1].copy(), d[::-1].copy()
+    ref_rev = run_gpu(g, rs, rd, kq[::-1].copy(), k_max=16)
+    plan = g.plan(s, d, kq, k_max=16)
+    for rep in range(3):
+        got = plan.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got.to_numpy()):
+            assert np.array_equal(a, b), f"replay {rep}"
+        run_gpu(g, rs, rd, 16)   # eager work between replays
+        torch.cuda.synchronize()
+    plan.set_queries(rs, rd, kq[::-1].copy())
+    got = plan.launch()
+    torch.cuda.synchronize()
+    for a, b in zip(ref_rev, got.to_numpy()):
+        assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_autotune_keeps_results():
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    say("case autotune")
+    g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y)
+    ref = run_gpu(g, s, d, 16)
+    tuned, ms = g.autotune(s, d, 16, reps=2)
+    assert tuned.tile_edges in (8192, 16384, 32768, 65536, 131072, 262144, 524288)
+    assert tuned.hash_log2 in (10, 11, 12)
+    assert ms > 0
+    got = run_gpu(g, s, d, 16, opts=tuned)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_batched_full_size_sample():
+    """The batched workload: the 1M-vertex graph with 16,384 queries (10%
+    hub sources), K drawn from {1, 8, 64}, autotuned and run as one captured
+    plan; 16 sampled queries are checked against the oracle."""
+    import torch
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("batched")
+    n, R = cfg.graph.n, cfg.graph.R
+    say("case batched full size")
+    g = gpu_graph(n, R, h, r, t, X, Y)
+    tuned, ms = g.autotune(s, d, kk, k_max=64, reps=1)
+    say(f"tuned tile_edges={tuned.tile_edges} hash_log2={tuned.hash_log2} ({ms:.2f} ms)")
+    plan = g.plan(s, d, kk, k_max=64, opts=tuned)
+    plan.launch()
+    torch.cuda.synchronize()
+    gpu = plan.out.to_numpy()
+    rng = np.random.Generator(np.random.PCG64(23))
+    sample = np.sort(rng.choice(len(s), 16, replace=False))
+    say("oracle on sample")
+    orc = run_oracle(n, R, h, r, t, X, Y, s[sample], d[sample], kk[sample])
+    compare(gpu, orc, queries=list(sample))
+    p, c, tot, st = gpu
+    assert np.all((st & ~np.uint32(4)) == 0)
+    assert np.all(c == np.minimum(kk, tot))
+    plan.close()
