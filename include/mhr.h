@@ -192,6 +192,23 @@ mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *opt
                                    void *workspace, size_t ws_bytes, void *stream,
                                    const mhr_phase_events *ev);
 
+/* Pruned search: mhr_topk_paths restricted by keep flags, as a frontier
+ * pruner decides them (the learned pruner below, or any other rule).
+ *   keep      device uint8 flags; for query q, keep[keep_off[q] + i] is the
+ *             flag of entry i of s's out-row (i < deg+(s), forward CSR order)
+ *             and keep[keep_off[q] + deg+(s) + j] that of entry j of t's
+ *             in-row (reverse CSR order); nonzero = kept
+ *   keep_off  device uint64[nq]
+ * The result is the exact top-K over the paths s -> a -> b -> t whose pair
+ * (s, a) and pair (b, t) are kept: the search of the full graph with the
+ * pruned-away first and last edges removed.  out_total counts those paths.
+ * Other arguments and errors as mhr_topk_paths. */
+mhr_status mhr_topk_paths_pruned(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                                 const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                 uint32_t k_max, const uint8_t *keep, const uint64_t *keep_off,
+                                 mhr_path *out, uint32_t *out_count, uint64_t *out_total,
+                                 uint32_t *out_status, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched form: one captured launch for a fixed batch shape.
  *

@@ -62,7 +62,20 @@ struct GArgs {
     Cand *cands;
     uint32_t *exact_list;
     uint32_t tcap, hash_log2, nq, kc, tile_edges;
+    const uint8_t *keep;         // pruned search: keep flags (nullptr: every entry kept)
+    const uint64_t *keep_off;    // per query: offset of its flags in keep
 };
+
+// Keep flags of the pruned search: per query, one byte per entry of s's
+// out-row, then one per entry of t's in-row (nonzero = kept).  A pruned-away
+// entry removes that first (or last) edge pair from every path.  nullptr
+// when the search is not pruned.
+__device__ inline const uint8_t *keep_row(const GArgs &A, uint32_t q, uint32_t s, bool t_row) {
+    if (!A.keep) return nullptr;
+    uint64_t off = A.keep_off[q];
+    if (t_row) off += A.out_rp[s + 1] - A.out_rp[s];
+    return A.keep + off;
+}
 
 constexpr uint32_t kMaxTilesPerQuery = 4096;
 constexpr uint32_t kMergeSlots = 2048;      // LDS candidates per merge step
@@ -144,10 +157,11 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
     }
     // backward: list N-(t) (reverse CSR row of t), scanned rows in the reverse CSR
     const uint32_t lb_beg = A.in_rp[P.t], lb_len = A.in_rp[P.t + 1] - lb_beg;
+    const uint8_t *kb = keep_row(A, q, P.s, true), *kf = keep_row(A, q, P.s, false);
     uint64_t part = 0;
     for (uint32_t i = threadIdx.x; i < lb_len; i += kBlock) {
         uint32_t b = A.in_col[lb_beg + i];
-        part += A.in_rp[b + 1] - A.in_rp[b];
+        if (!kb || kb[i]) part += A.in_rp[b + 1] - A.in_rp[b];
     }
     const uint64_t cost_b = block_sum<uint64_t>(part, red64);
     // forward: list N+(s), scanned rows in the forward CSR; stop once it
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
     for (uint32_t base = 0; base < lf_len && cost_f < cost_b; base += kBlock) {
         uint64_t p = 0;
         uint32_t i = base + threadIdx.x;
-        if (i < lf_len) {
+        if (i < lf_len && (!kf || kf[i])) {
             uint32_t a = A.out_col[lf_beg + i];
             p = A.out_rp[a + 1] - A.out_rp[a];
         }
@@ -254,11 +268,12 @@ __global__ __launch_bounds__(kBlock) void tile_starts_kernel(GArgs A) {
     const bool fwd = P.dir != 0;
     const uint32_t *rp = fwd ? A.out_rp : A.in_rp;
     const uint32_t *col = fwd ? A.out_col : A.in_col;
+    const uint8_t *kl = keep_row(A, q, P.s, !fwd);
     uint64_t run = 0;
     for (uint32_t base = 0; base < P.list_len; base += kBlock) {
         const uint32_t i = base + threadIdx.x;
         uint64_t deg = 0;
-        if (i < P.list_len) {
+        if (i < P.list_len && (!kl || kl[i])) {
             const uint32_t x = col[P.list_beg + i];
             deg = rp[x + 1] - rp[x];
         }
@@ -708,8 +723,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             sh->thr = cand_sentinel();
         }
         __syncthreads();
+        const uint8_t *kl = keep_row(A, q, P.s, !fwd), *kp = keep_row(A, q, P.s, fwd);
         if (!heavy) {
             for (uint32_t i = tid; i < P.probe_len; i += kBlock) {
+                if (kp && !kp[i]) continue;   // pruned away
                 uint32_t y = Pcol[P.probe_beg + i];
                 uint32_t m = Pmask[P.probe_beg + i];
                 uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
@@ -746,6 +763,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 if (i == ts.x) beg += ts.y;
                 if (i == te.x) end = Lrp[x] + te.y;
                 len = end > beg ? end - beg : 0u;
+                if (kl && !kl[i]) len = 0;   // pruned away
                 nv = __popc(mask);
                 rows[tid].x = x;
                 rows[tid].mask = mask;
@@ -836,7 +854,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         uint32_t lo = dir[bk], hi = dir[bk + 1];
                         for (uint32_t i = lo; i < hi; ++i) {
                             uint32_t c = Pcol[P.probe_beg + i];
-                            if (c == y) { hits[k] = true; mps[k] = Pmask[P.probe_beg + i]; break; }
+                            if (c == y) {
+                                if (!kp || kp[i]) { hits[k] = true; mps[k] = Pmask[P.probe_beg + i]; }
+                                break;
+                            }
                             if (c > y) break;
                         }
                     }
@@ -1506,8 +1527,10 @@ template <bool BF16, int KC>
 mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, const uint32_t *src,
                       const uint32_t *dst, const uint32_t *k, uint32_t kmax, mhr_path *out, uint32_t *out_count,
                       uint64_t *out_total, uint32_t *out_status, void *ws, hipStream_t st,
-                      const mhr_phase_events *ev) {
+                      const mhr_phase_events *ev, const uint8_t *keep, const uint64_t *keep_off) {
     GArgs A = make_args(g);
+    A.keep = keep;
+    A.keep_off = keep_off;
     auto rec = [&](void *e) -> hipError_t {
         return e ? hipEventRecord(static_cast<hipEvent_t>(e), st) : hipSuccess;
     };
@@ -1604,11 +1627,12 @@ extern "C" mhr_status mhr_topk_paths(const mhr_graph *g, const mhr_query_opts *o
                                    ws_bytes, stream, nullptr);
 }
 
-extern "C" mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq,
-                                              const uint32_t *src, const uint32_t *dst, const uint32_t *k,
-                                              uint32_t kmax, mhr_path *out, uint32_t *out_count,
-                                              uint64_t *out_total, uint32_t *out_status, void *workspace,
-                                              size_t ws_bytes, void *stream, const mhr_phase_events *ev) {
+namespace {
+
+mhr_status topk_impl(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, const uint32_t *src,
+                     const uint32_t *dst, const uint32_t *k, uint32_t kmax, mhr_path *out, uint32_t *out_count,
+                     uint64_t *out_total, uint32_t *out_status, void *workspace, size_t ws_bytes, void *stream,
+                     const mhr_phase_events *ev, const uint8_t *keep, const uint64_t *keep_off) {
     MHR_ARG_CHECK(g != nullptr, "mhr_topk_paths: null graph");
     if (!g->X) {
         set_error("embeddings not set");
@@ -1636,13 +1660,35 @@ extern "C" mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_quer
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool bf = g->dtype == MHR_DTYPE_BF16;
     switch (kc) {
-        case 64: return bf ? launch_all<true, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev)
-                           : launch_all<false, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev);
-        case 128: return bf ? launch_all<true, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev)
-                            : launch_all<false, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev);
-        default: return bf ? launch_all<true, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev)
-                           : launch_all<false, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev);
+        case 64: return bf ? launch_all<true, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
+                           : launch_all<false, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
+        case 128: return bf ? launch_all<true, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
+                            : launch_all<false, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
+        default: return bf ? launch_all<true, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
+                           : launch_all<false, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
     }
+}
+
+}  // namespace
+
+extern "C" mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq,
+                                              const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                              uint32_t kmax, mhr_path *out, uint32_t *out_count,
+                                              uint64_t *out_total, uint32_t *out_status, void *workspace,
+                                              size_t ws_bytes, void *stream, const mhr_phase_events *ev) {
+    return topk_impl(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, ws_bytes, stream,
+                     ev, nullptr, nullptr);
+}
+
+extern "C" mhr_status mhr_topk_paths_pruned(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq,
+                                            const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                            uint32_t kmax, const uint8_t *keep, const uint64_t *keep_off,
+                                            mhr_path *out, uint32_t *out_count, uint64_t *out_total,
+                                            uint32_t *out_status, void *workspace, size_t ws_bytes,
+                                            void *stream) {
+    MHR_ARG_CHECK(keep != nullptr && keep_off != nullptr, "mhr_topk_paths_pruned: null keep flags");
+    return topk_impl(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, ws_bytes, stream,
+                     nullptr, keep, keep_off);
 }
 
 extern "C" mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const uint32_t *u, const uint32_t *r,
