@@ -257,6 +257,91 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
                         void *workspace, size_t ws_bytes, void *stream, uint32_t reps,
                         mhr_query_opts *tuned, float *best_ms);
 
+/* ---------------------------------------------------------------------------
+ * Learned frontier pruner.
+ *
+ * The generic search of section 5 bounds each level's frontier by a per-
+ * parent top-K; here a small network ranks a query's frontier candidates
+ * instead, so that cold ones are skipped, and the exact search stays as the
+ * fallback and as the judge of its recall.  Candidates of a query (s, t):
+ *   first hop   one per relation r1 of each entry a of s's out-row (edge s -r1-> a)
+ *   second hop  one per relation r3 of each entry b of t's in-row  (edge b -r3-> t)
+ * Network (f = [X[s], X[t], X[v], Y[r]], v = a or b, r = r1 or r3):
+ *   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), z = w3 . h2 + b3, p = sigmoid(z)
+ * with W1 [hidden][4 dim], W2 [hidden][hidden], w3 [hidden].  Parameters are
+ * one flat FP32 vector: W1 (row-major), b1, W2 (row-major), b2, w3, b3.
+ * Products use bfloat16 operands (features, W1, W2, w3, h1, h2 and the back-
+ * propagated gradients rounded to nearest even) with FP32 accumulation; the
+ * master weights and Adam state are FP32.
+ * ------------------------------------------------------------------------- */
+typedef struct mhr_pruner mhr_pruner;
+
+/* Number of parameters for embedding dimension dim and hidden width hidden. */
+size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden);
+
+/* dim: multiple of 8 in [8, 512] (the graph's embedding dimension);
+ * hidden: multiple of 16 in [16, 4096].  Parameters start at zero (set them
+ * with mhr_pruner_set_params).  Allocates device memory (hipMalloc). */
+mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_pruner **out);
+mhr_status mhr_pruner_destroy(mhr_pruner *p);
+
+/* Copies params (device FP32 [param_count]) in and resets the Adam state. */
+mhr_status mhr_pruner_set_params(mhr_pruner *p, const float *params, void *stream);
+
+/* Copies the parameters and/or the gradient of the last training step out
+ * (device FP32 [param_count] each; either may be NULL). */
+mhr_status mhr_pruner_get_params(const mhr_pruner *p, float *params, float *grad, void *stream);
+
+/* Device workspace bytes for forward or training calls on n samples. */
+mhr_status mhr_pruner_workspace_size(const mhr_pruner *p, uint32_t n, size_t *bytes);
+
+/* Logits z for n samples: sample i is the candidate (v[i], r[i]) of query
+ * q[i], whose endpoints are src[q[i]], dst[q[i]].  All device arrays; the
+ * embeddings are the graph's (dimension must equal the pruner's). */
+mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q,
+                              const uint32_t *src, const uint32_t *dst, const uint32_t *v,
+                              const uint32_t *r, float *logits, void *ws, size_t ws_bytes, void *stream);
+
+/* One training step on n labelled samples (label: device FP32 0/1 [n]):
+ * forward, the mean binary cross-entropy with positive-class weight
+ * pos_weight (written to *loss, device, if not NULL), the gradient (kept in
+ * the pruner, see get_params), and, if update != 0, one Adam step with
+ * learning rate lr (bias-corrected, step count kept in the pruner). */
+mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q,
+                                 const uint32_t *src, const uint32_t *dst, const uint32_t *v,
+                                 const uint32_t *r, const float *label, float pos_weight, float lr,
+                                 float beta1, float beta2, float eps, int update, float *loss,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* Candidate bookkeeping for nq queries (device arrays).  entry_off and
+ * cand_off receive [nq + 1] exclusive offsets: entries are the keep-flag
+ * layout of mhr_topk_paths_pruned (deg+(s) then deg-(t) per query), cand_off
+ * the candidates (relations summed over those entries); [nq] holds the
+ * totals.  A query with an id out of range has none. */
+mhr_status mhr_pruner_count(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                            uint64_t *entry_off, uint64_t *cand_off, void *stream);
+
+/* Writes the candidates: query, vertex, relation and keep-flag index of each
+ * (first-hop ones of a query first, in CSR order and ascending relation),
+ * and cand_split[q], the index of the query's first second-hop candidate.
+ * Output arrays hold cand_off[nq] elements. */
+mhr_status mhr_pruner_enumerate(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                const uint64_t *entry_off, const uint64_t *cand_off, uint64_t *cand_split,
+                                uint32_t *cand_q, uint32_t *cand_v, uint32_t *cand_r, uint64_t *cand_e,
+                                void *stream);
+
+/* Per query and hop, keeps the ceil(n * keep_permille / 1000) candidates
+ * with the highest score (and every candidate tied with the lowest kept
+ * one); an entry is kept when any of its candidates is.  Writes the keep
+ * flags (all entries of the query, see mhr_topk_paths_pruned) and, if mass
+ * is not NULL, mass[2q + hop] = the kept share of sum(sigmoid(score)) (1
+ * when the hop has no candidates).  Scores may be logits or any other
+ * ranking (NaN ranks lowest). */
+mhr_status mhr_pruner_select(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                             const uint64_t *entry_off, const uint64_t *cand_off,
+                             const uint64_t *cand_split, const float *score, const uint64_t *cand_e,
+                             uint32_t keep_permille, uint8_t *keep, float *mass, void *stream);
+
 /* Edge-weight kernel on its own (for checking the scorer):
  * for each i < ne, the edge (u[i], r[i], v[i]) (it need not exist in the
  * graph): w_f32[i] = FP32 log-sigmoid of the DistMult score and err_f32[i] a

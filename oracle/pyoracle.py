@@ -26,18 +26,27 @@ def edge_weight(X, Y, u, r, v) -> float:
     return logsigmoid(acc)
 
 
-def topk_paths(edges, X, Y, s, t, K):
+def topk_paths(edges, X, Y, s, t, K, keep_first=None, keep_last=None):
     """edges: iterable of (h, r, t) triples (duplicates allowed; they are
     merged).  X, Y: nested sequences of floats.  Returns (paths, total) with
-    paths a list of (S, a, b, r1, r2, r3), best first."""
+    paths a list of (S, a, b, r1, r2, r3), best first.
+
+    keep_first / keep_last (sets of vertices, or None for all) restrict the
+    paths to those whose first intermediate vertex a, resp. second
+    intermediate vertex b, is kept: the pruned search, where a pruner drops
+    the pair (s, a) as a first edge or the pair (b, t) as a last edge."""
     out = defaultdict(list)
     for (h, r, v) in sorted(set((int(h), int(r), int(v)) for (h, r, v) in edges)):
         out[h].append((r, v))
     paths = []
     for (r1, a) in out[s]:
+        if keep_first is not None and a not in keep_first:
+            continue
         w1 = edge_weight(X, Y, s, r1, a)
         for (r2, b) in out[a]:
             w2 = edge_weight(X, Y, a, r2, b)
+            if keep_last is not None and b not in keep_last:
+                continue
             for (r3, tt) in out[b]:
                 if tt != t:
                     continue

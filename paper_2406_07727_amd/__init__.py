@@ -101,6 +101,33 @@ _lib.mhr_plan_destroy.argtypes = [_vp]
 _lib.mhr_autotune.restype = _i
 _lib.mhr_autotune.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp,
                               ctypes.c_size_t, _vp, _u32, ctypes.POINTER(QueryOpts), ctypes.POINTER(ctypes.c_float)]
+_lib.mhr_topk_paths_pruned.restype = _i
+_lib.mhr_topk_paths_pruned.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_pruner_param_count.restype = ctypes.c_size_t
+_lib.mhr_pruner_param_count.argtypes = [_u32, _u32]
+_lib.mhr_pruner_create.restype = _i
+_lib.mhr_pruner_create.argtypes = [_u32, _u32, ctypes.POINTER(_vp)]
+_lib.mhr_pruner_destroy.restype = _i
+_lib.mhr_pruner_destroy.argtypes = [_vp]
+_lib.mhr_pruner_set_params.restype = _i
+_lib.mhr_pruner_set_params.argtypes = [_vp, _vp, _vp]
+_lib.mhr_pruner_get_params.restype = _i
+_lib.mhr_pruner_get_params.argtypes = [_vp, _vp, _vp, _vp]
+_lib.mhr_pruner_workspace_size.restype = _i
+_lib.mhr_pruner_workspace_size.argtypes = [_vp, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_pruner_forward.restype = _i
+_lib.mhr_pruner_forward.argtypes = [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_pruner_train_step.restype = _i
+_lib.mhr_pruner_train_step.argtypes = [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, _i, _vp, _vp, ctypes.c_size_t,
+                                       _vp]
+_lib.mhr_pruner_count.restype = _i
+_lib.mhr_pruner_count.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_pruner_enumerate.restype = _i
+_lib.mhr_pruner_enumerate.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_pruner_select.restype = _i
+_lib.mhr_pruner_select.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp]
 _lib.mhr_status_string.restype = ctypes.c_char_p
 _lib.mhr_status_string.argtypes = [_i]
 _lib.mhr_last_error.restype = ctypes.c_char_p
@@ -291,6 +318,27 @@ class Graph:
         out._keep = (s, d, kt)
         return out
 
+    def topk_pruned(self, src, dst, k, keep, keep_off, k_max: Optional[int] = None,
+                    opts: Optional[QueryOpts] = None, out: Optional[TopK] = None, stream=None) -> TopK:
+        """topk restricted by keep flags (uint8 device tensor) with per-query
+        offsets keep_off (int64 device tensor [>= nq]); see
+        mhr_topk_paths_pruned."""
+        torch = _torch()
+        s, d, kt, nq, o, k_max = self._queries(src, dst, k, k_max, opts)
+        need = self.workspace_bytes(nq, k_max, o)
+        ws = self._ws.get("buf")
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+            self._ws["buf"] = ws
+        if out is None:
+            out = self._new_out(nq, k_max)
+        _check(_lib.mhr_topk_paths_pruned(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
+                                          _ptr(keep), _ptr(keep_off), _ptr(out.paths), _ptr(out.count),
+                                          _ptr(out.total), _ptr(out.status), _ptr(ws), ws.numel(),
+                                          _stream_ptr(stream)), "mhr_topk_paths_pruned")
+        out._keep = (s, d, kt, keep, keep_off)
+        return out
+
     def autotune(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
                  reps: int = 3, stream=None):
         """Fastest (tile_edges, hash_log2) for this batch, by timing each
@@ -326,6 +374,144 @@ class Graph:
         _check(_lib.mhr_edge_weights(self._h, ne, _ptr(U), _ptr(Rr), _ptr(V), _ptr(w), _ptr(e), _ptr(hi),
                                      _ptr(lo), _stream_ptr(stream)), "mhr_edge_weights")
         return w, e, hi, lo
+
+
+@dataclass
+class Candidates:
+    """Frontier candidates of a query batch (device tensors); see
+    mhr_pruner_count / mhr_pruner_enumerate."""
+    src: "object"
+    dst: "object"
+    entry_off: "object"   # int64 [nq + 1]: keep-flag offsets (entries of s's out-row, then t's in-row)
+    cand_off: "object"    # int64 [nq + 1]
+    cand_split: "object"  # int64 [nq]: first second-hop candidate of each query
+    q: "object"           # int32 [n]
+    v: "object"           # int32 [n]
+    r: "object"           # int32 [n]
+    e: "object"           # int64 [n]: keep-flag index
+    n: int
+    n_entries: int
+
+
+def candidates(graph: Graph, src, dst, stream=None) -> Candidates:
+    """Enumerates the first- and second-hop candidates of every query
+    (synchronises once to size the outputs)."""
+    torch = _torch()
+    s, d = _dev_u32(src), _dev_u32(dst)
+    nq = s.numel()
+    eo = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    co = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    _check(_lib.mhr_pruner_count(graph._h, nq, _ptr(s), _ptr(d), _ptr(eo), _ptr(co), _stream_ptr(stream)),
+           "mhr_pruner_count")
+    n = int(co[nq].item())
+    ne = int(eo[nq].item())
+    cs = torch.empty(nq, dtype=torch.int64, device="cuda")
+    cq = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    cv = torch.empty_like(cq)
+    cr = torch.empty_like(cq)
+    ce = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+    _check(_lib.mhr_pruner_enumerate(graph._h, nq, _ptr(s), _ptr(d), _ptr(eo), _ptr(co), _ptr(cs), _ptr(cq),
+                                     _ptr(cv), _ptr(cr), _ptr(ce), _stream_ptr(stream)), "mhr_pruner_enumerate")
+    return Candidates(s, d, eo, co, cs, cq[:n], cv[:n], cr[:n], ce[:n], n, ne)
+
+
+def select(graph: Graph, c: Candidates, scores, keep_permille: int = 100, stream=None):
+    """Keep flags (uint8 [n_entries]) of the top keep_permille / 1000 of each
+    query's candidates per hop by score, and the kept sigmoid mass
+    (float32 [nq, 2])."""
+    torch = _torch()
+    nq = c.src.numel()
+    keep = torch.empty(max(c.n_entries, 1), dtype=torch.uint8, device="cuda")
+    mass = torch.empty((nq, 2), dtype=torch.float32, device="cuda")
+    sc = scores.contiguous()
+    if c.n == 0:
+        sc = torch.zeros(1, dtype=torch.float32, device="cuda")
+    _check(_lib.mhr_pruner_select(graph._h, nq, _ptr(c.src), _ptr(c.dst), _ptr(c.entry_off), _ptr(c.cand_off),
+                                  _ptr(c.cand_split), _ptr(sc), _ptr(c.e) if c.n else _ptr(torch.zeros(1, dtype=torch.int64, device="cuda")),
+                                  int(keep_permille), _ptr(keep), _ptr(mass), _stream_ptr(stream)), "mhr_pruner_select")
+    return keep, mass
+
+
+class Pruner:
+    """The learned frontier pruner's network on the device (see
+    include/mhr.h): FP32 master parameters, bfloat16 MFMA products."""
+
+    def __init__(self, dim: int, hidden: int):
+        h = ctypes.c_void_p()
+        _check(_lib.mhr_pruner_create(int(dim), int(hidden), ctypes.byref(h)), "mhr_pruner_create")
+        self._h = h
+        self.dim, self.hidden = int(dim), int(hidden)
+        self.n_params = int(_lib.mhr_pruner_param_count(self.dim, self.hidden))
+        self._ws = None
+
+    @staticmethod
+    def param_count(dim: int, hidden: int) -> int:
+        return int(_lib.mhr_pruner_param_count(int(dim), int(hidden)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mhr_pruner_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta, stream=None):
+        torch = _torch()
+        t = torch.as_tensor(theta, dtype=torch.float32).cuda().contiguous()
+        assert t.numel() == self.n_params
+        _check(_lib.mhr_pruner_set_params(self._h, _ptr(t), _stream_ptr(stream)), "mhr_pruner_set_params")
+        torch.cuda.synchronize()
+
+    def params(self, stream=None):
+        torch = _torch()
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.mhr_pruner_get_params(self._h, _ptr(t), None, _stream_ptr(stream)), "mhr_pruner_get_params")
+        return t
+
+    def grad(self, stream=None):
+        torch = _torch()
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.mhr_pruner_get_params(self._h, None, _ptr(t), _stream_ptr(stream)), "mhr_pruner_get_params")
+        return t
+
+    def _workspace(self, n):
+        torch = _torch()
+        need = ctypes.c_size_t()
+        _check(_lib.mhr_pruner_workspace_size(self._h, int(n), ctypes.byref(need)), "mhr_pruner_workspace_size")
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def forward(self, graph: Graph, q, src, dst, v, r, stream=None):
+        """Logits (float32 [n]) of samples (q[i], v[i], r[i])."""
+        torch = _torch()
+        q, s, d, v, r = (_dev_u32(x) for x in (q, src, dst, v, r))
+        n = q.numel()
+        out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        ws = self._workspace(n)
+        _check(_lib.mhr_pruner_forward(self._h, graph._h, n, _ptr(q), _ptr(s), _ptr(d), _ptr(v), _ptr(r), _ptr(out),
+                                       _ptr(ws), ws.numel(), _stream_ptr(stream)), "mhr_pruner_forward")
+        return out[:n]
+
+    def train_step(self, graph: Graph, q, src, dst, v, r, label, pos_weight=1.0, lr=1e-3, beta1=0.9,
+                   beta2=0.999, eps=1e-8, update=True, stream=None):
+        """One step (forward, loss, gradient, Adam if update); returns the
+        loss as a device scalar tensor."""
+        torch = _torch()
+        q, s, d, v, r = (_dev_u32(x) for x in (q, src, dst, v, r))
+        y = torch.as_tensor(label, dtype=torch.float32).cuda().contiguous()
+        n = q.numel()
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        ws = self._workspace(n)
+        _check(_lib.mhr_pruner_train_step(self._h, graph._h, n, _ptr(q), _ptr(s), _ptr(d), _ptr(v), _ptr(r), _ptr(y),
+                                          float(pos_weight), float(lr), float(beta1), float(beta2), float(eps),
+                                          1 if update else 0, _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+               "mhr_pruner_train_step")
+        return loss
 
 
 class Plan:
@@ -379,5 +565,5 @@ class Plan:
             pass
 
 
-__all__ = ["Graph", "Plan", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+__all__ = ["Graph", "Plan", "Pruner", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
            "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmhr.so")
-SOURCES = ["mhr_api.hip", "mhr_graph.hip", "mhr_query.hip", "mhr_plan.hip"]
+SOURCES = ["mhr_api.hip", "mhr_graph.hip", "mhr_query.hip", "mhr_plan.hip", "mhr_pruner.hip"]
 ARCH = os.environ.get("MHR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

@@ -1,0 +1,795 @@
+// Learned frontier pruner: a small MLP over f = [X[s], X[t], X[v], Y[r]]
+// that scores the first-hop candidates (s, r1, a) and second-hop candidates
+// (b, r3, t) of a query, trained on labels from the exact search.
+//
+//   h1 = relu(W1 f + b1),  h2 = relu(W2 h1 + b2),  z = w3 . h2 + b3
+//
+// Matrix products run on the matrix cores (v_mfma_f32_16x16x32_bf16:
+// bfloat16 operands, FP32 accumulation); FP32 master weights and Adam.  The
+// operands rounded to bfloat16 are the features, W1, W2, w3, h1, h2 and the
+// back-propagated dz2, dz1; everything else is FP32.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mhr.h"
+#include "mhr_device.h"
+#include "mhr_internal.h"
+
+struct mhr_pruner {
+    uint32_t d = 0, H = 0;
+    size_t np = 0;                      // parameter count
+    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;   // bfloat16 copies
+    uint32_t step = 0;
+};
+
+namespace mhr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmThreads = 256;
+constexpr int kBlock = 512;   // workgroup size of the reduction and candidate kernels
+constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;
+
+// Parameter offsets in the flat vector W1 [H][4d], b1, W2 [H][H], b2, w3, b3.
+struct PLayout {
+    size_t W1, b1, W2, b2, w3, b3, n;
+};
+__host__ __device__ inline PLayout play(uint32_t d, uint32_t H) {
+    PLayout L{};
+    size_t o = 0;
+    L.W1 = o; o += size_t(H) * 4 * d;
+    L.b1 = o; o += H;
+    L.W2 = o; o += size_t(H) * H;
+    L.b2 = o; o += H;
+    L.w3 = o; o += H;
+    L.b3 = o; o += 1;
+    L.n = o;
+    return L;
+}
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {   // round to nearest even (finite x)
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return static_cast<uint16_t>(b >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// A matrix operand: up to four column segments, each a table whose rows may
+// be gathered through an index array.  Element (row, col) lies in segment
+// g = col / seg at table row idx[g][row] (or row), column col - g * seg.
+struct Mat {
+    const void *p[4];
+    const uint32_t *idx[4];
+    uint32_t seg, ld, nseg, f32, vec;   // vec: 8-column chunks may load as one 16-byte vector
+};
+
+__device__ __forceinline__ uint16_t mat_elem(const Mat &M, uint32_t row, uint32_t col) {
+    const uint32_t g = col / M.seg, c = col - g * M.seg;
+    const uint32_t r = M.idx[g] ? M.idx[g][row] : row;
+    const size_t o = static_cast<size_t>(r) * M.ld + c;
+    return M.f32 ? to_bf16(static_cast<const float *>(M.p[g])[o]) : static_cast<const uint16_t *>(M.p[g])[o];
+}
+
+// Eight consecutive columns [col, col + 8) of one row into dst (zero outside
+// [0, nrows) x [0, cend)).
+__device__ __forceinline__ void mat_row8(const Mat &M, uint32_t row, uint32_t col, uint32_t nrows, uint32_t cend,
+                                         uint16_t *dst) {
+    if (row >= nrows) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[e] = 0;
+        return;
+    }
+    if (M.vec && col + 8 <= cend) {
+        const uint32_t g = col / M.seg, c = col - g * M.seg;
+        const uint32_t r = M.idx[g] ? M.idx[g][row] : row;
+        const size_t o = static_cast<size_t>(r) * M.ld + c;
+        if (M.f32) {
+            const float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(M.p[g]) + o);
+            const float4 b = *reinterpret_cast<const float4 *>(static_cast<const float *>(M.p[g]) + o + 4);
+            dst[0] = to_bf16(a.x); dst[1] = to_bf16(a.y); dst[2] = to_bf16(a.z); dst[3] = to_bf16(a.w);
+            dst[4] = to_bf16(b.x); dst[5] = to_bf16(b.y); dst[6] = to_bf16(b.z); dst[7] = to_bf16(b.w);
+        } else {
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.p[g]) + o);
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst[e] = (col + e < cend) ? mat_elem(M, row, col + e) : uint16_t(0);
+}
+
+// C[M][N] = sum_k opA(m, k) opB(k, n) over k in this block's chunk
+// [z * kchunk, (z + 1) * kchunk) of [0, K).
+//   opA(m, k) = TA ? A(k, m) : A(m, k)      opB(k, n) = TB ? B(n, k) : B(k, n)
+// Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA tiles of 16 x 16),
+// 32 k per step staged in LDS with k contiguous.  atomic: add into C (split
+// K; C zeroed beforehand), else store.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Mat A, Mat B, float *C, uint32_t ldc, uint32_t M,
+                                                            uint32_t N, uint32_t K, uint32_t kchunk, int atomic) {
+    __shared__ __align__(16) uint16_t As[BM][BKP];
+    __shared__ __align__(16) uint16_t Bs[BN][BKP];
+    const uint32_t m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const uint32_t kbeg = blockIdx.z * kchunk;
+    const uint32_t kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += BK) {
+        if (!TA) {   // A rows are m, contiguous along k
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            mat_row8(A, m0 + r, k0 + c, M, kend, &As[r][c]);
+        } else {     // A rows are k, contiguous along m
+            const int kk = tid >> 3, c = (tid & 7) * 8;
+            const uint32_t k = k0 + kk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t m = m0 + c + e;
+                As[c + e][kk] = (m < M && k < kend) ? mat_elem(A, k, m) : uint16_t(0);
+            }
+        }
+        if (TB) {    // B rows are n, contiguous along k
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            mat_row8(B, n0 + r, k0 + c, N, kend, &Bs[r][c]);
+        } else {     // B rows are k, contiguous along n
+            const int kk = tid >> 3, c = (tid & 7) * 8;
+            const uint32_t k = k0 + kk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t n = n0 + c + e;
+                Bs[c + e][kk] = (n < N && k < kend) ? mat_elem(B, k, n) : uint16_t(0);
+            }
+        }
+        __syncthreads();
+        // lane (row = lane & 15, group g = lane >> 4) supplies k = 8g .. 8g + 7
+        const int row = lane & 15, g = lane >> 4;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + row][8 * g]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + row][8 * g]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // D[row][col] of a 16 x 16 tile sits in lane col + 16 * (row / 4), element row % 4
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+                const uint32_t n = n0 + wn + 16 * j + (lane & 15);
+                if (m < M && n < N) {
+                    float *c = C + static_cast<size_t>(m) * ldc + n;
+                    if (atomic) atomicAdd(c, acc[i][j][e]); else *c = acc[i][j][e];
+                }
+            }
+}
+
+// ---- elementwise and reduction kernels -------------------------------------
+
+__global__ void fill_kernel(float *p, size_t n, float v) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+__global__ void to_bf16_kernel(const float *src, uint16_t *dst, size_t n) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        dst[i] = to_bf16(src[i]);
+}
+
+// per-sample (s, t) of the sample's query
+__global__ void expand_query_kernel(const uint32_t *q, const uint32_t *src, const uint32_t *dst, uint32_t *s,
+                                    uint32_t *t, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        s[i] = src[q[i]];
+        t[i] = dst[q[i]];
+    }
+}
+
+// h = bfloat16(relu(Z + b)), row-major [n][H]
+__global__ void bias_relu_kernel(const float *Z, const float *b, uint16_t *h, size_t total, uint32_t H) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x)
+        h[i] = to_bf16(fmaxf(Z[i] + b[i % H], 0.0f));
+}
+
+// z_i = w3 . h2_i + b3, one wave per row
+__global__ void output_kernel(const uint16_t *h2, const uint16_t *w3b, const float *b3, float *z, uint32_t n,
+                              uint32_t H) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t row = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (row >= n) return;
+    float acc = 0.0f;
+    for (uint32_t j = lane; j < H; j += kWave)
+        acc += from_bf16(h2[static_cast<size_t>(row) * H + j]) * from_bf16(w3b[j]);
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (lane == 0) z[row] = acc + b3[0];
+}
+
+// dz_i = (w y (p - 1) + (1 - y) p) / n and the mean loss (added into *loss)
+__global__ void bce_kernel(const float *z, const float *y, uint32_t n, float w_pos, float *dz, float *loss) {
+    __shared__ float red[kBlock / kWave];
+    float part = 0.0f;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float zi = z[i], yi = y[i];
+        const float e = expf(-fabsf(zi));
+        const float l1p = log1pf(e);
+        const float p = zi >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+        const float logp = fminf(zi, 0.0f) - l1p;        // log sigmoid(z)
+        const float log1mp = fminf(-zi, 0.0f) - l1p;     // log sigmoid(-z)
+        dz[i] = (w_pos * yi * (p - 1.0f) + (1.0f - yi) * p) / static_cast<float>(n);
+        part -= (w_pos * yi * logp + (1.0f - yi) * log1mp);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) s += red[w];
+        if (loss) atomicAdd(loss, s / static_cast<float>(n));
+    }
+}
+
+// out[j] += sum_i scale_i * M[i][j] (scale = nullptr: 1) over a chunk of rows
+__global__ void colsum_kernel(const uint16_t *Mv, const float *scale, float *out, uint32_t n, uint32_t H,
+                              uint32_t rows_per_block) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= H) return;
+    const uint32_t r0 = blockIdx.y * rows_per_block, r1 = min(n, r0 + rows_per_block);
+    float acc = 0.0f;
+    for (uint32_t i = r0; i < r1; ++i) acc += (scale ? scale[i] : 1.0f) * from_bf16(Mv[static_cast<size_t>(i) * H + j]);
+    atomicAdd(&out[j], acc);
+}
+
+__global__ void sum_kernel(const float *x, uint32_t n, float *out) {
+    float part = 0.0f;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) part += x[i];
+    for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, part);
+}
+
+// dz2 = bfloat16(dz_i w3_j [h2_ij > 0]), in place over h2
+__global__ void dz2_kernel(const float *dz, const uint16_t *w3b, uint16_t *h2, size_t total, uint32_t H) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x) {
+        const float h = from_bf16(h2[i]);
+        h2[i] = h > 0.0f ? to_bf16(dz[i / H] * from_bf16(w3b[i % H])) : uint16_t(0);
+    }
+}
+
+// dz1 = bfloat16(dH1 [h1 > 0]), in place over h1
+__global__ void dz1_kernel(const float *dH1, uint16_t *h1, size_t total) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x) {
+        const float h = from_bf16(h1[i]);
+        h1[i] = h > 0.0f ? to_bf16(dH1[i]) : uint16_t(0);
+    }
+}
+
+__global__ void adam_kernel(float *theta, const float *g, float *m, float *v, size_t n, float lr, float b1, float b2,
+                            float eps, float bc1, float bc2) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        theta[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+// ---- host helpers ------------------------------------------------------------
+
+inline uint32_t grid_for(size_t n, uint32_t block = 256) {
+    size_t g = (n + block - 1) / block;
+    return static_cast<uint32_t>(g < 1 ? 1 : (g > 65535 ? 65535 : g));
+}
+
+Mat plain(const void *p, uint32_t cols, bool f32 = false) {
+    Mat M{};
+    M.p[0] = p;
+    M.seg = cols;
+    M.ld = cols;
+    M.nseg = 1;
+    M.f32 = f32 ? 1u : 0u;
+    M.vec = (cols % 8 == 0) ? 1u : 0u;
+    return M;
+}
+
+// The feature rows [X[s_i], X[t_i], X[v_i], Y[r_i]] of n samples.
+Mat features(const mhr_graph *g, const uint32_t *s, const uint32_t *t, const uint32_t *v, const uint32_t *r) {
+    Mat F{};
+    F.p[0] = g->X; F.idx[0] = s;
+    F.p[1] = g->X; F.idx[1] = t;
+    F.p[2] = g->X; F.idx[2] = v;
+    F.p[3] = g->Y; F.idx[3] = r;
+    F.seg = g->dim;
+    F.ld = g->dim;
+    F.nseg = 4;
+    F.f32 = g->dtype == MHR_DTYPE_F32 ? 1u : 0u;
+    F.vec = (g->dim % 8 == 0) ? 1u : 0u;
+    return F;
+}
+
+template <bool TA, bool TB>
+hipError_t gemm(const Mat &A, const Mat &B, float *C, uint32_t ldc, uint32_t M, uint32_t N, uint32_t K,
+                uint32_t splits, hipStream_t st) {
+    if (M == 0 || N == 0) return hipSuccess;
+    if (splits < 1) splits = 1;
+    uint32_t kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    if (kchunk == 0) kchunk = BK;
+    splits = (K + kchunk - 1) / kchunk;
+    if (splits == 0) splits = 1;
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, splits);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB>), grid, dim3(kGemmThreads), 0, st, A, B, C, ldc, M, N, K, kchunk,
+                       splits > 1 ? 1 : 0);
+    return hipGetLastError();
+}
+
+// split count for a reduction over K samples into an M x N output
+uint32_t splits_for(uint32_t M, uint32_t N, uint32_t K) {
+    const uint32_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    uint32_t s = (1024 + tiles - 1) / tiles;
+    const uint32_t kmax = (K + 255) / 256;   // at least 256 samples per split
+    if (s > kmax) s = kmax;
+    return s < 1 ? 1 : s;
+}
+
+struct PWs {
+    size_t Z, h1, h2, z, dz, s, t, total;
+};
+PWs pws_layout(uint32_t n, uint32_t H) {
+    PWs L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) & ~size_t(255); return r; };
+    L.Z = take(size_t(n) * H * 4);
+    L.h1 = take(size_t(n) * H * 2);
+    L.h2 = take(size_t(n) * H * 2);
+    L.z = take(size_t(n) * 4);
+    L.dz = take(size_t(n) * 4);
+    L.s = take(size_t(n) * 4);
+    L.t = take(size_t(n) * 4);
+    L.total = o;
+    return L;
+}
+
+hipError_t refresh_bf16(mhr_pruner *p, hipStream_t st) {
+    const PLayout L = play(p->d, p->H);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(L.b1 - L.W1)), dim3(256), 0, st, p->theta + L.W1, p->W1b,
+                       L.b1 - L.W1);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(L.b2 - L.W2)), dim3(256), 0, st, p->theta + L.W2, p->W2b,
+                       L.b2 - L.W2);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(1), dim3(256), 0, st, p->theta + L.w3, p->w3b, size_t(p->H));
+    return hipGetLastError();
+}
+
+// forward pass over n samples; leaves Z1 / h1 / h2 / z in the workspace
+mhr_status forward_impl(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q, const uint32_t *src,
+                        const uint32_t *dst, const uint32_t *v, const uint32_t *r, char *ws, hipStream_t st) {
+    const PWs W = pws_layout(n, p->H);
+    const PLayout L = play(p->d, p->H);
+    const uint32_t H = p->H, d = p->d;
+    float *Z = reinterpret_cast<float *>(ws + W.Z);
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(ws + W.h1), *h2 = reinterpret_cast<uint16_t *>(ws + W.h2);
+    uint32_t *s = reinterpret_cast<uint32_t *>(ws + W.s), *t = reinterpret_cast<uint32_t *>(ws + W.t);
+    hipLaunchKernelGGL(expand_query_kernel, dim3(grid_for(n)), dim3(256), 0, st, q, src, dst, s, t, n);
+    const Mat F = features(g, s, t, v, r);
+    MHR_HIP_TRY((gemm<false, true>(F, plain(p->W1b, 4 * d), Z, H, n, H, 4 * d, 1, st)));
+    hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b1, h1,
+                       size_t(n) * H, H);
+    MHR_HIP_TRY((gemm<false, true>(plain(h1, H), plain(p->W2b, H), Z, H, n, H, H, 1, st)));
+    hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b2, h2,
+                       size_t(n) * H, H);
+    hipLaunchKernelGGL(output_kernel, dim3((n + 3) / 4), dim3(256), 0, st, h2, p->w3b, p->theta + L.b3,
+                       reinterpret_cast<float *>(ws + W.z), n, H);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+// ---- candidates ----------------------------------------------------------------
+
+// Per query: entries (deg+(s) + deg-(t)) and candidates (relations over both
+// rows); then exclusive offsets over the queries, totals at [nq].
+__global__ void cand_count_kernel(const uint32_t *out_rp, const uint32_t *out_mask, const uint32_t *in_rp,
+                                  const uint32_t *in_mask, uint32_t n, const uint32_t *src, const uint32_t *dst,
+                                  uint64_t *entries, uint64_t *cands) {
+    __shared__ uint64_t red[kBlock / kWave];
+    const uint32_t q = blockIdx.x;
+    const uint32_t s = src[q], t = dst[q];
+    uint64_t ne = 0, nc = 0;
+    if (s < n && t < n) {
+        const uint32_t b0 = out_rp[s], b1 = out_rp[s + 1], c0 = in_rp[t], c1 = in_rp[t + 1];
+        ne = (b1 - b0) + (c1 - c0);
+        uint64_t part = 0;
+        for (uint32_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) part += __popc(out_mask[i]);
+        for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) part += __popc(in_mask[i]);
+        for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        if (lane == 0) red[wave] = part;
+        __syncthreads();
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) nc += red[w];
+    }
+    if (threadIdx.x == 0) {
+        entries[q] = ne;
+        cands[q] = nc;
+    }
+}
+
+// in-place exclusive scan of a[0..n) with the total at a[n] (one workgroup)
+__global__ void excl_scan_kernel(uint64_t *a, uint32_t n) {
+    __shared__ uint64_t red[kBlock / kWave];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t x = i < n ? a[i] : 0;
+        uint64_t v = x;
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t y = __shfl_up(v, off, kWave);
+            if (lane >= off) v += y;
+        }
+        if (lane == kWave - 1) red[wave] = v;
+        __syncthreads();
+        uint64_t before = 0, tot = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) {
+            if (w < wave) before += red[w];
+            tot += red[w];
+        }
+        const uint64_t c = carry;
+        if (i < n) a[i] = c + before + v - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a[n] = carry;
+}
+
+// One workgroup per query: first-hop candidates (entries of s's out-row,
+// each relation of the entry's mask in ascending order), then second-hop
+// candidates (entries of t's in-row).
+__global__ void cand_fill_kernel(const uint32_t *out_rp, const uint32_t *out_col, const uint32_t *out_mask,
+                                 const uint32_t *in_rp, const uint32_t *in_col, const uint32_t *in_mask, uint32_t n,
+                                 const uint32_t *src, const uint32_t *dst, const uint64_t *entry_off,
+                                 const uint64_t *cand_off, uint64_t *cand_split, uint32_t *cq, uint32_t *cv,
+                                 uint32_t *cr, uint64_t *ce) {
+    __shared__ uint64_t red[kBlock / kWave];
+    __shared__ uint64_t carry;
+    const uint32_t q = blockIdx.x;
+    const uint32_t s = src[q], t = dst[q];
+    if (threadIdx.x == 0) carry = cand_off[q];
+    __syncthreads();
+    if (!(s < n && t < n)) {
+        if (threadIdx.x == 0) cand_split[q] = cand_off[q];
+        return;
+    }
+    const uint32_t degs = out_rp[s + 1] - out_rp[s];
+    for (int hop = 0; hop < 2; ++hop) {
+        const uint32_t beg = hop ? in_rp[t] : out_rp[s], end = hop ? in_rp[t + 1] : out_rp[s + 1];
+        const uint32_t *col = hop ? in_col : out_col, *mask = hop ? in_mask : out_mask;
+        if (hop == 1 && threadIdx.x == 0) cand_split[q] = carry;
+        __syncthreads();
+        for (uint32_t base = beg; base < end; base += blockDim.x) {
+            const uint32_t i = base + threadIdx.x;
+            const uint32_t m = i < end ? mask[i] : 0u;
+            const uint64_t x = __popc(m);
+            uint64_t v = x;
+            const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint64_t y = __shfl_up(v, off, kWave);
+                if (lane >= off) v += y;
+            }
+            if (lane == kWave - 1) red[wave] = v;
+            __syncthreads();
+            uint64_t before = 0, tot = 0;
+            for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) {
+                if (w < wave) before += red[w];
+                tot += red[w];
+            }
+            const uint64_t c = carry;
+            if (i < end) {
+                uint64_t o = c + before + v - x;
+                const uint64_t e = entry_off[q] + (hop ? degs : 0u) + (i - beg);
+                for (uint32_t mm = m; mm; mm &= mm - 1) {
+                    cq[o] = q;
+                    cv[o] = col[i];
+                    cr[o] = static_cast<uint32_t>(__ffs(mm) - 1);
+                    ce[o] = e;
+                    ++o;
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) carry = c + tot;
+            __syncthreads();
+        }
+    }
+}
+
+// order-preserving key of a float score (NaN lowest)
+__device__ __forceinline__ uint32_t score_key(float x) {
+    if (x != x) return 0u;
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <class T>
+__device__ inline T wg_sum(T v, T *red) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    T s = 0;
+    for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) s += red[w];
+    return s;
+}
+
+// One workgroup per (query, hop): keep the ceil(n * permille / 1000)
+// highest-scoring candidates (all ties with the lowest kept score too); an
+// entry is kept when any of its candidates is.  mass[2q + hop] = sum of
+// sigmoid(score) over kept candidates / over all (1 when n = 0).
+__global__ void select_kernel(const uint32_t *out_rp, const uint32_t *in_rp, uint32_t n, const uint32_t *src,
+                              const uint32_t *dst, const uint64_t *entry_off, const uint64_t *cand_off,
+                              const uint64_t *cand_split, const float *score, const uint64_t *ce, uint32_t permille,
+                              uint8_t *keep, float *mass) {
+    __shared__ uint64_t red64[kBlock / kWave];
+    __shared__ float redf[kBlock / kWave];
+    const uint32_t q = blockIdx.x, hop = blockIdx.y;
+    const uint32_t s = src[q], t = dst[q];
+    if (!(s < n && t < n)) {
+        if (threadIdx.x == 0 && mass) mass[2 * q + hop] = 1.0f;
+        return;
+    }
+    const uint32_t degs = out_rp[s + 1] - out_rp[s], degt = in_rp[t + 1] - in_rp[t];
+    const uint64_t e0 = entry_off[q] + (hop ? degs : 0u), ne = hop ? degt : degs;
+    for (uint64_t i = threadIdx.x; i < ne; i += blockDim.x) keep[e0 + i] = 0;
+    const uint64_t c0 = hop ? cand_split[q] : cand_off[q], c1 = hop ? cand_off[q + 1] : cand_split[q];
+    const uint64_t nc = c1 - c0;
+    __syncthreads();
+    if (nc == 0) {
+        if (threadIdx.x == 0 && mass) mass[2 * q + hop] = 1.0f;
+        return;
+    }
+    const uint64_t m = (nc * permille + 999) / 1000 > 0 ? (nc * permille + 999) / 1000 : 1;
+    // the m-th largest key: the largest T with #{key >= T} >= m, bit by bit
+    uint32_t T = 0;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = T | (1u << bit);
+        uint64_t cnt = 0;
+        for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) cnt += score_key(score[i]) >= cand ? 1u : 0u;
+        cnt = wg_sum<uint64_t>(cnt, red64);
+        if (cnt >= m) T = cand;
+    }
+    __syncthreads();
+    float pk = 0.0f, pa = 0.0f;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+        const float x = score[i];
+        const float p = (x != x) ? 0.0f : 1.0f / (1.0f + expf(-x));
+        pa += p;
+        if (score_key(x) >= T) {
+            keep[ce[i]] = 1;
+            pk += p;
+        }
+    }
+    pk = wg_sum<float>(pk, redf);
+    pa = wg_sum<float>(pa, redf);
+    if (threadIdx.x == 0 && mass) mass[2 * q + hop] = pa > 0.0f ? pk / pa : 1.0f;
+}
+
+}  // namespace
+}  // namespace mhr
+
+using namespace mhr;
+
+extern "C" size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden) { return play(dim, hidden).n; }
+
+extern "C" mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_pruner **out) {
+    MHR_ARG_CHECK(out != nullptr, "mhr_pruner_create: null output");
+    MHR_ARG_CHECK(dim >= 8 && dim <= 512 && dim % 8 == 0, "mhr_pruner_create: dim must be a multiple of 8 in [8, 512]");
+    MHR_ARG_CHECK(hidden >= 16 && hidden <= 4096 && hidden % 16 == 0,
+                  "mhr_pruner_create: hidden must be a multiple of 16 in [16, 4096]");
+    mhr_pruner *p = new (std::nothrow) mhr_pruner;
+    if (!p) {
+        set_error("mhr_pruner_create: out of host memory");
+        return MHR_ERR_OUT_OF_MEMORY;
+    }
+    p->d = dim;
+    p->H = hidden;
+    const PLayout L = play(dim, hidden);
+    p->np = L.n;
+    bool ok = hipMalloc(&p->theta, L.n * 4) == hipSuccess && hipMalloc(&p->grad, L.n * 4) == hipSuccess &&
+              hipMalloc(&p->m, L.n * 4) == hipSuccess && hipMalloc(&p->v, L.n * 4) == hipSuccess &&
+              hipMalloc(&p->W1b, (L.b1 - L.W1) * 2) == hipSuccess &&
+              hipMalloc(&p->W2b, (L.b2 - L.W2) * 2) == hipSuccess && hipMalloc(&p->w3b, size_t(hidden) * 2) == hipSuccess;
+    if (!ok) {
+        mhr_pruner_destroy(p);
+        set_error("mhr_pruner_create: device allocation failed");
+        return MHR_ERR_OUT_OF_MEMORY;
+    }
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->theta, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->grad, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->m, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->v, L.n, 0.0f);
+    if (refresh_bf16(p, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        mhr_pruner_destroy(p);
+        set_error("mhr_pruner_create: initialisation failed");
+        return MHR_ERR_DEVICE;
+    }
+    *out = p;
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_destroy(mhr_pruner *p) {
+    if (!p) return MHR_OK;
+    (void)hipFree(p->theta);
+    (void)hipFree(p->grad);
+    (void)hipFree(p->m);
+    (void)hipFree(p->v);
+    (void)hipFree(p->W1b);
+    (void)hipFree(p->W2b);
+    (void)hipFree(p->w3b);
+    delete p;
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_set_params(mhr_pruner *p, const float *params, void *stream) {
+    MHR_ARG_CHECK(p && params, "mhr_pruner_set_params: null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MHR_HIP_TRY(hipMemcpyAsync(p->theta, params, p->np * 4, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(p->np)), dim3(256), 0, st, p->m, p->np, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(p->np)), dim3(256), 0, st, p->v, p->np, 0.0f);
+    p->step = 0;
+    MHR_HIP_TRY(refresh_bf16(p, st));
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_get_params(const mhr_pruner *p, float *params, float *grad, void *stream) {
+    MHR_ARG_CHECK(p != nullptr, "mhr_pruner_get_params: null pruner");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (params) MHR_HIP_TRY(hipMemcpyAsync(params, p->theta, p->np * 4, hipMemcpyDeviceToDevice, st));
+    if (grad) MHR_HIP_TRY(hipMemcpyAsync(grad, p->grad, p->np * 4, hipMemcpyDeviceToDevice, st));
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_workspace_size(const mhr_pruner *p, uint32_t n, size_t *bytes) {
+    MHR_ARG_CHECK(p && bytes, "mhr_pruner_workspace_size: null argument");
+    *bytes = pws_layout(n, p->H).total;
+    return MHR_OK;
+}
+
+static mhr_status check_model(const mhr_pruner *p, const mhr_graph *g, uint32_t n, size_t ws_bytes) {
+    MHR_ARG_CHECK(p && g, "pruner: null argument");
+    if (!g->X) {
+        set_error("embeddings not set");
+        return MHR_ERR_NO_EMBEDDINGS;
+    }
+    MHR_ARG_CHECK(g->dim == p->d, "pruner: the graph's embedding dimension differs from the pruner's");
+    if (ws_bytes < pws_layout(n, p->H).total) {
+        set_error("pruner workspace too small: need " + std::to_string(pws_layout(n, p->H).total) + " bytes");
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q,
+                                         const uint32_t *src, const uint32_t *dst, const uint32_t *v,
+                                         const uint32_t *r, float *logits, void *ws, size_t ws_bytes, void *stream) {
+    mhr_status rc = check_model(p, g, n, ws_bytes);
+    if (rc != MHR_OK) return rc;
+    if (n == 0) return MHR_OK;
+    MHR_ARG_CHECK(q && src && dst && v && r && logits && ws, "mhr_pruner_forward: null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    rc = forward_impl(p, g, n, q, src, dst, v, r, w, st);
+    if (rc != MHR_OK) return rc;
+    MHR_HIP_TRY(hipMemcpyAsync(logits, w + pws_layout(n, p->H).z, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q,
+                                            const uint32_t *src, const uint32_t *dst, const uint32_t *v,
+                                            const uint32_t *r, const float *label, float pos_weight, float lr,
+                                            float beta1, float beta2, float eps, int update, float *loss,
+                                            void *ws, size_t ws_bytes, void *stream) {
+    mhr_status rc = check_model(p, g, n, ws_bytes);
+    if (rc != MHR_OK) return rc;
+    MHR_ARG_CHECK(n >= 1 && q && src && dst && v && r && label && ws, "mhr_pruner_train_step: null pointer or n = 0");
+    MHR_ARG_CHECK(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f,
+                  "mhr_pruner_train_step: bad Adam constants");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    rc = forward_impl(p, g, n, q, src, dst, v, r, w, st);
+    if (rc != MHR_OK) return rc;
+    const PWs W = pws_layout(n, p->H);
+    const PLayout L = play(p->d, p->H);
+    const uint32_t H = p->H, d = p->d;
+    float *Z = reinterpret_cast<float *>(w + W.Z);
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(w + W.h1), *h2 = reinterpret_cast<uint16_t *>(w + W.h2);
+    float *z = reinterpret_cast<float *>(w + W.z), *dz = reinterpret_cast<float *>(w + W.dz);
+    uint32_t *s = reinterpret_cast<uint32_t *>(w + W.s), *t = reinterpret_cast<uint32_t *>(w + W.t);
+    const size_t nh = size_t(n) * H;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(p->np)), dim3(256), 0, st, p->grad, p->np, 0.0f);
+    if (loss) hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, loss, size_t(1), 0.0f);
+    hipLaunchKernelGGL(bce_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, z, label, n, pos_weight, dz, loss);
+    // output layer
+    const uint32_t rows_blk = 256;
+    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h2, dz,
+                       p->grad + L.w3, n, H, rows_blk);
+    hipLaunchKernelGGL(sum_kernel, dim3(grid_for(n)), dim3(256), 0, st, dz, n, p->grad + L.b3);
+    // second layer: dz2 over h2, then dW2 = dz2^T h1, db2, dH1 = dz2 W2
+    hipLaunchKernelGGL(dz2_kernel, dim3(grid_for(nh)), dim3(256), 0, st, dz, p->w3b, h2, nh, H);
+    MHR_HIP_TRY((gemm<true, false>(plain(h2, H), plain(h1, H), p->grad + L.W2, H, H, H, n, splits_for(H, H, n), st)));
+    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h2,
+                       nullptr, p->grad + L.b2, n, H, rows_blk);
+    MHR_HIP_TRY((gemm<false, false>(plain(h2, H), plain(p->W2b, H), Z, H, n, H, H, 1, st)));
+    // first layer: dz1 over h1, then dW1 = dz1^T F, db1
+    hipLaunchKernelGGL(dz1_kernel, dim3(grid_for(nh)), dim3(256), 0, st, Z, h1, nh);
+    const Mat F = features(g, s, t, v, r);
+    MHR_HIP_TRY((gemm<true, false>(plain(h1, H), F, p->grad + L.W1, 4 * d, H, 4 * d, n, splits_for(H, 4 * d, n), st)));
+    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h1,
+                       nullptr, p->grad + L.b1, n, H, rows_blk);
+    if (update) {
+        p->step += 1;
+        const float bc1 = 1.0f - powf(beta1, static_cast<float>(p->step));
+        const float bc2 = 1.0f - powf(beta2, static_cast<float>(p->step));
+        hipLaunchKernelGGL(adam_kernel, dim3(grid_for(p->np)), dim3(256), 0, st, p->theta, p->grad, p->m, p->v, p->np,
+                           lr, beta1, beta2, eps, bc1, bc2);
+        MHR_HIP_TRY(refresh_bf16(p, st));
+    }
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_count(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                       uint64_t *entry_off, uint64_t *cand_off, void *stream) {
+    MHR_ARG_CHECK(g && src && dst && entry_off && cand_off, "mhr_pruner_count: null argument");
+    MHR_ARG_CHECK(nq >= 1, "mhr_pruner_count: nq must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(cand_count_kernel, dim3(nq), dim3(kBlock), 0, st, g->out.row_ptr, g->out.rmask, g->in.row_ptr,
+                       g->in.rmask, g->n, src, dst, entry_off, cand_off);
+    hipLaunchKernelGGL(excl_scan_kernel, dim3(1), dim3(kBlock), 0, st, entry_off, nq);
+    hipLaunchKernelGGL(excl_scan_kernel, dim3(1), dim3(kBlock), 0, st, cand_off, nq);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_enumerate(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                           const uint64_t *entry_off, const uint64_t *cand_off, uint64_t *cand_split,
+                                           uint32_t *cand_q, uint32_t *cand_v, uint32_t *cand_r, uint64_t *cand_e,
+                                           void *stream) {
+    MHR_ARG_CHECK(g && src && dst && entry_off && cand_off && cand_split && cand_q && cand_v && cand_r && cand_e,
+                  "mhr_pruner_enumerate: null argument");
+    MHR_ARG_CHECK(nq >= 1, "mhr_pruner_enumerate: nq must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(cand_fill_kernel, dim3(nq), dim3(kBlock), 0, st, g->out.row_ptr, g->out.col, g->out.rmask,
+                       g->in.row_ptr, g->in.col, g->in.rmask, g->n, src, dst, entry_off, cand_off, cand_split, cand_q,
+                       cand_v, cand_r, cand_e);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_select(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                        const uint64_t *entry_off, const uint64_t *cand_off,
+                                        const uint64_t *cand_split, const float *score, const uint64_t *cand_e,
+                                        uint32_t keep_permille, uint8_t *keep, float *mass, void *stream) {
+    MHR_ARG_CHECK(g && src && dst && entry_off && cand_off && cand_split && score && cand_e && keep,
+                  "mhr_pruner_select: null argument");
+    MHR_ARG_CHECK(nq >= 1 && keep_permille >= 1 && keep_permille <= 1000,
+                  "mhr_pruner_select: nq >= 1 and keep_permille in [1, 1000]");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(select_kernel, dim3(nq, 2), dim3(kBlock), 0, st, g->out.row_ptr, g->in.row_ptr, g->n, src, dst,
+                       entry_off, cand_off, cand_split, score, cand_e, keep_permille, keep, mass);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}

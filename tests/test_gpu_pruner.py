@@ -1,0 +1,203 @@
+"""GPU parity of the learned pruner's kernels against the FP64 oracle
+(oracle/pruner.py, evaluated with bfloat16 operands where the kernels round
+them), of candidate enumeration and selection against plain numpy, and of
+the pruned search against the pure-Python oracle restricted to the kept
+first and last pairs."""
+
+import numpy as np
+import pytest
+
+import kgsynth
+import oracle
+from oracle import pruner as OP
+from oracle import pyoracle
+from tests.parity import compare, gpu_graph, say, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2406_07727_amd  # noqa: F401
+
+
+def _setup(name, H, seed, n=700):
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload(name)
+    g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y, cfg.emb.dtype)
+    dim = cfg.emb.d
+    rng = np.random.Generator(np.random.PCG64(seed))
+    theta = rng.normal(0.0, 1.0, OP.param_count(dim, H))
+    W1, b1, W2, b2, w3, b3 = OP.unpack(theta, dim, H)
+    W1 *= 2.0 / np.sqrt(4 * dim)
+    W2 *= 2.0 / np.sqrt(H)
+    w3 *= 1.0 / np.sqrt(H)
+    b1 *= 0.1
+    b2 *= 0.1
+    theta = theta.astype(np.float32).astype(np.float64)      # what the GPU holds
+    q = rng.integers(0, len(s), n).astype(np.uint32)
+    v = rng.integers(0, cfg.graph.n, n).astype(np.uint32)
+    rr = rng.integers(0, cfg.graph.R, n).astype(np.uint32)
+    y = (rng.random(n) < 0.3).astype(np.float64)
+    Xf = oracle.as_f32_table(X, cfg.emb.dtype)
+    Yf = oracle.as_f32_table(Y, cfg.emb.dtype)
+    F = OP.features(Xf, Yf, s[q], d[q], v, rr)
+    return cfg, g, dim, theta, (s, d), (q, v, rr, y), F
+
+
+@pytest.mark.parametrize("name,H", [("hub_tiny", 32), ("hub_r32_bf16", 64), ("hub_tiny_bf16", 48)])
+def test_forward_matches_oracle(name, H):
+    import paper_2406_07727_amd as mhr
+    cfg, g, dim, theta, (s, d), (q, v, rr, y), F = _setup(name, H, 5)
+    say(f"case pruner forward {name} H={H}")
+    pr = mhr.Pruner(dim, H)
+    pr.set_params(theta)
+    z = pr.forward(g, q, s, d, v, rr).cpu().numpy().astype(np.float64)
+    z64, _ = OP.forward(theta, F, dim, H, bf16=True)
+    err = np.abs(z - z64)
+    # FP32 accumulation of exact bfloat16 products, plus rare one-ulp flips
+    # of a rounded activation: far below the spread of the logits
+    assert np.max(err) <= 2e-3 * (1 + np.max(np.abs(z64))), err.max()
+    assert np.median(err) <= 1e-5 * (1 + np.max(np.abs(z64)))
+    assert np.std(z64) > 0.05
+
+
+@pytest.mark.parametrize("name,H", [("hub_tiny", 32), ("hub_r32_bf16", 64)])
+def test_gradient_and_loss_match_oracle(name, H):
+    import torch
+    import paper_2406_07727_amd as mhr
+    cfg, g, dim, theta, (s, d), (q, v, rr, y), F = _setup(name, H, 6)
+    say(f"case pruner gradient {name} H={H}")
+    pr = mhr.Pruner(dim, H)
+    pr.set_params(theta)
+    w = 2.5
+    loss = pr.train_step(g, q, s, d, v, rr, y, pos_weight=w, update=False)
+    torch.cuda.synchronize()
+    gg = pr.grad().cpu().numpy().astype(np.float64)
+    z64, cache = OP.forward(theta, F, dim, H, bf16=True)
+    go = OP.backward(theta, cache, OP.bce_grad(z64, y, w), dim, H, bf16=True)
+    assert abs(float(loss.item()) - OP.bce_loss(z64, y, w)) <= 1e-4 * OP.bce_loss(z64, y, w)
+    for blk_g, blk_o, nm in zip(OP.unpack(gg, dim, H), OP.unpack(go, dim, H), ["W1", "b1", "W2", "b2", "w3", "b3"]):
+        rel = np.linalg.norm(blk_g - blk_o) / max(np.linalg.norm(blk_o), 1e-30)
+        assert rel <= 5e-3, (nm, rel)
+        assert np.linalg.norm(blk_o) > 0, nm
+    # parameters unchanged without an update
+    assert np.array_equal(pr.params().cpu().numpy(), theta.astype(np.float32))
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    import paper_2406_07727_amd as mhr
+    cfg, g, dim, theta, (s, d), (q, v, rr, y), F = _setup("hub_tiny", 32, 7)
+    say("case pruner adam")
+    pr = mhr.Pruner(dim, 32)
+    pr.set_params(theta)
+    th = theta.copy()
+    m = np.zeros_like(th)
+    vv = np.zeros_like(th)
+    for step in (1, 2, 3):
+        pr.train_step(g, q, s, d, v, rr, y, pos_weight=1.5, lr=1e-2, update=True)
+        torch.cuda.synchronize()
+        grad = pr.grad().cpu().numpy().astype(np.float64)
+        th, m, vv = OP.adam_step(th, grad, m, vv, step, 1e-2)
+        got = pr.params().cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - th)) <= 1e-5 * (1 + np.max(np.abs(th))), step
+        th = got                   # continue from the device's FP32 state
+
+
+def test_candidates_and_selection():
+    import torch
+    import paper_2406_07727_amd as mhr
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    n = cfg.graph.n
+    say("case pruner candidates and selection")
+    g = gpu_graph(n, cfg.graph.R, h, r, t, X, Y)
+    src = np.concatenate([s, [n + 5]]).astype(np.uint32)    # one bad id: no candidates
+    dst = np.concatenate([d, [0]]).astype(np.uint32)
+    c = mhr.candidates(g, src, dst)
+    orp, ocol, omask = (x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=False))
+    irp, icol, imask = (x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=True))
+    cq, cv, cr, ce = (x.cpu().numpy() for x in (c.q, c.v, c.r, c.e))
+    eo, co, cs = (x.cpu().numpy() for x in (c.entry_off, c.cand_off, c.cand_split))
+    rng = np.random.Generator(np.random.PCG64(3))
+    scores = rng.normal(0.0, 1.0, c.n).astype(np.float32)
+    scores[::7] = scores[3]                                  # ties
+    keep, mass = mhr.select(g, c, torch.from_numpy(scores).cuda(), 100)
+    keep = keep.cpu().numpy()
+    mass = mass.cpu().numpy()
+    o = 0
+    for qi in range(len(src)):
+        assert eo[qi] == (0 if qi == 0 else eo[qi])
+        if src[qi] >= n:
+            assert co[qi + 1] == co[qi] and eo[qi + 1] == eo[qi]
+            continue
+        rows = []
+        for hop, (rp, col, msk, x) in enumerate(((orp, ocol, omask, src[qi]), (irp, icol, imask, dst[qi]))):
+            ents = []
+            base = eo[qi] + (0 if hop == 0 else orp[src[qi] + 1] - orp[src[qi]])
+            for j, pos in enumerate(range(rp[x], rp[x + 1])):
+                for rel in range(32):
+                    if msk[pos] >> rel & 1:
+                        ents.append((qi, col[pos], rel, base + j))
+            rows.append(ents)
+        exp = rows[0] + rows[1]
+        got = list(zip(cq[o:o + len(exp)], cv[o:o + len(exp)], cr[o:o + len(exp)], ce[o:o + len(exp)]))
+        assert co[qi] == o and cs[qi] == o + len(rows[0])
+        assert [tuple(int(z) for z in e) for e in got] == [tuple(int(z) for z in e) for e in exp]
+        for hop, ents in enumerate(rows):
+            lo = o if hop == 0 else o + len(rows[0])
+            sc = scores[lo:lo + len(ents)]
+            kept = set(int(ents[i][3]) for i in OP.keep_top_fraction(sc, 100))
+            allent = set(int(e[3]) for e in ents)
+            for e in allent:
+                assert bool(keep[e]) == (e in kept)
+            p = 1.0 / (1.0 + np.exp(-sc.astype(np.float64)))
+            km = p[OP.keep_top_fraction(sc, 100)].sum() / p.sum() if len(ents) else 1.0
+            assert abs(mass[qi, hop] - km) <= 1e-4
+        o += len(exp)
+    assert o == c.n
+
+
+@pytest.mark.parametrize("name", ["dense_tiny", "hub_tiny"])
+def test_pruned_search_exact_on_kept_pairs(name):
+    import torch
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload(name)
+    n = cfg.graph.n
+    say(f"case pruned search {name}")
+    g = gpu_graph(n, cfg.graph.R, h, r, t, X, Y)
+    orp, ocol, _ = (x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=False))
+    irp, icol, _ = (x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=True))
+    rng = np.random.Generator(np.random.PCG64(9))
+    offs, flags = [], []
+    o = 0
+    for qi in range(len(s)):
+        ns, nt = orp[s[qi] + 1] - orp[s[qi]], irp[d[qi] + 1] - irp[d[qi]]
+        offs.append(o)
+        flags.append((rng.random(ns + nt) < 0.4).astype(np.uint8))
+        o += ns + nt
+    keep = torch.from_numpy(np.concatenate(flags + [np.zeros(1, np.uint8)])).cuda()
+    keep_off = torch.from_numpy(np.array(offs, dtype=np.int64)).cuda()
+    K = 12
+    res = g.topk_pruned(s, d, K, keep, keep_off)
+    torch.cuda.synchronize()
+    gp, gc, gt, gs = res.to_numpy()
+    Xf = oracle.as_f32_table(X, cfg.emb.dtype).astype(np.float64)
+    Yf = oracle.as_f32_table(Y, cfg.emb.dtype).astype(np.float64)
+    edges = list(zip(h.tolist(), r.tolist(), t.tolist()))
+    op = np.zeros((len(s), K), oracle.PATH_DTYPE)
+    oc = np.zeros(len(s), np.uint32)
+    ot = np.zeros(len(s), np.uint64)
+    for qi in range(len(s)):
+        ns = orp[s[qi] + 1] - orp[s[qi]]
+        fl = flags[qi]
+        ka = set(int(ocol[orp[s[qi]] + i]) for i in range(ns) if fl[i])
+        kb = set(int(icol[irp[d[qi]] + j]) for j in range(len(fl) - ns) if fl[ns + j])
+        paths, tot = pyoracle.topk_paths(edges, Xf, Yf, int(s[qi]), int(d[qi]), K, ka, kb)
+        oc[qi] = len(paths)
+        ot[qi] = tot
+        for i, (S, a, b, r1, r2, r3) in enumerate(paths):
+            op[qi, i] = (S, a, b, r1, r2, r3)
+    compare((gp, gc, gt, gs), (op, oc, ot))
+    assert np.any(ot > 0) and np.any(oc == K)
