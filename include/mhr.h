@@ -266,7 +266,12 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
  * fallback and as the judge of its recall.  Candidates of a query (s, t):
  *   first hop   one per relation r1 of each entry a of s's out-row (edge s -r1-> a)
  *   second hop  one per relation r3 of each entry b of t's in-row  (edge b -r3-> t)
- * Network (f = [X[s], X[t], X[v], Y[r]], v = a or b, r = r1 or r3):
+ * Network input f = [X[u], X[w], X[v], Y[r]]: v the candidate vertex (a or
+ * b), r its edge's relation (r1 or r3), u the query endpoint that edge
+ * touches (s for the first hop, t for the second) and w the other endpoint
+ * (the same functional form for both hops: the DistMult weight is
+ * symmetric).  A sample's query word carries the hop in bit 31
+ * (MHR_PRUNER_HOP2).  Network:
  *   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), z = w3 . h2 + b3, p = sigmoid(z)
  * with W1 [hidden][4 dim], W2 [hidden][hidden], w3 [hidden].  Parameters are
  * one flat FP32 vector: W1 (row-major), b1, W2 (row-major), b2, w3, b3.
@@ -275,6 +280,8 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
  * master weights and Adam state are FP32.
  * ------------------------------------------------------------------------- */
 typedef struct mhr_pruner mhr_pruner;
+
+#define MHR_PRUNER_HOP2 0x80000000u   /* second-hop flag in a sample's or candidate's query word */
 
 /* Number of parameters for embedding dimension dim and hidden width hidden. */
 size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden);
@@ -296,7 +303,8 @@ mhr_status mhr_pruner_get_params(const mhr_pruner *p, float *params, float *grad
 mhr_status mhr_pruner_workspace_size(const mhr_pruner *p, uint32_t n, size_t *bytes);
 
 /* Logits z for n samples: sample i is the candidate (v[i], r[i]) of query
- * q[i], whose endpoints are src[q[i]], dst[q[i]].  All device arrays; the
+ * q[i] & ~MHR_PRUNER_HOP2 (a second-hop candidate when bit 31 is set), whose
+ * endpoints are src[...], dst[...].  All device arrays; the
  * embeddings are the graph's (dimension must equal the pruner's). */
 mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q,
                               const uint32_t *src, const uint32_t *dst, const uint32_t *v,
@@ -321,7 +329,8 @@ mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, uint32_t n, 
 mhr_status mhr_pruner_count(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                             uint64_t *entry_off, uint64_t *cand_off, void *stream);
 
-/* Writes the candidates: query, vertex, relation and keep-flag index of each
+/* Writes the candidates: query word (the query index, | MHR_PRUNER_HOP2 for
+ * second-hop candidates), vertex, relation and keep-flag index of each
  * (first-hop ones of a query first, in CSR order and ascending relation),
  * and cand_split[q], the index of the query's first second-hop candidate.
  * Output arrays hold cand_off[nq] elements. */
@@ -330,17 +339,60 @@ mhr_status mhr_pruner_enumerate(const mhr_graph *g, uint32_t nq, const uint32_t 
                                 uint32_t *cand_q, uint32_t *cand_v, uint32_t *cand_r, uint64_t *cand_e,
                                 void *stream);
 
-/* Per query and hop, keeps the ceil(n * keep_permille / 1000) candidates
- * with the highest score (and every candidate tied with the lowest kept
- * one); an entry is kept when any of its candidates is.  Writes the keep
- * flags (all entries of the query, see mhr_topk_paths_pruned) and, if mass
- * is not NULL, mass[2q + hop] = the kept share of sum(sigmoid(score)) (1
- * when the hop has no candidates).  Scores may be logits or any other
- * ranking (NaN ranks lowest). */
+/* Per query and hop, keeps the ceil(n * keep_permille / 1000) of the hop's
+ * n entries (vertices) with the best entry score, an entry's score being
+ * the highest score of its candidates (and every entry tied with the lowest
+ * kept one).  Writes the keep flags (all entries of the query, see
+ * mhr_topk_paths_pruned) and, if mass is not NULL, mass[2q + hop] = the
+ * share of sum(sigmoid(score)) held by the candidates of kept entries (1
+ * when the hop has none).  Scores may be logits or any other ranking (NaN
+ * ranks lowest).  ncand = cand_off[nq], nentries = entry_off[nq] (host
+ * values); entry_key: device workspace of nentries uint32. */
 mhr_status mhr_pruner_select(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                              const uint64_t *entry_off, const uint64_t *cand_off,
                              const uint64_t *cand_split, const float *score, const uint64_t *cand_e,
-                             uint32_t keep_permille, uint8_t *keep, float *mass, void *stream);
+                             uint64_t ncand, uint64_t nentries, uint32_t keep_permille, uint8_t *keep,
+                             float *mass, uint32_t *entry_key, void *stream);
+
+/* Training labels: pos[e] = 1 for the entries e (keep-flag layout) whose
+ * vertex is the a (first-hop entry) or the b (second-hop entry) of one of the
+ * query's paths paths[q][0 .. count[q]) (e.g. the exact top-K), else 0. */
+mhr_status mhr_pruner_label(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                            const uint64_t *entry_off, const mhr_path *paths, const uint32_t *count,
+                            uint32_t kmax, uint8_t *pos, void *stream);
+
+/* Device workspace bytes of mhr_pruner_sample. */
+size_t mhr_pruner_sample_workspace(uint32_t nq, uint64_t ncand);
+
+/* Training samples from the candidates: every positive candidate (pos of
+ * its entry) and each negative with probability min(1, neg_per_hop / the
+ * negatives of its query and hop), drawn from a counter-based generator
+ * (SplitMix64 of seed and the candidate index).  Writes, in candidate order,
+ * the samples' query, vertex, relation and label (0/1) into arrays of
+ * capacity ncand, and their number to *nsamples (device). */
+mhr_status mhr_pruner_sample(uint32_t nq, const uint64_t *cand_off, const uint64_t *cand_split,
+                             uint64_t ncand, const uint32_t *cand_q, const uint32_t *cand_v,
+                             const uint32_t *cand_r, const uint64_t *cand_e, const uint8_t *pos,
+                             uint32_t neg_per_hop, uint64_t seed, uint32_t *sq, uint32_t *sv,
+                             uint32_t *sr, float *slabel, uint64_t *nsamples, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Confidence test of a pruned search: the queries (status 0) whose pruned
+ * result has fewer than k paths, or whose kept share of the predicted mass
+ * (mass[2q], mass[2q + 1] from mhr_pruner_select) is below tau at either
+ * hop, are compacted in order into fb_src / fb_dst / fb_k / fb_idx (the
+ * original index), their number in *nfb (device).  k may be NULL (kdef). */
+mhr_status mhr_pruner_fallback(uint32_t nq, const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                               uint32_t kdef, const uint32_t *count, const uint32_t *status,
+                               const float *mass, float tau, uint32_t *fb_src, uint32_t *fb_dst,
+                               uint32_t *fb_k, uint32_t *fb_idx, uint32_t *nfb, void *stream);
+
+/* Copies result row i of a compact batch (paths[i][0..kmax), count, total,
+ * status) to row idx[i] of a full batch, for i < n (host count). */
+mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint32_t kmax, const mhr_path *src_paths,
+                               const uint32_t *src_count, const uint64_t *src_total,
+                               const uint32_t *src_status, mhr_path *paths, uint32_t *count,
+                               uint64_t *total, uint32_t *status, void *stream);
 
 /* Edge-weight kernel on its own (for checking the scorer):
  * for each i < ne, the edge (u[i], r[i], v[i]) (it need not exist in the

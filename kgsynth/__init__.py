@@ -120,6 +120,20 @@ CONFIGS = {
         GraphSpec("chunglu", 3000, 4, 30000, seed=31, wmax=600.0),
         EmbSpec(16, "bf16", seed=34),
         QuerySpec(48, "degree", 16, seed=33)),
+    # learned-pruner tests: a mid-sized Chung-Lu graph, d=64 bfloat16; the
+    # query spec is the held-out evaluation set (training queries use seed 82)
+    "pruner_small": Workload(
+        "pruner_small",
+        GraphSpec("chunglu", 200_000, 16, 4_000_000, seed=77, wmax=20_000.0),
+        EmbSpec(64, "bf16", seed=78),
+        QuerySpec(2000, "degree", 32, seed=80)),
+    # the learned-pruner form: the precision graph; held-out evaluation
+    # queries (training queries use seed 15)
+    "pruner": Workload(
+        "pruner",
+        GraphSpec("chunglu", 4_000_000, 32, 64_000_000, seed=2407),
+        EmbSpec(256, "bf16", seed=7728),
+        QuerySpec(8192, "degree", 32, seed=14)),
     "hub_r32_bf16": Workload(
         "hub_r32_bf16",
         GraphSpec("chunglu", 4000, 32, 60000, seed=41, wmax=800.0),

@@ -4,9 +4,11 @@ The learned pruner ranks the frontier candidates of a query (s, t): a
 first-hop candidate is an edge (s, r1, a) and a second-hop candidate an edge
 (b, r3, t).  The paper's generic search keeps a bounded frontier per level
 (section 5); here a small network learns which candidates lie on the exact
-top-K paths.  For a candidate with vertex v and relation r:
+top-K paths.  For a candidate with vertex v and relation r, u the query
+endpoint its edge touches (s for the first hop, t for the second) and w the
+other endpoint:
 
-    f  = [X[s], X[t], X[v], Y[r]]                     (4d inputs)
+    f  = [X[u], X[w], X[v], Y[r]]                     (4d inputs)
     h1 = relu(W1 f + b1)                              W1: [H, 4d]
     h2 = relu(W2 h1 + b2)                             W2: [H, H]
     z  = w3 . h2 + b3                                 w3: [H]
@@ -69,11 +71,17 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def features(X, Y, s, t, v, r) -> np.ndarray:
-    """f_i = [X[s_i], X[t_i], X[v_i], Y[r_i]] in float64 (tables as stored:
-    float32 values, or bfloat16 values widened exactly)."""
+def features(X, Y, s, t, v, r, hop2=None) -> np.ndarray:
+    """f_i = [X[u_i], X[w_i], X[v_i], Y[r_i]] in float64 (tables as stored:
+    float32 values, or bfloat16 values widened exactly), with (u, w) = (s, t)
+    for first-hop candidates and (t, s) where hop2 is true."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
+    s = np.asarray(s)
+    t = np.asarray(t)
+    if hop2 is not None:
+        hop2 = np.asarray(hop2, dtype=bool)
+        s, t = np.where(hop2, t, s), np.where(hop2, s, t)
     return np.concatenate([X[s], X[t], X[v], Y[r]], axis=1)
 
 

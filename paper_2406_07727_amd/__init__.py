@@ -127,7 +127,20 @@ _lib.mhr_pruner_count.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_pruner_enumerate.restype = _i
 _lib.mhr_pruner_enumerate.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_pruner_select.restype = _i
-_lib.mhr_pruner_select.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp]
+_lib.mhr_pruner_select.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u32, _vp, _vp, _vp,
+                                   _vp]
+_lib.mhr_pruner_label.restype = _i
+_lib.mhr_pruner_label.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp]
+_lib.mhr_pruner_sample_workspace.restype = ctypes.c_size_t
+_lib.mhr_pruner_sample_workspace.argtypes = [_u32, _u64]
+_lib.mhr_pruner_sample.restype = _i
+_lib.mhr_pruner_sample.argtypes = [_u32, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u32, _u64, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, ctypes.c_size_t, _vp]
+_lib.mhr_pruner_fallback.restype = _i
+_lib.mhr_pruner_fallback.argtypes = [_u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp,
+                                     _vp, _vp]
+_lib.mhr_scatter_results.restype = _i
+_lib.mhr_scatter_results.argtypes = [_u32, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_status_string.restype = ctypes.c_char_p
 _lib.mhr_status_string.argtypes = [_i]
 _lib.mhr_last_error.restype = ctypes.c_char_p
@@ -417,18 +430,18 @@ def candidates(graph: Graph, src, dst, stream=None) -> Candidates:
 
 def select(graph: Graph, c: Candidates, scores, keep_permille: int = 100, stream=None):
     """Keep flags (uint8 [n_entries]) of the top keep_permille / 1000 of each
-    query's candidates per hop by score, and the kept sigmoid mass
-    (float32 [nq, 2])."""
+    query's entries per hop, ranked by their best candidate score, and the
+    kept sigmoid mass (float32 [nq, 2])."""
     torch = _torch()
     nq = c.src.numel()
     keep = torch.empty(max(c.n_entries, 1), dtype=torch.uint8, device="cuda")
     mass = torch.empty((nq, 2), dtype=torch.float32, device="cuda")
-    sc = scores.contiguous()
-    if c.n == 0:
-        sc = torch.zeros(1, dtype=torch.float32, device="cuda")
+    key = torch.empty(max(c.n_entries, 1), dtype=torch.int32, device="cuda")
+    sc = scores.contiguous() if c.n else None
     _check(_lib.mhr_pruner_select(graph._h, nq, _ptr(c.src), _ptr(c.dst), _ptr(c.entry_off), _ptr(c.cand_off),
-                                  _ptr(c.cand_split), _ptr(sc), _ptr(c.e) if c.n else _ptr(torch.zeros(1, dtype=torch.int64, device="cuda")),
-                                  int(keep_permille), _ptr(keep), _ptr(mass), _stream_ptr(stream)), "mhr_pruner_select")
+                                  _ptr(c.cand_split), _ptr(sc), _ptr(c.e) if c.n else None, c.n, c.n_entries,
+                                  int(keep_permille), _ptr(keep), _ptr(mass), _ptr(key), _stream_ptr(stream)),
+           "mhr_pruner_select")
     return keep, mass
 
 

@@ -1,6 +1,10 @@
-// Learned frontier pruner: a small MLP over f = [X[s], X[t], X[v], Y[r]]
-// that scores the first-hop candidates (s, r1, a) and second-hop candidates
-// (b, r3, t) of a query, trained on labels from the exact search.
+// Learned frontier pruner: a small MLP that scores the first-hop candidates
+// (s, r1, a) and second-hop candidates (b, r3, t) of a query, trained on
+// labels from the exact search.  Its input is f = [X[u], X[w], X[v], Y[r]]
+// with u the query endpoint the candidate edge touches (s, or t for the
+// second hop), w the other endpoint, v the candidate vertex and r the
+// edge's relation: the same functional form for both hops, as the DistMult
+// weight w(b, r3, t) = w(t, r3, b) is symmetric.
 //
 //   h1 = relu(W1 f + b1),  h2 = relu(W2 h1 + b2),  z = w3 . h2 + b3
 //
@@ -188,12 +192,17 @@ __global__ void to_bf16_kernel(const float *src, uint16_t *dst, size_t n) {
         dst[i] = to_bf16(src[i]);
 }
 
-// per-sample (s, t) of the sample's query
+constexpr uint32_t kHop2 = 0x80000000u;   // second-hop flag in a sample's query word
+
+// Per sample, the query endpoint its candidate edge touches (s for the first
+// hop, t for the second) and the other endpoint: the first two feature slots.
 __global__ void expand_query_kernel(const uint32_t *q, const uint32_t *src, const uint32_t *dst, uint32_t *s,
                                     uint32_t *t, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        s[i] = src[q[i]];
-        t[i] = dst[q[i]];
+        const uint32_t w = q[i], qq = w & ~kHop2;
+        const bool hop2 = (w & kHop2) != 0;
+        s[i] = hop2 ? dst[qq] : src[qq];
+        t[i] = hop2 ? src[qq] : dst[qq];
     }
 }
 
@@ -502,7 +511,7 @@ __global__ void cand_fill_kernel(const uint32_t *out_rp, const uint32_t *out_col
                 uint64_t o = c + before + v - x;
                 const uint64_t e = entry_off[q] + (hop ? degs : 0u) + (i - beg);
                 for (uint32_t mm = m; mm; mm &= mm - 1) {
-                    cq[o] = q;
+                    cq[o] = hop ? (q | kHop2) : q;
                     cv[o] = col[i];
                     cr[o] = static_cast<uint32_t>(__ffs(mm) - 1);
                     ce[o] = e;
@@ -535,14 +544,24 @@ __device__ inline T wg_sum(T v, T *red) {
     return s;
 }
 
-// One workgroup per (query, hop): keep the ceil(n * permille / 1000)
-// highest-scoring candidates (all ties with the lowest kept score too); an
-// entry is kept when any of its candidates is.  mass[2q + hop] = sum of
-// sigmoid(score) over kept candidates / over all (1 when n = 0).
+// An entry's score: the best score of its candidates (order-preserving key).
+__global__ void entry_key_kernel(const float *score, const uint64_t *ce, uint64_t n, uint32_t *key) {
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        atomicMax(&key[ce[i]], score_key(score[i]));
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+// One workgroup per (query, hop): keep the ceil(n * permille / 1000) entries
+// (vertices) of the hop with the best entry scores, and every entry tied
+// with the lowest kept one.  mass[2q + hop] = sum of sigmoid(score) over the
+// candidates of kept entries / over all candidates (1 when there are none).
 __global__ void select_kernel(const uint32_t *out_rp, const uint32_t *in_rp, uint32_t n, const uint32_t *src,
                               const uint32_t *dst, const uint64_t *entry_off, const uint64_t *cand_off,
-                              const uint64_t *cand_split, const float *score, const uint64_t *ce, uint32_t permille,
-                              uint8_t *keep, float *mass) {
+                              const uint64_t *cand_split, const float *score, const uint64_t *ce, const uint32_t *ekey,
+                              uint32_t permille, uint8_t *keep, float *mass) {
     __shared__ uint64_t red64[kBlock / kWave];
     __shared__ float redf[kBlock / kWave];
     const uint32_t q = blockIdx.x, hop = blockIdx.y;
@@ -553,38 +572,214 @@ __global__ void select_kernel(const uint32_t *out_rp, const uint32_t *in_rp, uin
     }
     const uint32_t degs = out_rp[s + 1] - out_rp[s], degt = in_rp[t + 1] - in_rp[t];
     const uint64_t e0 = entry_off[q] + (hop ? degs : 0u), ne = hop ? degt : degs;
-    for (uint64_t i = threadIdx.x; i < ne; i += blockDim.x) keep[e0 + i] = 0;
-    const uint64_t c0 = hop ? cand_split[q] : cand_off[q], c1 = hop ? cand_off[q + 1] : cand_split[q];
-    const uint64_t nc = c1 - c0;
-    __syncthreads();
-    if (nc == 0) {
+    if (ne == 0) {
         if (threadIdx.x == 0 && mass) mass[2 * q + hop] = 1.0f;
         return;
     }
-    const uint64_t m = (nc * permille + 999) / 1000 > 0 ? (nc * permille + 999) / 1000 : 1;
-    // the m-th largest key: the largest T with #{key >= T} >= m, bit by bit
+    const uint64_t m = (ne * permille + 999) / 1000 > 0 ? (ne * permille + 999) / 1000 : 1;
+    // the m-th largest entry key: the largest T with #{key >= T} >= m, bit by bit
     uint32_t T = 0;
     for (int bit = 31; bit >= 0; --bit) {
         const uint32_t cand = T | (1u << bit);
         uint64_t cnt = 0;
-        for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) cnt += score_key(score[i]) >= cand ? 1u : 0u;
+        for (uint64_t i = threadIdx.x; i < ne; i += blockDim.x) cnt += ekey[e0 + i] >= cand ? 1u : 0u;
         cnt = wg_sum<uint64_t>(cnt, red64);
         if (cnt >= m) T = cand;
     }
-    __syncthreads();
+    for (uint64_t i = threadIdx.x; i < ne; i += blockDim.x) keep[e0 + i] = ekey[e0 + i] >= T ? 1 : 0;
+    const uint64_t c0 = hop ? cand_split[q] : cand_off[q], c1 = hop ? cand_off[q + 1] : cand_split[q];
     float pk = 0.0f, pa = 0.0f;
     for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
         const float x = score[i];
         const float p = (x != x) ? 0.0f : 1.0f / (1.0f + expf(-x));
         pa += p;
-        if (score_key(x) >= T) {
-            keep[ce[i]] = 1;
-            pk += p;
-        }
+        if (ekey[ce[i]] >= T) pk += p;
     }
     pk = wg_sum<float>(pk, redf);
     pa = wg_sum<float>(pa, redf);
     if (threadIdx.x == 0 && mass) mass[2 * q + hop] = pa > 0.0f ? pk / pa : 1.0f;
+}
+
+// Positive flags per entry: an entry of s's out-row (t's in-row) is positive
+// when its vertex is the a (the b) of one of the query's given paths.  The
+// rows are sorted by vertex id, so each lookup is a binary search.
+__device__ inline uint32_t row_find(const uint32_t *col, uint32_t beg, uint32_t end, uint32_t x) {
+    uint32_t lo = beg, hi = end;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (col[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && col[lo] == x) ? lo : 0xFFFFFFFFu;
+}
+
+__global__ void label_kernel(const uint32_t *out_rp, const uint32_t *out_col, const uint32_t *in_rp,
+                             const uint32_t *in_col, uint32_t n, const uint32_t *src, const uint32_t *dst,
+                             const uint64_t *entry_off, const mhr_path *paths, const uint32_t *count, uint32_t kmax,
+                             uint8_t *pos) {
+    const uint32_t q = blockIdx.x;
+    const uint32_t s = src[q], t = dst[q];
+    if (!(s < n && t < n)) return;
+    const uint32_t sb = out_rp[s], se = out_rp[s + 1], tb = in_rp[t], te = in_rp[t + 1];
+    const uint64_t e0 = entry_off[q];
+    for (uint32_t i = threadIdx.x; i < (se - sb) + (te - tb); i += blockDim.x) pos[e0 + i] = 0;
+    __syncthreads();
+    const uint32_t c = min(count[q], kmax);
+    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+        const mhr_path p = paths[static_cast<size_t>(q) * kmax + i];
+        const uint32_t ja = row_find(out_col, sb, se, p.a);
+        const uint32_t jb = row_find(in_col, tb, te, p.b);
+        if (ja != 0xFFFFFFFFu) pos[e0 + (ja - sb)] = 1;
+        if (jb != 0xFFFFFFFFu) pos[e0 + (se - sb) + (jb - tb)] = 1;
+    }
+}
+
+// Counter-based uniform number in [0, 1) for (seed, i): the SplitMix64
+// finaliser (Steele, Lea & Flood 2014) of seed + (i + 1) * golden gamma.
+__device__ __forceinline__ float uniform01(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return static_cast<float>(z >> 40) * (1.0f / 16777216.0f);
+}
+
+// Training-sample choice per candidate: every positive, and each negative
+// with probability min(1, neg / negatives of its query and hop), so that
+// about `neg` negatives per hop and query are drawn.
+__global__ void sample_mask_kernel(const uint64_t *cand_off, const uint64_t *cand_split, uint64_t n,
+                                   const uint32_t *cq, const uint64_t *ce, const uint8_t *pos, const uint32_t *npos,
+                                   uint32_t neg, uint64_t seed, uint8_t *take) {
+    for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t q = cq[i] & ~kHop2;
+        const bool hop = i >= cand_split[q];
+        const uint64_t nh = hop ? cand_off[q + 1] - cand_split[q] : cand_split[q] - cand_off[q];
+        const uint64_t nneg = nh - npos[2 * q + (hop ? 1 : 0)];
+        const bool p = pos[ce[i]] != 0;
+        take[i] = (p || (nneg > 0 && uniform01(seed, i) * static_cast<float>(nneg) < static_cast<float>(neg))) ? 1 : 0;
+    }
+}
+
+// positive candidates per (query, hop)
+__global__ void count_pos_kernel(const uint64_t *cand_off, const uint64_t *cand_split, const uint64_t *ce,
+                                 const uint8_t *pos, uint32_t *npos) {
+    __shared__ uint64_t red[kBlock / kWave];
+    const uint32_t q = blockIdx.x, hop = blockIdx.y;
+    const uint64_t c0 = hop ? cand_split[q] : cand_off[q], c1 = hop ? cand_off[q + 1] : cand_split[q];
+    uint64_t cnt = 0;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) cnt += pos[ce[i]] ? 1u : 0u;
+    cnt = wg_sum<uint64_t>(cnt, red);
+    if (threadIdx.x == 0) npos[2 * q + hop] = static_cast<uint32_t>(cnt);
+}
+
+constexpr uint32_t kCompactChunk = 4096;   // flags per block in the compaction passes
+
+__global__ void chunk_count_kernel(const uint8_t *flag, uint64_t n, uint64_t *cnt) {
+    __shared__ uint64_t red[kBlock / kWave];
+    const uint64_t b0 = blockIdx.x * uint64_t(kCompactChunk), b1 = min(n, b0 + kCompactChunk);
+    uint64_t c = 0;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) c += flag[i] ? 1u : 0u;
+    c = wg_sum<uint64_t>(c, red);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+// In-order compaction of the taken candidates into training samples.
+__global__ void sample_fill_kernel(const uint8_t *take, uint64_t n, const uint64_t *chunk_off, const uint32_t *cq,
+                                   const uint32_t *cv, const uint32_t *cr, const uint64_t *ce, const uint8_t *pos,
+                                   uint32_t *sq, uint32_t *sv, uint32_t *sr, float *sl) {
+    __shared__ uint64_t red[kBlock / kWave];
+    __shared__ uint64_t carry;
+    const uint64_t b0 = blockIdx.x * uint64_t(kCompactChunk), b1 = min(n, b0 + kCompactChunk);
+    if (threadIdx.x == 0) carry = chunk_off[blockIdx.x];
+    __syncthreads();
+    for (uint64_t base = b0; base < b1; base += blockDim.x) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t x = (i < b1 && take[i]) ? 1u : 0u;
+        uint64_t v = x;
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t y = __shfl_up(v, off, kWave);
+            if (lane >= off) v += y;
+        }
+        if (lane == kWave - 1) red[wave] = v;
+        __syncthreads();
+        uint64_t before = 0, tot = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) {
+            if (w < wave) before += red[w];
+            tot += red[w];
+        }
+        const uint64_t c = carry;
+        if (x) {
+            const uint64_t o = c + before + v - 1;
+            sq[o] = cq[i];
+            sv[o] = cv[i];
+            sr[o] = cr[i];
+            sl[o] = pos[ce[i]] ? 1.0f : 0.0f;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+// One workgroup: the queries to answer exactly, because the pruned search
+// found fewer than k paths or kept less than tau of the predicted mass at
+// either hop; compacted in order, their count in *nfb.
+__global__ void fallback_kernel(uint32_t nq, const uint32_t *src, const uint32_t *dst, const uint32_t *kq,
+                                uint32_t kdef, const uint32_t *count, const uint32_t *status, const float *mass,
+                                float tau, uint32_t *fb_src, uint32_t *fb_dst, uint32_t *fb_k, uint32_t *fb_idx,
+                                uint32_t *nfb) {
+    __shared__ uint32_t red[kBlock / kWave];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nq; base += blockDim.x) {
+        const uint32_t q = base + threadIdx.x;
+        uint32_t x = 0;
+        if (q < nq && status[q] == 0) {
+            const uint32_t k = kq ? kq[q] : kdef;
+            x = (count[q] < k || mass[2 * q] < tau || mass[2 * q + 1] < tau) ? 1u : 0u;
+        }
+        uint32_t v = x;
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = __shfl_up(v, off, kWave);
+            if (lane >= off) v += y;
+        }
+        if (lane == kWave - 1) red[wave] = v;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) {
+            if (w < wave) before += red[w];
+            tot += red[w];
+        }
+        const uint32_t c = carry;
+        if (x) {
+            const uint32_t o = c + before + v - 1;
+            fb_src[o] = src[q];
+            fb_dst[o] = dst[q];
+            fb_k[o] = kq ? kq[q] : kdef;
+            fb_idx[o] = q;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nfb = carry;
+}
+
+__global__ void scatter_kernel(uint32_t n, const uint32_t *idx, uint32_t kmax, const mhr_path *sp, const uint32_t *sc,
+                               const uint64_t *st, const uint32_t *ss, mhr_path *dp, uint32_t *dc, uint64_t *dt,
+                               uint32_t *ds) {
+    const uint32_t i = blockIdx.x;
+    if (i >= n) return;
+    const uint32_t q = idx[i];
+    for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x)
+        dp[static_cast<size_t>(q) * kmax + j] = sp[static_cast<size_t>(i) * kmax + j];
+    if (threadIdx.x == 0) {
+        dc[q] = sc[i];
+        if (dt && st) dt[q] = st[i];
+        if (ds && ss) ds[q] = ss[i];
+    }
 }
 
 }  // namespace
@@ -782,14 +977,100 @@ extern "C" mhr_status mhr_pruner_enumerate(const mhr_graph *g, uint32_t nq, cons
 extern "C" mhr_status mhr_pruner_select(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                                         const uint64_t *entry_off, const uint64_t *cand_off,
                                         const uint64_t *cand_split, const float *score, const uint64_t *cand_e,
-                                        uint32_t keep_permille, uint8_t *keep, float *mass, void *stream) {
-    MHR_ARG_CHECK(g && src && dst && entry_off && cand_off && cand_split && score && cand_e && keep,
+                                        uint64_t ncand, uint64_t nentries, uint32_t keep_permille, uint8_t *keep,
+                                        float *mass, uint32_t *entry_key, void *stream) {
+    MHR_ARG_CHECK(g && src && dst && entry_off && cand_off && cand_split && keep && entry_key,
                   "mhr_pruner_select: null argument");
+    MHR_ARG_CHECK(ncand == 0 || (score && cand_e), "mhr_pruner_select: null scores");
     MHR_ARG_CHECK(nq >= 1 && keep_permille >= 1 && keep_permille <= 1000,
                   "mhr_pruner_select: nq >= 1 and keep_permille in [1, 1000]");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (nentries) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nentries)), dim3(256), 0, st, entry_key, nentries, 0u);
+        if (ncand)
+            hipLaunchKernelGGL(entry_key_kernel, dim3(grid_for(ncand)), dim3(256), 0, st, score, cand_e, ncand,
+                               entry_key);
+    }
     hipLaunchKernelGGL(select_kernel, dim3(nq, 2), dim3(kBlock), 0, st, g->out.row_ptr, g->in.row_ptr, g->n, src, dst,
-                       entry_off, cand_off, cand_split, score, cand_e, keep_permille, keep, mass);
+                       entry_off, cand_off, cand_split, score, cand_e, entry_key, keep_permille, keep, mass);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_label(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                       const uint64_t *entry_off, const mhr_path *paths, const uint32_t *count,
+                                       uint32_t kmax, uint8_t *pos, void *stream) {
+    MHR_ARG_CHECK(g && src && dst && entry_off && paths && count && pos, "mhr_pruner_label: null argument");
+    MHR_ARG_CHECK(nq >= 1 && kmax >= 1, "mhr_pruner_label: nq >= 1 and kmax >= 1");
+    hipLaunchKernelGGL(label_kernel, dim3(nq), dim3(256), 0, static_cast<hipStream_t>(stream), g->out.row_ptr,
+                       g->out.col, g->in.row_ptr, g->in.col, g->n, src, dst, entry_off, paths, count, kmax, pos);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" size_t mhr_pruner_sample_workspace(uint32_t nq, uint64_t ncand) {
+    const size_t chunks = static_cast<size_t>((ncand + kCompactChunk - 1) / kCompactChunk);
+    return ((ncand + 255) & ~uint64_t(255)) + (size_t(2) * nq * 4 + 255) / 256 * 256 + (chunks + 1) * 8;
+}
+
+extern "C" mhr_status mhr_pruner_sample(uint32_t nq, const uint64_t *cand_off, const uint64_t *cand_split,
+                                        uint64_t ncand, const uint32_t *cand_q, const uint32_t *cand_v,
+                                        const uint32_t *cand_r, const uint64_t *cand_e, const uint8_t *pos,
+                                        uint32_t neg_per_hop, uint64_t seed, uint32_t *sq, uint32_t *sv,
+                                        uint32_t *sr, float *slabel, uint64_t *nsamples, void *ws, size_t ws_bytes,
+                                        void *stream) {
+    MHR_ARG_CHECK(cand_off && cand_split && pos && sq && sv && sr && slabel && nsamples && ws,
+                  "mhr_pruner_sample: null argument");
+    MHR_ARG_CHECK(nq >= 1, "mhr_pruner_sample: nq must be >= 1");
+    if (ws_bytes < mhr_pruner_sample_workspace(nq, ncand)) {
+        set_error("mhr_pruner_sample: workspace too small");
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    uint8_t *take = reinterpret_cast<uint8_t *>(w);
+    uint32_t *npos = reinterpret_cast<uint32_t *>(w + ((ncand + 255) & ~uint64_t(255)));
+    uint64_t *chunk = reinterpret_cast<uint64_t *>(w + ((ncand + 255) & ~uint64_t(255)) +
+                                                   (size_t(2) * nq * 4 + 255) / 256 * 256);
+    const uint32_t chunks = static_cast<uint32_t>((ncand + kCompactChunk - 1) / kCompactChunk);
+    if (ncand == 0) {
+        hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float *>(nsamples), size_t(2), 0.0f);
+        MHR_HIP_TRY(hipGetLastError());
+        return MHR_OK;
+    }
+    hipLaunchKernelGGL(count_pos_kernel, dim3(nq, 2), dim3(kBlock), 0, st, cand_off, cand_split, cand_e, pos, npos);
+    hipLaunchKernelGGL(sample_mask_kernel, dim3(grid_for(ncand)), dim3(256), 0, st, cand_off, cand_split, ncand,
+                       cand_q, cand_e, pos, npos, neg_per_hop, seed, take);
+    hipLaunchKernelGGL(chunk_count_kernel, dim3(chunks), dim3(kBlock), 0, st, take, ncand, chunk);
+    hipLaunchKernelGGL(excl_scan_kernel, dim3(1), dim3(kBlock), 0, st, chunk, chunks);
+    hipLaunchKernelGGL(sample_fill_kernel, dim3(chunks), dim3(kBlock), 0, st, take, ncand, chunk, cand_q, cand_v,
+                       cand_r, cand_e, pos, sq, sv, sr, slabel);
+    MHR_HIP_TRY(hipMemcpyAsync(nsamples, chunk + chunks, 8, hipMemcpyDeviceToDevice, st));
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_fallback(uint32_t nq, const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                          uint32_t kdef, const uint32_t *count, const uint32_t *status,
+                                          const float *mass, float tau, uint32_t *fb_src, uint32_t *fb_dst,
+                                          uint32_t *fb_k, uint32_t *fb_idx, uint32_t *nfb, void *stream) {
+    MHR_ARG_CHECK(src && dst && count && status && mass && fb_src && fb_dst && fb_k && fb_idx && nfb,
+                  "mhr_pruner_fallback: null argument");
+    MHR_ARG_CHECK(nq >= 1 && (k || kdef >= 1), "mhr_pruner_fallback: nq >= 1 and a K");
+    hipLaunchKernelGGL(fallback_kernel, dim3(1), dim3(kBlock), 0, static_cast<hipStream_t>(stream), nq, src, dst, k,
+                       kdef, count, status, mass, tau, fb_src, fb_dst, fb_k, fb_idx, nfb);
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint32_t kmax, const mhr_path *src_paths,
+                                          const uint32_t *src_count, const uint64_t *src_total,
+                                          const uint32_t *src_status, mhr_path *paths, uint32_t *count,
+                                          uint64_t *total, uint32_t *status, void *stream) {
+    if (n == 0) return MHR_OK;
+    MHR_ARG_CHECK(idx && src_paths && src_count && paths && count && kmax >= 1, "mhr_scatter_results: null argument");
+    hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(64), 0, static_cast<hipStream_t>(stream), n, idx, kmax, src_paths,
+                       src_count, src_total, src_status, paths, count, total, status);
     MHR_HIP_TRY(hipGetLastError());
     return MHR_OK;
 }
