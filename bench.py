@@ -170,6 +170,51 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps}), flush=True)
 
 
+def run_pruner(args, cfg, g, h, s, d):
+    """The learned-pruner form: train the network on exact-search labels,
+    then answer the held-out batch with the pruned search (and the exact
+    search as fallback) beside the exact search alone."""
+    import torch
+    import kgsynth
+    import paper_2406_07727_amd as mhr
+    from paper_2406_07727_amd.learned import LearnedPruner, topk_recall
+    K = cfg.query.k
+    s_tr, d_tr, _ = kgsynth.queries(h, cfg.graph.n, kgsynth.QuerySpec(args.train_queries, "degree", K, seed=15))
+    lp = LearnedPruner(g, cfg.emb.d, args.hidden, seed=3)
+    t0 = time.perf_counter()
+    losses = lp.fit(s_tr, d_tr, K=K, step_samples=8192, epochs=1, lr=1e-3, seed=4, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t1) / reps
+
+    exact, t_exact = timed(lambda: g.topk(s, d, K), args.steps)
+    exn = exact.to_numpy()
+    out = {"train_queries": args.train_queries, "hidden": args.hidden, "train_seconds": round(train_s, 1),
+           "train_steps": len(losses), "loss_first": round(float(np.mean(losses[:5])), 4),
+           "loss_last": round(float(np.mean(losses[-20:])), 4), "keep_permille": 100,
+           "exact_queries_per_s": len(s) / t_exact}
+    c = mhr.candidates(g, s, d)
+    for kind in ("net", "random", "beam"):
+        sc = None if kind == "net" else lp.baseline_scores(c, kind, seed=5)
+        res, st = lp.search(s, d, K, keep_permille=100, scores=sc, fallback=False)
+        torch.cuda.synchronize()
+        out[f"recall_{kind}_no_fallback"] = round(topk_recall(exn, res.to_numpy()), 4)
+    for tau in (0.0, 0.25):
+        (res, st), t_pr = timed(lambda: lp.search(s, d, K, keep_permille=100, tau=tau), args.steps)
+        out[f"tau_{tau}"] = {"recall": round(topk_recall(exn, res.to_numpy()), 4), "fallback": st["fallback"],
+                             "queries_per_s": len(s) / t_pr}
+    log(f"pruner: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +224,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bytes", action="store_true")
+    ap.add_argument("--train-queries", type=int, default=200000, help="learned-pruner form: training queries")
+    ap.add_argument("--hidden", type=int, default=512, help="learned-pruner form: hidden width")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -223,6 +270,16 @@ def main():
     kk = kd if per_query_k else int(k[0])
 
     ev = HipEvents()
+    if args.config == "pruner":
+        pr = run_pruner(args, cfg, g, h, s, d)
+        print(json.dumps({"metric": "pruned top-K recall and queries/s at K=32 (learned pruner vs exact search)",
+                          "value": pr["tau_0.0"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                          "dtype": cfg.emb.dtype, "data": "synthetic",
+                          "config": {"workload": "pruner: Chung-Lu 4M vertices, 32 relations, 64M edges, d=256 bf16, "
+                                                 f"{len(s)} held-out queries, K={cfg.query.k}"},
+                          "pruner": pr}), flush=True)
+        return
     batched = {}
     if args.config == "batched":
         # the batched form: autotuned settings, one captured plan per batch
