@@ -148,7 +148,13 @@ typedef struct mhr_query_opts {
     uint32_t grid_blocks;  /* persistent gather workgroups (0 = default) */
     uint32_t hash_log2;    /* log2 of the LDS probe-table slots, 10..13 (0 = the largest of
                               10..12 whose workgroup fits in LDS) */
-    uint32_t reserved[8];  /* must be zero */
+    float band_abs;        /* minimum width of the rescoring band below the K-th score:
+                              every candidate with fast-pass score >= S_K - max(2 eps, band_abs)
+                              is rescored in float-float (0 = the rigorous band 2 eps alone, which
+                              already makes the result exact; a wider band costs time, and a band
+                              wider than the tile lists hold sends the query to the exhaustive
+                              pass).  Finite, >= 0. */
+    uint32_t reserved[7];  /* must be zero */
 } mhr_query_opts;
 
 /* Device workspace bytes needed by mhr_topk_paths for nq queries with

@@ -67,7 +67,7 @@ class PhaseEvents(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("tile_edges", ctypes.c_uint32),
                 ("grid_blocks", ctypes.c_uint32), ("hash_log2", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 8)]
+                ("band_abs", ctypes.c_float), ("reserved", ctypes.c_uint32 * 7)]
 
 
 _vp, _u32, _u64, _i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
@@ -288,7 +288,7 @@ class Graph:
         kt = None
         if k is None or isinstance(k, (int, np.integer)):
             kk = int(k if k is not None else o.k)
-            o = QueryOpts(kk, o.tile_edges, o.grid_blocks, o.hash_log2)
+            o = QueryOpts(kk, o.tile_edges, o.grid_blocks, o.hash_log2, o.band_abs)
             if k_max is None:
                 k_max = kk
         else:

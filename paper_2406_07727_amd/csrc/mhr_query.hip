@@ -62,6 +62,7 @@ struct GArgs {
     Cand *cands;
     uint32_t *exact_list;
     uint32_t tcap, hash_log2, nq, kc, tile_edges;
+    float band_abs;              // minimum rescoring band width below the K-th score
     const uint8_t *keep;         // pruned search: keep flags (nullptr: every entry kept)
     const uint64_t *keep_off;    // per query: offset of its flags in keep
 };
@@ -1364,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
     const float theta = c[kk - 1].s;
     const float eps = s_eps;
     // band threshold, rounded down generously
-    const float thr = (theta - 2.0f * eps) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
+    const float thr = (theta - fmaxf(2.0f * eps, A.band_abs)) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
     if (threadIdx.x == 0) {
         uint32_t over = s_drop >= thr ? 1u : 0u;
         for (uint32_t j = 0; j < P.ntiles && !over; ++j) {
@@ -1529,6 +1530,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
                       uint64_t *out_total, uint32_t *out_status, void *ws, hipStream_t st,
                       const mhr_phase_events *ev, const uint8_t *keep, const uint64_t *keep_off) {
     GArgs A = make_args(g);
+    A.band_abs = o ? o->band_abs : 0.0f;
     A.keep = keep;
     A.keep_off = keep_off;
     auto rec = [&](void *e) -> hipError_t {
@@ -1645,6 +1647,7 @@ mhr_status topk_impl(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, c
     if (o) {
         MHR_ARG_CHECK(o->hash_log2 == 0 || (o->hash_log2 >= 10 && o->hash_log2 <= 13), "hash_log2 must be 10..13");
         for (uint32_t v : o->reserved) MHR_ARG_CHECK(v == 0, "reserved option fields must be zero");
+        MHR_ARG_CHECK(o->band_abs >= 0.0f && o->band_abs <= 1e30f, "band_abs must be finite and >= 0");
     }
     const uint32_t kc = kc_for(kmax);
     const size_t need = ws_layout(nq, kc).total;

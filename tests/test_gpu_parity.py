@@ -382,3 +382,18 @@ def test_batched_full_size_sample():
     assert np.all((st & ~np.uint32(4)) == 0)
     assert np.all(c == np.minimum(kk, tot))
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["dense_tiny", "hub_r32_bf16"])
+def test_wide_rescoring_band_keeps_results(name):
+    """A fixed rescoring band of 1e-2 below the K-th score (the precision
+    form's margin): far wider than the rigorous band, so most queries take
+    the exhaustive float-float pass; the results still equal the oracle's."""
+    import paper_2406_07727_amd as mhr
+    cfg = kgsynth.CONFIGS[name]
+    opts = mhr.QueryOpts()
+    opts.band_abs = 1e-2
+    gpu, orc = _small(name, opts=opts)
+    compare(gpu, orc)
+    if name == "hub_r32_bf16":   # d = 64: the band holds most paths, beyond the tile lists
+        assert np.sum((gpu[3] & 4) != 0) > 0
