@@ -146,7 +146,7 @@ typedef struct mhr_query_opts {
     uint32_t k;            /* K for every query when the per-query array is NULL */
     uint32_t tile_edges;   /* scan entries per work tile (0 = default) */
     uint32_t grid_blocks;  /* persistent gather workgroups (0 = default) */
-    uint32_t hash_log2;    /* log2 of the LDS probe-table slots, 10..13 (0 = the largest of
+    uint32_t hash_log2;    /* log2 of the LDS probe-table slots, 10..12 (0 = the largest of
                               10..12 whose workgroup fits in LDS) */
     float band_abs;        /* minimum width of the rescoring band below the K-th score:
                               every candidate with fast-pass score >= S_K - max(2 eps, band_abs)

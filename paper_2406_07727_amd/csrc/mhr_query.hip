@@ -42,7 +42,8 @@ constexpr int kBlock = 512;
 constexpr int kEPT = 4;                   // scan entries per thread per chunk
 constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
-constexpr int kSlab = 1024;               // scored edge values per sub-batch
+constexpr int kSlab = 2560;               // scored edge values per sub-batch
+constexpr int kQueue = kChunk + kBlock;    // queued matches: a partial sub-batch plus one chunk's hits
 constexpr int kStage = 768;               // staged candidates before a merge
 constexpr uint32_t kMaxQuota = 8;         // candidates a thread stages per round
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
@@ -80,6 +81,7 @@ __device__ inline const uint8_t *keep_row(const GArgs &A, uint32_t q, uint32_t s
 
 constexpr uint32_t kMaxTilesPerQuery = 4096;
 constexpr uint32_t kMergeSlots = 2048;      // LDS candidates per merge step
+constexpr uint32_t kSpan = 16;              // embedding elements a scoring lane holds per step
 
 // Tiles the workspace holds for nq queries.
 __host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
@@ -418,7 +420,7 @@ struct GatherShared {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 struct GatherLayout {
-    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, qy, sub, slab, slab_eps, list, stage,
+    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, qy, sub, slab, list, stage,
         ymax, rowrel, slab_rel, agg, shared, total;
 };
 
@@ -436,13 +438,12 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     L.rows = o; o = align16(o + kRowBatch * sizeof(RowInfo));
     L.rowval = o; o = align16(o + size_t(kRowBatch) * R * 4);
     L.roweps = o; o = align16(o + size_t(kRowBatch) * R * 4);
-    L.qpos = o; o = align16(o + kChunk * 4);
-    L.qmp = o; o = align16(o + kChunk * 4);
-    L.qy = o; o = align16(o + kChunk * 4);
+    L.qpos = o; o = align16(o + kQueue * 4);
+    L.qmp = o; o = align16(o + kQueue * 4);
+    L.qy = o; o = align16(o + kQueue * 4);
     L.sub = o; o = align16(o + kBlock * kSubFields * 4);
     L.agg = o; o = align16(o + kBlock * 6 * 4);
     L.slab = o; o = align16(o + kSlab * 4);
-    L.slab_eps = o; o = align16(o + kSlab * 4);
     L.list = o; o = align16(o + size_t(kc) * sizeof(Cand));
     L.stage = o; o = align16(o + size_t(next_pow2(kStage + kc)) * sizeof(Cand));
     L.ymax = o; o = align16(o + size_t(R) * 4);
@@ -570,18 +571,18 @@ __device__ __forceinline__ void split_bf16(float v, uint32_t &hi, uint32_t &lo) 
     lo = __float_as_uint(v - __uint_as_float(b & 0xFFFF0000u)) >> 16;
 }
 
-// Up to 32 consecutive elements [off, off + n) of an embedding row (zeros
+// Up to S consecutive elements [off, off + n) of an embedding row (zeros
 // past n, or everywhere when !valid).  n is a multiple of 2 and off of n's
-// alignment: the loads are 16-byte vectors when n >= 4 (FP32) / 8 (BF16).
-template <bool BF16>
-__device__ __forceinline__ void load_span32(const void *base, uint32_t row, uint32_t d, uint32_t off, uint32_t n,
-                                            bool valid, float (&v)[32]) {
+// alignment: the loads are 16-byte vectors when n == S.
+template <bool BF16, int S>
+__device__ __forceinline__ void load_span(const void *base, uint32_t row, uint32_t d, uint32_t off, uint32_t n,
+                                          bool valid, float (&v)[S]) {
 #pragma unroll
-    for (int l = 0; l < 32; ++l) v[l] = 0.0f;
+    for (int l = 0; l < S; ++l) v[l] = 0.0f;
     if (!valid) return;
-    if (n == 32) {
+    if (n == static_cast<uint32_t>(S)) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < S / 8; ++c) {
             float t[8];
             load8<BF16>(base, row, d, off + 8 * c, t);
 #pragma unroll
@@ -589,7 +590,7 @@ __device__ __forceinline__ void load_span32(const void *base, uint32_t row, uint
         }
     } else {
 #pragma unroll
-        for (int l = 0; l < 32; ++l)
+        for (int l = 0; l < S; ++l)
             if (static_cast<uint32_t>(l) < n) v[l] = load1<BF16>(base, static_cast<size_t>(row) * d + off + l);
     }
 }
@@ -635,7 +636,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     uint32_t *qy = reinterpret_cast<uint32_t *>(smem + Lo.qy);
     uint32_t *sub = reinterpret_cast<uint32_t *>(smem + Lo.sub);
     float *slab = reinterpret_cast<float *>(smem + Lo.slab);
-    float *slab_eps = reinterpret_cast<float *>(smem + Lo.slab_eps);
     Cand *list = reinterpret_cast<Cand *>(smem + Lo.list);
     Cand *stage = reinterpret_cast<Cand *>(smem + Lo.stage);
     GatherShared *sh = reinterpret_cast<GatherShared *>(smem + Lo.shared);
@@ -815,10 +815,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             __syncthreads();
             const uint32_t E = sh->E;
 
-            // ---- chunks of scanned entries
+            // ---- chunks of scanned entries.  Matches queue up across chunks
+            // until a full sub-batch is ready (all of them after the last
+            // chunk of the row batch).
+            if (tid == 0) sh->qcount = 0;
+            __syncthreads();
             for (uint32_t cb = 0; cb < E; cb += kChunk) {
-                if (tid == 0) sh->qcount = 0;
-                __syncthreads();
+                const bool last = cb + kChunk >= E;
                 uint32_t ys[kEPT], ps[kEPT], mps[kEPT];
                 bool hits[kEPT];
 #pragma unroll
@@ -884,7 +887,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 const uint32_t nmatch = sh->qcount;
 
                 // ---- sub-batches of at most kBlock matches (value slab permitting)
-                for (uint32_t m0 = 0; m0 < nmatch;) {
+                uint32_t m0 = 0;
+                while (m0 < nmatch && (last || nmatch - m0 >= static_cast<uint32_t>(kBlock))) {
                     const uint32_t mi = m0 + tid;
                     uint32_t pos = 0, y = 0, mp = 0, mm = 0, row = 0, nv2 = 0;
                     if (mi < nmatch) {
@@ -948,17 +952,17 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 aM[rb] = aP[rb];
                             }
                             float sup = 0.0f, sum_ = 0.0f;  // sum_k |up|, sum_k |um| over this lane's slice
-                            for (uint32_t kb = 0; kb < KCH; kb += 32) {
+                            for (uint32_t kb = 0; kb < KCH; kb += kSpan) {
                                 const uint32_t off = static_cast<uint32_t>(kq) * KCH + kb;
-                                const uint32_t kn = KCH - kb < 32 ? KCH - kb : 32;
-                                float ey[32], ex[32];
-                                load_span32<BF16>(A.X, yrow, d, off, kn, mval, ey);
-                                load_span32<BF16>(A.X, xrow, d, off, kn, mval, ex);
+                                const uint32_t kn = KCH - kb < kSpan ? KCH - kb : kSpan;
+                                float ey[kSpan], ex[kSpan];
+                                load_span<BF16, kSpan>(A.X, yrow, d, off, kn, mval, ey);
+                                load_span<BF16, kSpan>(A.X, xrow, d, off, kn, mval, ex);
                                 if constexpr (BF16) {
                                     // four elements per lane per step: A = [hi(u) | lo(u)] and
                                     // B = [y | y] as 8 bfloat16 each, K = 32 per instruction
 #pragma unroll
-                                    for (uint32_t j = 0; j < 32; j += 4) {
+                                    for (uint32_t j = 0; j < kSpan; j += 4) {
                                         if (j < kn) {
                                             u32x4 wp, wm;
 #pragma unroll
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     }
                                 } else {
 #pragma unroll
-                                for (uint32_t j = 0; j < 32; ++j) {
+                                for (uint32_t j = 0; j < kSpan; ++j) {
                                     if (j < kn) {
                                         const float up = ey[j] * anc_p[off + j];
                                         const float um = ey[j] * ex[j];
@@ -1219,6 +1223,25 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     m0 += ncnt;
                     __syncthreads();
                 }
+                // the remaining matches (fewer than a sub-batch) move to the
+                // queue's front; the next chunk appends after them
+                const uint32_t rem = nmatch - m0;
+                if (rem > 0 && m0 > 0) {
+                    uint32_t p_ = 0, mp_ = 0, y_ = 0;
+                    if (tid < rem) {
+                        p_ = qpos[m0 + tid];
+                        mp_ = qmp[m0 + tid];
+                        y_ = qy[m0 + tid];
+                    }
+                    __syncthreads();
+                    if (tid < rem) {
+                        qpos[tid] = p_;
+                        qmp[tid] = mp_;
+                        qy[tid] = y_;
+                    }
+                }
+                if (tid == 0) sh->qcount = rem;
+                __syncthreads();
             }
             __syncthreads();  // rows[] and sh->E are rewritten by the next batch
         }
@@ -1645,7 +1668,7 @@ mhr_status topk_impl(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, c
     MHR_ARG_CHECK(src && dst && out && out_count && workspace, "mhr_topk_paths: null pointer");
     MHR_ARG_CHECK(k != nullptr || (o && o->k >= 1 && o->k <= kmax), "opts->k must be in [1, k_max] when k is NULL");
     if (o) {
-        MHR_ARG_CHECK(o->hash_log2 == 0 || (o->hash_log2 >= 10 && o->hash_log2 <= 13), "hash_log2 must be 10..13");
+        MHR_ARG_CHECK(o->hash_log2 == 0 || (o->hash_log2 >= 10 && o->hash_log2 <= 12), "hash_log2 must be 10..12");
         for (uint32_t v : o->reserved) MHR_ARG_CHECK(v == 0, "reserved option fields must be zero");
         MHR_ARG_CHECK(o->band_abs >= 0.0f && o->band_abs <= 1e30f, "band_abs must be finite and >= 0");
     }

@@ -135,7 +135,7 @@ def test_tiling_and_grid_do_not_change_results():
     say("case tiling invariance")
     g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y)
     ref = run_gpu(g, s, d, 16)
-    for te, gb, hl in ((64, 3, 10), (500, 7, 11), (1 << 20, 1, 13), (0, 0, 0)):
+    for te, gb, hl in ((64, 3, 10), (500, 7, 11), (1 << 20, 1, 12), (0, 0, 0)):
         got = run_gpu(g, s, d, 16, opts=mhr.QueryOpts(0, te, gb, hl))
         for a, b in zip(ref, got):
             assert np.array_equal(a, b), (te, gb, hl)
