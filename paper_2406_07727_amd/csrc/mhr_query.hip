@@ -1137,87 +1137,96 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         const uint32_t iincl = block_incl_scan<uint32_t>(nitems, sh->red32, &ntot);
                         sub_item[tid] = iincl - nitems;
                         __syncthreads();
-                        for (uint32_t w0 = 0; w0 < ntot; w0 += kBlock) {
-                            const uint32_t it = w0 + tid;
-                            bool done = it >= ntot;
-                            uint32_t il = 0, nl = 0, lb = 0, sx = 0, sy = 0, rp_ = 0, rm_ = 0;
-                            float fp = 0.0f, fm = 0.0f;
-                            if (!done) {
-                                // the last match whose items start at or before `it`
-                                uint32_t lo = 0, hi = ncnt;
-                                while (hi - lo > 1) {
-                                    const uint32_t mid = (lo + hi) >> 1;
-                                    if (sub_item[mid] <= it) lo = mid; else hi = mid;
+                        // Each thread walks the items tid, tid + kBlock, ...; its cursor
+                        // (item, list position) survives the rounds, so a round ends
+                        // only when the stage quota is used up or the items run out.
+                        uint32_t it = tid;
+                        bool have = false;
+                        uint32_t il = 0, nl = 0, lb = 0, sx = 0, sy = 0, rp_ = 0, rm_ = 0;
+                        float fp = 0.0f, fm = 0.0f;
+                        // threads that still hold items (bounds the emitters of a round)
+                        uint32_t nact = ntot < static_cast<uint32_t>(kBlock) ? ntot : static_cast<uint32_t>(kBlock);
+                        while (nact > 0) {
+                            // the free stage slots are shared by the threads still
+                            // walking (at least one each)
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC>(list, stage, sh);
+                            uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
+                            if (quota > kMaxQuota) quota = kMaxQuota;
+                            const Cand thr = sh->thr;
+                            const float tS = EXACT ? thr_exact : thr.s;
+                            uint32_t emitted = 0;
+                            bool dropped = false;
+                            while (emitted < quota) {
+                                if (!have) {
+                                    if (it >= ntot) break;
+                                    // the last match whose items start at or before `it`
+                                    uint32_t lo = 0, hi = ncnt;
+                                    while (hi - lo > 1) {
+                                        const uint32_t mid = (lo + hi) >> 1;
+                                        if (sub_item[mid] <= it) lo = mid; else hi = mid;
+                                    }
+                                    const uint32_t m = lo;
+                                    const uint32_t np = __popc(sub_mp[m]), nm = __popc(sub_mm[m]);
+                                    const uint32_t l = it - sub_item[m];
+                                    const uint32_t ip = l / nm, im = l - ip * nm;
+                                    const uint32_t vo = sub_voff[m];
+                                    fp = slab[vo + ip];
+                                    fm = slab[vo + np + im];
+                                    const RowInfo &ri = rows[sub_row[m]];
+                                    if (combine3(fwd, fp, fm, ri.fmax) < tS) {
+                                        dropped = true;   // every path of this pair of values
+                                        it += kBlock;
+                                        continue;
+                                    }
+                                    rp_ = slab_rel[vo + ip];
+                                    rm_ = slab_rel[vo + np + im];
+                                    lb = ri.vbase;
+                                    nl = __popc(ri.mask);
+                                    sx = ri.x;
+                                    sy = sub_y[m];
+                                    il = 0;
+                                    have = true;
                                 }
-                                const uint32_t m = lo;
-                                const uint32_t np = __popc(sub_mp[m]), nm = __popc(sub_mm[m]);
-                                const uint32_t l = it - sub_item[m];
-                                const uint32_t ip = l / nm, im = l - ip * nm;
-                                const uint32_t vo = sub_voff[m];
-                                fp = slab[vo + ip];
-                                fm = slab[vo + np + im];
-                                rp_ = slab_rel[vo + ip];
-                                rm_ = slab_rel[vo + np + im];
-                                const RowInfo &ri = rows[sub_row[m]];
-                                lb = ri.vbase;
-                                nl = __popc(ri.mask);
-                                sx = ri.x;
-                                sy = sub_y[m];
-                                const float tS0 = EXACT ? thr_exact : sh->thr.s;
-                                if (combine3(fwd, fp, fm, ri.fmax) < tS0) {
-                                    done = true;   // every path of this pair of values
-                                    sh->truncated = 1;
+                                if (il >= nl) {
+                                    have = false;
+                                    it += kBlock;
+                                    continue;
+                                }
+                                const float fl = rowval[lb + il];
+                                const float S = combine3(fwd, fp, fm, fl);
+                                if (S < tS) {
+                                    dropped = true;   // this and every later list value
+                                    have = false;
+                                    it += kBlock;
+                                    continue;
+                                }
+                                const uint32_t rl_ = rowrel[lb + il];
+                                ++il;
+                                Cand cd;
+                                cd.a = fwd ? sx : sy;
+                                cd.b = fwd ? sy : sx;
+                                const uint32_t r1 = fwd ? rl_ : rp_, r3 = fwd ? rp_ : rl_;
+                                cd.rel = (r1 << 16) | (rm_ << 8) | r3;
+                                cd.s = S;
+                                cd.s_lo = 0.0f;
+                                cd.eps = 0.0f;
+                                if (EXACT) {
+                                    float e2;
+                                    ff sc = path_score_ff<BF16, false>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
+                                    cd.s = sc.hi;
+                                    cd.s_lo = sc.lo;
+                                    cd.eps = e2;
+                                }
+                                if (cand_better(cd, thr)) {
+                                    uint32_t slot = atomicAdd(&sh->stage_n, 1u);
+                                    stage[slot] = cd;
+                                    ++emitted;
+                                } else {
+                                    dropped = true;
                                 }
                             }
-                            int active = __syncthreads_count(!done);
-                            while (active > 0) {
-                                // the free stage slots are shared by the items still
-                                // walking (at least one each)
-                                if (sh->stage_n + static_cast<uint32_t>(active) > static_cast<uint32_t>(kStage))
-                                    merge_stage<KC>(list, stage, sh);
-                                uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / static_cast<uint32_t>(active);
-                                if (quota > kMaxQuota) quota = kMaxQuota;
-                                const Cand thr = sh->thr;
-                                const float tS = EXACT ? thr_exact : thr.s;
-                                uint32_t emitted = 0;
-                                bool dropped = false;
-                                while (!done && emitted < quota) {
-                                    if (il >= nl) { done = true; break; }
-                                    const float fl = rowval[lb + il];
-                                    const float S = combine3(fwd, fp, fm, fl);
-                                    if (S < tS) {
-                                        dropped = true;   // this and every later list value
-                                        done = true;
-                                        break;
-                                    }
-                                    const uint32_t rl_ = rowrel[lb + il];
-                                    ++il;
-                                    Cand cd;
-                                    cd.a = fwd ? sx : sy;
-                                    cd.b = fwd ? sy : sx;
-                                    const uint32_t r1 = fwd ? rl_ : rp_, r3 = fwd ? rp_ : rl_;
-                                    cd.rel = (r1 << 16) | (rm_ << 8) | r3;
-                                    cd.s = S;
-                                    cd.s_lo = 0.0f;
-                                    cd.eps = 0.0f;
-                                    if (EXACT) {
-                                        float e2;
-                                        ff sc = path_score_ff<BF16, false>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
-                                        cd.s = sc.hi;
-                                        cd.s_lo = sc.lo;
-                                        cd.eps = e2;
-                                    }
-                                    if (cand_better(cd, thr)) {
-                                        uint32_t slot = atomicAdd(&sh->stage_n, 1u);
-                                        stage[slot] = cd;
-                                        ++emitted;
-                                    } else {
-                                        dropped = true;
-                                    }
-                                }
-                                if (dropped) sh->truncated = 1;
-                                active = __syncthreads_count(!done);
-                            }
+                            if (dropped) sh->truncated = 1;
+                            nact = static_cast<uint32_t>(__syncthreads_count(it < ntot));
                         }
                     }
                     m0 += ncnt;
