@@ -534,26 +534,79 @@ __device__ inline void score_values(const float (&a)[8], float suma, uint32_t ma
 }
 
 // Merge the staged candidates into the kept list (whole block).
-template <int KC>
-__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh) {
+// Order-preserving integer key of an FP32 score.
+__device__ __forceinline__ uint32_t fkey(float x) {
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Merges the staged candidates into the tile's list.
+// Fast pass: the best KC of list + stage by fast-pass score, in descending
+// score order (ties in any order: a tie at the list's end marks the tile
+// truncated at that score, and the band is re-sorted by the total order
+// after rescoring).  The bitonic sort runs on 8-byte keys (score key, slot)
+// in `keys` (next_pow2(kStage + KC) entries); only the KC winners are
+// gathered.
+// Exhaustive pass (EXACT): the scores are final, so the list keeps the best
+// KC under the total order (score, then ids) and the whole candidates are
+// sorted.
+template <int KC, bool EXACT>
+__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint64_t *keys) {
     const uint32_t ns = sh->stage_n;
     const uint32_t tot = ns + KC;
     const uint32_t n2 = next_pow2(tot);
-    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-        if (i >= ns && i < tot) stage[i] = list[i - ns];
-        else if (i >= tot) stage[i] = cand_sentinel();
+    if (EXACT) {
+        for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+            if (i >= ns && i < tot) stage[i] = list[i - ns];
+            else if (i >= tot) stage[i] = cand_sentinel();
+        }
+        __syncthreads();
+        block_sort_cands(stage, static_cast<int>(n2));
+        if (threadIdx.x == 0) {
+            if (stage[KC].a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
+            uint32_t cnt = sh->list_n + ns;
+            sh->list_n = cnt < static_cast<uint32_t>(KC) ? cnt : KC;
+            sh->stage_n = 0;
+            sh->thr = (sh->list_n == static_cast<uint32_t>(KC)) ? stage[KC - 1] : cand_sentinel();
+        }
+        for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) list[i] = stage[i];
+        __syncthreads();
+        return;
     }
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) stage[ns + i] = list[i];
     __syncthreads();
-    block_sort_cands(stage, static_cast<int>(n2));
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x)
+        keys[i] = i < tot ? (static_cast<uint64_t>(fkey(stage[i].s)) << 32) | i : 0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                const uint32_t p = i ^ j;
+                if (p > i) {
+                    const uint64_t x = keys[i], y = keys[p];
+                    const bool desc = (i & k) == 0;   // this half ends highest-first
+                    if (desc ? (x < y) : (x > y)) {
+                        keys[i] = y;
+                        keys[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
     if (threadIdx.x == 0) {
-        Cand c = stage[KC];
-        if (c.a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
+        const uint64_t kk = keys[KC];
+        if (kk != 0ull && stage[static_cast<uint32_t>(kk)].a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
         uint32_t cnt = sh->list_n + ns;
         sh->list_n = cnt < static_cast<uint32_t>(KC) ? cnt : KC;
         sh->stage_n = 0;
-        sh->thr = (sh->list_n == static_cast<uint32_t>(KC)) ? stage[KC - 1] : cand_sentinel();
     }
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) list[i] = stage[i];
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) {
+        const uint64_t kk = keys[i];
+        list[i] = kk != 0ull ? stage[static_cast<uint32_t>(kk)] : cand_sentinel();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sh->thr = (sh->list_n == static_cast<uint32_t>(KC)) ? list[KC - 1] : cand_sentinel();
     __syncthreads();
 }
 
@@ -1149,7 +1202,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         while (nact > 0) {
                             // the free stage slots are shared by the threads still
                             // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC>(list, stage, sh);
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT>(list, stage, sh, reinterpret_cast<uint64_t *>(agg));
                             uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
@@ -1256,7 +1309,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         // ---- tile end: final merge and output
         __syncthreads();
-        if (sh->stage_n > 0) merge_stage<KC>(list, stage, sh);
+        if (sh->stage_n > 0) merge_stage<KC, EXACT>(list, stage, sh, reinterpret_cast<uint64_t *>(agg));
         float em = block_max(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
