@@ -368,9 +368,21 @@ __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint3
         x2 = edge_x_ff<BF16>(A, a, r2, b, &as2);
         x3 = edge_x_ff<BF16>(A, b, r3, t, &as3);
     }
-    ff w1 = ff_logsigmoid(x1);
-    ff w2 = ff_logsigmoid(x2);
-    ff w3 = ff_logsigmoid(x3);
+    ff w1, w2, w3;
+    if (WAVE) {
+        // lanes 0, 1, 2 (mod 3) take one log-sigmoid each; every lane then
+        // reads all three
+        const int lane = static_cast<int>(threadIdx.x & (kWave - 1));
+        const int e = lane % 3;
+        const ff w = ff_logsigmoid(e == 0 ? x1 : (e == 1 ? x2 : x3));
+        w1 = ff{__shfl(w.hi, 0, kWave), __shfl(w.lo, 0, kWave)};
+        w2 = ff{__shfl(w.hi, 1, kWave), __shfl(w.lo, 1, kWave)};
+        w3 = ff{__shfl(w.hi, 2, kWave), __shfl(w.lo, 2, kWave)};
+    } else {
+        w1 = ff_logsigmoid(x1);
+        w2 = ff_logsigmoid(x2);
+        w3 = ff_logsigmoid(x3);
+    }
     // Sum in a canonical order (descending) so that the result depends only
     // on the multiset of weights: paths whose weights are permutations of
     // each other (DistMult is symmetric) then tie exactly, as their real
