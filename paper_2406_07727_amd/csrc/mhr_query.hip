@@ -885,10 +885,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             // chunk of the row batch).
             if (tid == 0) sh->qcount = 0;
             __syncthreads();
-            for (uint32_t cb = 0; cb < E; cb += kChunk) {
-                const bool last = cb + kChunk >= E;
-                uint32_t ys[kEPT], ps[kEPT], mps[kEPT];
-                bool hits[kEPT];
+            // positions and column ids of a chunk's entries; a chunk's ids are
+            // loaded while the previous chunk is probed
+            auto chunk_entries = [&](uint32_t cb, uint32_t (&ps)[kEPT], uint32_t (&ys)[kEPT]) {
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
                     uint32_t e = cb + k * kBlock + tid;
@@ -904,6 +903,19 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 }
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) ys[k] = (ps[k] != kEmpty) ? Lcol[ps[k]] : kEmpty;
+            };
+            uint32_t ps_n[kEPT], ys_n[kEPT];
+            chunk_entries(0, ps_n, ys_n);
+            for (uint32_t cb = 0; cb < E; cb += kChunk) {
+                const bool last = cb + kChunk >= E;
+                uint32_t ys[kEPT], ps[kEPT], mps[kEPT];
+                bool hits[kEPT];
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) {
+                    ps[k] = ps_n[k];
+                    ys[k] = ys_n[k];
+                }
+                if (!last) chunk_entries(cb + kChunk, ps_n, ys_n);
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
                     hits[k] = false;
