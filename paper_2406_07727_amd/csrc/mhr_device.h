@@ -161,6 +161,33 @@ __device__ __forceinline__ float centred_logsigmoid(float x) {
 // covers the composition).
 __device__ __forceinline__ float centred_logsigmoid_err(float f) { return 16.0f * kUnit * fabsf(f); }
 
+// The centred log-sigmoid with a rigorous bound on its FP32 error, for the
+// fast pass.  For |x| <= 1/2 it uses f(x) = x/2 - log cosh(x/2) and the
+// Taylor series of log cosh(y) (y = x/2, z = y^2):
+//     z/2 - z^2/12 + z^3/45 - 17 z^4/2520 + 31 z^5/14175 - ...
+// alternating with decreasing terms for |y| < pi/2; the first omitted term,
+// 691 z^6/467775, is below 1e-10 for |y| <= 1/4.  Horner's rule in z costs
+// five fused multiply-adds; its rounding error (the rounded constants, z,
+// each step and the final subtraction) stays below 16 u (|x|/2 + z).
+// Larger |x| (rare: x has a spread of about 1/d) take the library path.
+__device__ __forceinline__ float centred_logsigmoid_e(float x, float &err) {
+    if (fabsf(x) <= 0.5f) {
+        const float y = 0.5f * x;
+        const float z = y * y;
+        float lc = 31.0f / 14175.0f;
+        lc = fmaf(lc, z, -17.0f / 2520.0f);
+        lc = fmaf(lc, z, 1.0f / 45.0f);
+        lc = fmaf(lc, z, -1.0f / 12.0f);
+        lc = fmaf(lc, z, 0.5f);
+        lc = lc * z;
+        err = 16.0f * kUnit * (fabsf(y) + z) + 1e-10f;
+        return y - lc;
+    }
+    const float f = centred_logsigmoid(x);
+    err = centred_logsigmoid_err(f);
+    return f;
+}
+
 // gamma_n = n u / (1 - n u): the classical bound factor for n roundings.
 __device__ __forceinline__ float gamma_n(int n) {
     float nu = static_cast<float>(n) * kUnit;

@@ -537,9 +537,10 @@ __device__ inline void score_values(const float (&a)[8], float suma, uint32_t ma
             const float x = glane == 0 ? part[0] : glane == 1 ? part[1] : glane == 2 ? part[2] : part[3];
             const uint32_t r = glane == 0 ? rel[0] : glane == 1 ? rel[1] : glane == 2 ? rel[2] : rel[3];
             const bool ia = glane == 0 ? isa[0] : glane == 1 ? isa[1] : glane == 2 ? isa[2] : isa[3];
-            const float f = centred_logsigmoid(x);
+            float fe;
+            const float f = centred_logsigmoid_e(x, fe);
             out[c + glane] = f;
-            out_eps[c + glane] = gam * ymax[r] * (ia ? suma : sumb) + centred_logsigmoid_err(f);
+            out_eps[c + glane] = gam * ymax[r] * (ia ? suma : sumb) + fe;
             out_rel[c + glane] = static_cast<uint8_t>(r);
         }
     }
@@ -1133,12 +1134,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
                                     if (rb < nrb && mv && r < R) {
                                         if ((smp >> r) & 1u) {
-                                            fP[rb] = centred_logsigmoid(aP[rb][i]);
-                                            eP[rb] = gam * ymax[r] * su_p + centred_logsigmoid_err(fP[rb]);
+                                            float fe;
+                                            fP[rb] = centred_logsigmoid_e(aP[rb][i], fe);
+                                            eP[rb] = gam * ymax[r] * su_p + fe;
                                         }
                                         if ((smm >> r) & 1u) {
-                                            fM[rb] = centred_logsigmoid(aM[rb][i]);
-                                            eM[rb] = gam * ymax[r] * su_m + centred_logsigmoid_err(fM[rb]);
+                                            float fe;
+                                            fM[rb] = centred_logsigmoid_e(aM[rb][i], fe);
+                                            eM[rb] = gam * ymax[r] * su_m + fe;
                                         }
                                     }
                                 }
@@ -1567,10 +1570,10 @@ __global__ void edge_weight_kernel(GArgs A, uint64_t ne, const uint32_t *u, cons
         x = __builtin_fmaf(z, xv, x);
         as += fabsf(z * xv);
     }
-    float f = centred_logsigmoid(x);
+    float fe;
+    float f = centred_logsigmoid_e(x, fe);   // the fast pass's evaluation and bound
     float w = f - kLn2f;
-    float err = gamma_n(static_cast<int>(A.d) + 2) * as + centred_logsigmoid_err(f) + kUnit * fabsf(w) +
-                kUnit * kLn2f;
+    float err = gamma_n(static_cast<int>(A.d) + 2) * as + fe + kUnit * fabsf(w) + kUnit * kLn2f;
     if (w32) w32[i] = w;
     if (e32) e32[i] = err;
     float asf;
