@@ -661,6 +661,22 @@ __device__ __forceinline__ void load_span(const void *base, uint32_t row, uint32
     }
 }
 
+// S consecutive LDS floats p[0 .. n) (zeros past n): 16-byte reads when
+// n == S (p is then 16-byte aligned), single reads otherwise.
+template <int S>
+__device__ __forceinline__ void lds_span(const float *p, uint32_t n, float (&v)[S]) {
+    if (n == static_cast<uint32_t>(S)) {
+#pragma unroll
+        for (int c = 0; c < S / 4; ++c) {
+            const float4 t = *reinterpret_cast<const float4 *>(p + 4 * c);
+            v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < S; ++l) v[l] = static_cast<uint32_t>(l) < n ? p[l] : 0.0f;
+    }
+}
+
 // Insertion sort of n (<= 32) values into descending order, carrying their
 // relation ids.  Equal values keep their relation order.
 __device__ inline void sort_desc(float *v, uint8_t *rel, uint32_t n) {
@@ -1036,6 +1052,20 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 float ey[kSpan], ex[kSpan];
                                 load_span<BF16, kSpan>(A.X, yrow, d, off, kn, mval, ey);
                                 load_span<BF16, kSpan>(A.X, xrow, d, off, kn, mval, ex);
+                                // this lane's slices of the anchor row and of its
+                                // relation rows, from LDS into registers
+                                float av[kSpan], yb[2][kSpan];
+                                lds_span<kSpan>(anc_p + off, kn, av);
+#pragma unroll
+                                for (uint32_t rb = 0; rb < 2; ++rb) {
+                                    const uint32_t rr = rb * 16 + static_cast<uint32_t>(mrow);
+                                    if (rb < nrb && rr < R) {
+                                        lds_span<kSpan>(Ys + rr * ystr + off, kn, yb[rb]);
+                                    } else {
+#pragma unroll
+                                        for (int l = 0; l < static_cast<int>(kSpan); ++l) yb[rb][l] = 0.0f;
+                                    }
+                                }
                                 if constexpr (BF16) {
                                     // four elements per lane per step: A = [hi(u) | lo(u)] and
                                     // B = [y | y] as 8 bfloat16 each, K = 32 per instruction
@@ -1049,7 +1079,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
 #pragma unroll
                                                 for (uint32_t h = 0; h < 2; ++h) {
                                                     const bool ok = j + e + h < kn;
-                                                    const float up = ok ? ey[j + e + h] * anc_p[off + j + e + h] : 0.0f;
+                                                    const float up = ok ? ey[j + e + h] * av[j + e + h] : 0.0f;
                                                     const float um = ok ? ey[j + e + h] * ex[j + e + h] : 0.0f;
                                                     sup += fabsf(up);
                                                     sum_ += fabsf(um);
@@ -1067,15 +1097,15 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                             for (uint32_t rb = 0; rb < 2; ++rb) {
                                                 if (rb < nrb) {
                                                     const uint32_t rr = rb * 16 + static_cast<uint32_t>(mrow);
-                                                    uint32_t yb[4];
+                                                    uint32_t ybits[4];
 #pragma unroll
                                                     for (uint32_t e = 0; e < 4; ++e)
-                                                        yb[e] = (rr < R && j + e < kn)
-                                                                    ? __float_as_uint(Ys[rr * ystr + off + j + e]) >> 16
-                                                                    : 0u;
+                                                        ybits[e] = (rr < R && j + e < kn)
+                                                                       ? __float_as_uint(yb[rb][j + e]) >> 16
+                                                                       : 0u;
                                                     u32x4 wy;
-                                                    wy[0] = yb[0] | (yb[1] << 16);
-                                                    wy[1] = yb[2] | (yb[3] << 16);
+                                                    wy[0] = ybits[0] | (ybits[1] << 16);
+                                                    wy[1] = ybits[2] | (ybits[3] << 16);
                                                     wy[2] = wy[0];
                                                     wy[3] = wy[1];
                                                     const bf16x8 bv = __builtin_bit_cast(bf16x8, wy);
@@ -1089,15 +1119,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
 #pragma unroll
                                 for (uint32_t j = 0; j < kSpan; ++j) {
                                     if (j < kn) {
-                                        const float up = ey[j] * anc_p[off + j];
+                                        const float up = ey[j] * av[j];
                                         const float um = ey[j] * ex[j];
                                         sup += fabsf(up);
                                         sum_ += fabsf(um);
 #pragma unroll
                                         for (uint32_t rb = 0; rb < 2; ++rb) {
                                             if (rb < nrb) {
-                                                const uint32_t rr = rb * 16 + static_cast<uint32_t>(mrow);
-                                                const float yv = rr < R ? Ys[rr * ystr + off + j] : 0.0f;
+                                                const float yv = yb[rb][j];
                                                 aP[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(up, yv, aP[rb], 0, 0, 0);
                                                 aM[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(um, yv, aM[rb], 0, 0, 0);
                                             }
