@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # fetched (scale 2.0), WRITE_SIZE read 1048576 KiB (scale 1.0).  Valid only
 # for the kernel sources they were taken on (sha256 over the query sources).
 TRAFFIC = {
-    "sources_sha256": "8be38f94cb087c9d158f1b5a5d76e69a3a50afde6ba844a7a2e850b856083670",
-    "fetch_kib": 457324.9,
-    "write_kib": 3020.4,
+    "sources_sha256": "021b13b1efd06756f368bc3b3dffb68f26512c4ac1d5c635df90d3d58259ac8e",
+    "fetch_kib": 454481.6,
+    "write_kib": 3020.2,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
