@@ -82,6 +82,7 @@ __device__ inline const uint8_t *keep_row(const GArgs &A, uint32_t q, uint32_t s
 constexpr uint32_t kMaxTilesPerQuery = 4096;
 constexpr uint32_t kMergeSlots = 2048;      // LDS candidates per merge step
 constexpr uint32_t kSpan = 16;              // embedding elements a scoring lane holds per step
+constexpr int kRescoreLanes = 16;           // lanes that rescore one band candidate together
 
 // Tiles the workspace holds for nq queries.
 __host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
@@ -323,17 +324,18 @@ __device__ inline ff edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t 
     return acc;
 }
 
-// The same sum computed by one wave: lane l takes the terms l, l + 64, ...,
-// and a butterfly combines the lane sums (ff_add is symmetric in its
-// operands, so every lane ends with the same bits).  No term passes through
+// The same sum computed by an aligned group of G lanes (a power of two, at
+// most a wave): lane l of the group takes the terms l, l + G, ..., and a
+// butterfly combines the lane sums (ff_add is symmetric in its operands, so
+// every lane of the group ends with the same bits).  No term passes through
 // more than d float-float additions, so the error bound of the sequential
 // sum holds.
-template <bool BF16>
-__device__ inline ff wave_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
+template <bool BF16, int G>
+__device__ inline ff group_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
     ff acc = {0.0f, 0.0f};
     float as = 0.0f;
     const size_t d = A.d;
-    for (uint32_t i = threadIdx.x & (kWave - 1); i < A.d; i += kWave) {
+    for (uint32_t i = threadIdx.x & (G - 1); i < A.d; i += G) {
         float at;
         const ff t = distmult_term_ff(load1<BF16>(A.X, u * d + i), load1<BF16>(A.Y, r * d + i),
                                       load1<BF16>(A.X, v * d + i), &at);
@@ -341,7 +343,7 @@ __device__ inline ff wave_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint
         as += at;
     }
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
+    for (int o = G / 2; o > 0; o >>= 1) {
         const ff w = {__shfl_xor(acc.hi, o, kWave), __shfl_xor(acc.lo, o, kWave)};
         acc = ff_add(acc, w);
         as += __shfl_xor(as, o, kWave);
@@ -353,31 +355,34 @@ __device__ inline ff wave_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint
 // S = w(s,r1,a) + w(a,r2,b) + w(b,r3,t) in float-float, with a bound on
 // its error: per edge, the dot product (about 4 d u^2 sum|t|) plus the
 // log-sigmoid; then the two additions.
-template <bool BF16, bool WAVE>
+// G = 1: one thread alone; G > 1 (a power of two, >= 4): an aligned group
+// of G lanes computes the score together and every lane returns it.
+template <bool BF16, int G>
 __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint32_t b, uint32_t t, uint32_t r1,
                                    uint32_t r2, uint32_t r3, float *eps) {
     const float u2 = kUnit * kUnit;
     float as1, as2, as3;
     ff x1, x2, x3;
-    if (WAVE) {
-        x1 = wave_edge_x_ff<BF16>(A, s, r1, a, &as1);
-        x2 = wave_edge_x_ff<BF16>(A, a, r2, b, &as2);
-        x3 = wave_edge_x_ff<BF16>(A, b, r3, t, &as3);
+    if (G > 1) {
+        x1 = group_edge_x_ff<BF16, G>(A, s, r1, a, &as1);
+        x2 = group_edge_x_ff<BF16, G>(A, a, r2, b, &as2);
+        x3 = group_edge_x_ff<BF16, G>(A, b, r3, t, &as3);
     } else {
         x1 = edge_x_ff<BF16>(A, s, r1, a, &as1);
         x2 = edge_x_ff<BF16>(A, a, r2, b, &as2);
         x3 = edge_x_ff<BF16>(A, b, r3, t, &as3);
     }
     ff w1, w2, w3;
-    if (WAVE) {
-        // lanes 0, 1, 2 (mod 3) take one log-sigmoid each; every lane then
-        // reads all three
+    if (G > 1) {
+        // the group's lanes 0, 1, 2 (mod 3) take one log-sigmoid each; every
+        // lane then reads all three
         const int lane = static_cast<int>(threadIdx.x & (kWave - 1));
-        const int e = lane % 3;
+        const int g0 = lane & ~(G - 1);
+        const int e = (lane - g0) % 3;
         const ff w = ff_logsigmoid(e == 0 ? x1 : (e == 1 ? x2 : x3));
-        w1 = ff{__shfl(w.hi, 0, kWave), __shfl(w.lo, 0, kWave)};
-        w2 = ff{__shfl(w.hi, 1, kWave), __shfl(w.lo, 1, kWave)};
-        w3 = ff{__shfl(w.hi, 2, kWave), __shfl(w.lo, 2, kWave)};
+        w1 = ff{__shfl(w.hi, g0, kWave), __shfl(w.lo, g0, kWave)};
+        w2 = ff{__shfl(w.hi, g0 + 1, kWave), __shfl(w.lo, g0 + 1, kWave)};
+        w3 = ff{__shfl(w.hi, g0 + 2, kWave), __shfl(w.lo, g0 + 2, kWave)};
     } else {
         w1 = ff_logsigmoid(x1);
         w2 = ff_logsigmoid(x2);
@@ -1321,7 +1326,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 cd.eps = 0.0f;
                                 if (EXACT) {
                                     float e2;
-                                    ff sc = path_score_ff<BF16, false>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
+                                    ff sc = path_score_ff<BF16, 1>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
                                     cd.s = sc.hi;
                                     cd.s_lo = sc.lo;
                                     cd.eps = e2;
@@ -1529,16 +1534,16 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
         return;
     }
     const uint32_t nb = s_nb;
-    // one wave rescores one band candidate
-    for (uint32_t i = threadIdx.x / kWave; i < nb; i += blockDim.x / kWave) {
+    // a group of kRescoreLanes lanes rescores one band candidate
+    for (uint32_t i = threadIdx.x / kRescoreLanes; i < nb; i += blockDim.x / kRescoreLanes) {
         Cand x = c[i];
         const uint32_t r1 = (x.rel >> 16) & 0xFF, r2 = (x.rel >> 8) & 0xFF, r3 = x.rel & 0xFF;
         float e;
-        ff sc = path_score_ff<BF16, true>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
+        ff sc = path_score_ff<BF16, kRescoreLanes>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
         x.s = sc.hi;
         x.s_lo = sc.lo;
         x.eps = e;
-        if ((threadIdx.x & (kWave - 1)) == 0) c[i] = x;
+        if ((threadIdx.x & (kRescoreLanes - 1)) == 0) c[i] = x;
     }
     const uint32_t nb2 = next_pow2(nb);
     for (uint32_t i = nb + threadIdx.x; i < nb2; i += blockDim.x) c[i] = cand_sentinel();
