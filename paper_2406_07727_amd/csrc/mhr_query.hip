@@ -558,6 +558,27 @@ __device__ __forceinline__ uint32_t fkey(float x) {
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Bitonic sort of n2 (a power of two) 64-bit keys into descending order
+// (whole workgroup; ends with a barrier).
+__device__ inline void block_sort_keys_desc(uint64_t *keys, uint32_t n2) {
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                const uint32_t p = i ^ j;
+                if (p > i) {
+                    const uint64_t x = keys[i], y = keys[p];
+                    const bool desc = (i & k) == 0;   // this half ends highest-first
+                    if (desc ? (x < y) : (x > y)) {
+                        keys[i] = y;
+                        keys[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Merges the staged candidates into the tile's list.
 // Fast pass: the best KC of list + stage by fast-pass score, in descending
 // score order (ties in any order: a tie at the list's end marks the tile
@@ -596,22 +617,7 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, ui
     for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x)
         keys[i] = i < tot ? (static_cast<uint64_t>(fkey(stage[i].s)) << 32) | i : 0ull;
     __syncthreads();
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                const uint32_t p = i ^ j;
-                if (p > i) {
-                    const uint64_t x = keys[i], y = keys[p];
-                    const bool desc = (i & k) == 0;   // this half ends highest-first
-                    if (desc ? (x < y) : (x > y)) {
-                        keys[i] = y;
-                        keys[p] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    block_sort_keys_desc(keys, n2);
     if (threadIdx.x == 0) {
         const uint64_t kk = keys[KC];
         if (kk != 0ull && stage[static_cast<uint32_t>(kk)].a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
@@ -1426,11 +1432,14 @@ __device__ inline void write_result(mhr_path *row, const Cand *c, uint32_t nc, u
 }
 
 // Streams the query's tile lists through LDS (kMergeSlots candidates at a
-// time) and leaves the best KC by the total order, sorted, in c[0..KC).
+// time) and leaves the best KC, sorted, in c[0..KC): by the total order when
+// FULL (the exhaustive pass, whose scores are final), else by fast-pass score
+// (8-byte keys in `keys`, kMergeSlots of them; the band is re-sorted after
+// rescoring).
 // Also returns, through shared memory, the best key that fell off the
 // running list (its score, or -inf when nothing real was dropped).
-template <int KC>
-__device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, float *s_drop) {
+template <int KC, bool FULL>
+__device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, float *s_drop, uint64_t *keys) {
     constexpr uint32_t per = (kMergeSlots - KC) / KC;  // tile lists per step
     if (threadIdx.x == 0) *s_drop = -__builtin_huge_valf();
     if (P.ntiles == 1) {   // one tile: its list is already sorted and complete
@@ -1455,9 +1464,25 @@ __device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, 
             c[KC + i] = x;
         }
         __syncthreads();
-        block_sort_cands(c, static_cast<int>(n));
-        if (threadIdx.x == 0 && c[KC].a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, c[KC].s);
-        __syncthreads();
+        if (FULL) {
+            block_sort_cands(c, static_cast<int>(n));
+            if (threadIdx.x == 0 && c[KC].a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, c[KC].s);
+            __syncthreads();
+        } else {
+            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+                keys[i] = (static_cast<uint64_t>(fkey(c[i].s)) << 32) | i;
+            __syncthreads();
+            block_sort_keys_desc(keys, n);
+            if (threadIdx.x == 0) {
+                const Cand &f = c[static_cast<uint32_t>(keys[KC])];
+                if (f.a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, f.s);
+            }
+            Cand x = cand_sentinel();
+            if (threadIdx.x < static_cast<uint32_t>(KC)) x = c[static_cast<uint32_t>(keys[threadIdx.x])];
+            __syncthreads();
+            if (threadIdx.x < static_cast<uint32_t>(KC)) c[threadIdx.x] = x;
+            __syncthreads();
+        }
     }
 }
 
@@ -1495,7 +1520,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
         s_eps = eps;
         s_tot = tot;
     }
-    collect_top<KC>(A, P, c, &s_drop);
+    collect_top<KC, false>(A, P, c, &s_drop, reinterpret_cast<uint64_t *>(c + kMergeSlots));
     const uint32_t cnt = s_n;
     const uint32_t kept = min(cnt, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, cnt);
@@ -1576,7 +1601,7 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
         for (uint32_t j = 0; j < P.ntiles; ++j) n += A.hdr[P.tile_base + j].count;
         s_n = n;
     }
-    collect_top<KC>(A, P, c, &s_drop);
+    collect_top<KC, true>(A, P, c, &s_drop, nullptr);
     const uint32_t kept = min(s_n, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, kept);
     write_result(row, c, kept, kk, kmax);
@@ -1727,10 +1752,11 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     hipLaunchKernelGGL(gk, dim3(grid), dim3(kBlock), GL.total, st, A);
     MHR_HIP_TRY(rec(ev ? ev->gather_end : nullptr));
     const size_t msmem = size_t(kMergeSlots) * sizeof(Cand);
+    const size_t msmem_keys = msmem + size_t(kMergeSlots) * sizeof(uint64_t);   // fast merge: + sort keys
     auto mk = merge_kernel<BF16, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(mk),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem)));
-    hipLaunchKernelGGL(mk, dim3(nq), dim3(kBlock), msmem, st, A, out, out_count, out_total, out_status, kmax);
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem_keys)));
+    hipLaunchKernelGGL(mk, dim3(nq), dim3(kBlock), msmem_keys, st, A, out, out_count, out_total, out_status, kmax);
     auto xk = gather_kernel<BF16, true, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(xk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(GL.total)));
