@@ -944,13 +944,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     ys[k] = ys_n[k];
                 }
                 if (!last) chunk_entries(cb + kChunk, ps_n, ys_n);
+                if (!heavy) {
 #pragma unroll
-                for (int k = 0; k < kEPT; ++k) {
-                    hits[k] = false;
-                    mps[k] = 0;
-                    if (ps[k] == kEmpty) continue;
-                    const uint32_t y = ys[k];
-                    if (!heavy) {
+                    for (int k = 0; k < kEPT; ++k) {
+                        hits[k] = false;
+                        mps[k] = 0;
+                        if (ps[k] == kEmpty) continue;
+                        const uint32_t y = ys[k];
                         uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
                         for (;;) {
                             uint32_t key = hkeys[slot];
@@ -958,17 +958,47 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             if (key == kEmpty) break;
                             slot = (slot + 1) & smask;
                         }
-                    } else {
-                        uint32_t bk = y >> dsh;
-                        uint32_t lo = dir[bk], hi = dir[bk + 1];
-                        for (uint32_t i = lo; i < hi; ++i) {
-                            uint32_t c = Pcol[P.probe_beg + i];
-                            if (c == y) {
-                                if (!kp || kp[i]) { hits[k] = true; mps[k] = Pmask[P.probe_beg + i]; }
-                                break;
-                            }
+                    }
+                } else {
+                    // Directory probes in stages, each stage's loads issued
+                    // for all of the thread's entries before any is used: the
+                    // bucket bounds, then the bucket's first two ids (a bucket
+                    // holds two ids on average), then a walk over the rest of
+                    // the rare longer buckets, then the masks of the hits.
+                    const uint32_t *pc = Pcol + P.probe_beg;
+                    uint32_t lo[kEPT], hi[kEPT], c0[kEPT], c1[kEPT], at[kEPT];
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        lo[k] = hi[k] = 0;
+                        if (ps[k] != kEmpty) {
+                            const uint32_t bk = ys[k] >> dsh;
+                            lo[k] = dir[bk];
+                            hi[k] = dir[bk + 1];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        c0[k] = (lo[k] < hi[k]) ? pc[lo[k]] : kEmpty;
+                        c1[k] = (lo[k] + 1 < hi[k]) ? pc[lo[k] + 1] : kEmpty;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        const uint32_t y = ys[k];
+                        at[k] = kEmpty;
+                        if (lo[k] >= hi[k] || c0[k] > y) continue;   // empty bucket, or ids past y
+                        if (c0[k] == y) { at[k] = lo[k]; continue; }
+                        if (c1[k] == y) { at[k] = lo[k] + 1; continue; }
+                        if (c1[k] > y) continue;                      // includes a bucket of one id
+                        for (uint32_t i = lo[k] + 2; i < hi[k]; ++i) {
+                            const uint32_t c = pc[i];
+                            if (c == y) { at[k] = i; break; }
                             if (c > y) break;
                         }
+                    }
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        hits[k] = at[k] != kEmpty && (!kp || kp[at[k]]);
+                        mps[k] = hits[k] ? Pmask[P.probe_beg + at[k]] : 0u;
                     }
                 }
                 const int lane = tid & (kWave - 1);
