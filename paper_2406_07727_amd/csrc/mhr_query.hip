@@ -58,6 +58,7 @@ struct GArgs {
     QueryPlan *plans;
     Control *ctrl;
     uint32_t *tile_q;
+    uint32_t *tile_order;   // the order in which the gather takes the tiles
     uint2 *tile_start;
     TileHeader *hdr;
     Cand *cands;
@@ -212,12 +213,30 @@ __device__ inline uint32_t tiles_for(uint64_t cost, uint64_t tile) {
     return static_cast<uint32_t>((cost + L - 1) / L);
 }
 
+// Order class of a query's tiles, larger for longer expected tiles.  A
+// tile's time is mostly its matches, and the share of scanned entries that
+// hit the probe side grows with the probe side's size, so the tile length
+// times (probe length + 64) orders tiles by expected time.  Classes are
+// quarter-octaves of that product.
+constexpr uint32_t kOrderClasses = 256;
+__device__ inline uint32_t order_class(uint64_t tile_len, uint32_t probe_len) {
+    const uint64_t x = tile_len * (static_cast<uint64_t>(probe_len) + 64u);
+    if (x < 4) return static_cast<uint32_t>(x);
+    const int msb = 63 - __clzll(static_cast<long long>(x));
+    const uint32_t c = 4u * static_cast<uint32_t>(msb) + static_cast<uint32_t>((x >> (msb - 2)) & 3u);
+    return min(c, kOrderClasses - 1);
+}
+
 // One workgroup: per-query tile counts (tile size doubled until the batch
-// fits the workspace's tile capacity), their prefix and the tile -> query map.
+// fits the workspace's tile capacity), their prefix, the tile -> query map,
+// and the order in which the gather takes the tiles: longest expected first,
+// so that the last tiles to start are short ones (a counting sort over the
+// order classes; tiles of one class in any order).
 __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
     __shared__ uint32_t red[kBlock / kWave];
     __shared__ uint64_t red64[kBlock / kWave];
     __shared__ uint32_t carry;
+    __shared__ uint32_t cls_base[kOrderClasses];
     uint64_t tile = A.tile_edges;
     for (;;) {
         uint64_t part = 0;
@@ -252,6 +271,30 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
         __syncthreads();
         if (threadIdx.x == 0) carry = c + tot;
         __syncthreads();
+    }
+    // tiles per class, highest class first
+    for (uint32_t i = threadIdx.x; i < kOrderClasses; i += kBlock) cls_base[i] = 0;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
+        const QueryPlan &P = A.plans[q];
+        if (P.status == 0 && P.ntiles)
+            atomicAdd(&cls_base[kOrderClasses - 1 - order_class(P.pad[0], P.probe_len)], P.ntiles);
+    }
+    __syncthreads();
+    {
+        static_assert(kOrderClasses <= kBlock, "one class per thread");
+        const uint32_t v = threadIdx.x < kOrderClasses ? cls_base[threadIdx.x] : 0u;
+        uint32_t tot;
+        const uint32_t incl = block_incl_scan<uint32_t>(v, red, &tot);
+        if (threadIdx.x < kOrderClasses) cls_base[threadIdx.x] = incl - v;
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
+        const QueryPlan &P = A.plans[q];
+        if (P.status == 0 && P.ntiles) {
+            const uint32_t at = atomicAdd(&cls_base[kOrderClasses - 1 - order_class(P.pad[0], P.probe_len)], P.ntiles);
+            for (uint32_t j = 0; j < P.ntiles; ++j) A.tile_order[at + j] = P.tile_base + j;
+        }
     }
     if (threadIdx.x == 0) {
         A.ctrl->total_tiles = carry;
@@ -775,6 +818,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             } else {
                 t = atomicAdd(&A.ctrl->gather_ctr, 1u);
                 if (t < A.ctrl->total_tiles) {
+                    t = A.tile_order[t];
                     uint32_t q = A.tile_q[t];
                     sh->q = q;
                     sh->j = t - A.plans[q].tile_base;
@@ -1686,7 +1730,7 @@ GArgs make_args(const mhr_graph *g) {
 // workspace
 // ---------------------------------------------------------------------------
 struct WsLayout {
-    size_t ctrl, plans, tile_start, tile_q, exact_list, hdr, cands, total;
+    size_t ctrl, plans, tile_start, tile_q, tile_order, exact_list, hdr, cands, total;
 };
 
 uint32_t kc_for(uint32_t kmax) {
@@ -1704,6 +1748,7 @@ WsLayout ws_layout(uint32_t nq, uint32_t kc) {
     W.plans = o; o = al(o + size_t(nq) * sizeof(QueryPlan));
     W.tile_start = o; o = al(o + size_t(tcap) * sizeof(uint2));
     W.tile_q = o; o = al(o + size_t(tcap) * sizeof(uint32_t));
+    W.tile_order = o; o = al(o + size_t(tcap) * sizeof(uint32_t));
     W.exact_list = o; o = al(o + size_t(nq) * sizeof(uint32_t));
     W.hdr = o; o = al(o + size_t(tcap) * sizeof(TileHeader));
     W.cands = o; o = al(o + size_t(tcap) * kc * sizeof(Cand));
@@ -1743,6 +1788,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     A.plans = reinterpret_cast<QueryPlan *>(base + W.plans);
     A.tile_start = reinterpret_cast<uint2 *>(base + W.tile_start);
     A.tile_q = reinterpret_cast<uint32_t *>(base + W.tile_q);
+    A.tile_order = reinterpret_cast<uint32_t *>(base + W.tile_order);
     A.exact_list = reinterpret_cast<uint32_t *>(base + W.exact_list);
     A.hdr = reinterpret_cast<TileHeader *>(base + W.hdr);
     A.cands = reinterpret_cast<Cand *>(base + W.cands);
