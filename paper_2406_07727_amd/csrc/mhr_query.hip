@@ -1506,16 +1506,11 @@ __device__ inline void write_result(mhr_path *row, const Cand *c, uint32_t nc, u
 }
 
 // Streams the query's tile lists through LDS (kMergeSlots candidates at a
-// time) and leaves the best KC, sorted, in c[0..KC): by the total order when
-// FULL (the exhaustive pass, whose scores are final), else by fast-pass score
-// (8-byte keys in `keys`, kMergeSlots of them; the band is re-sorted after
-// rescoring).
-// Also returns, through shared memory, the best key that fell off the
-// running list (its score, or -inf when nothing real was dropped).
-template <int KC, bool FULL>
-__device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, float *s_drop, uint64_t *keys) {
+// time) and leaves the best KC in c[0..KC), sorted by the total order (the
+// exhaustive pass, whose scores are final).
+template <int KC>
+__device__ inline void collect_top_exact(const GArgs &A, const QueryPlan &P, Cand *c) {
     constexpr uint32_t per = (kMergeSlots - KC) / KC;  // tile lists per step
-    if (threadIdx.x == 0) *s_drop = -__builtin_huge_valf();
     if (P.ntiles == 1) {   // one tile: its list is already sorted and complete
         const uint32_t cnt = A.hdr[P.tile_base].count;
         for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x)
@@ -1538,26 +1533,127 @@ __device__ inline void collect_top(const GArgs &A, const QueryPlan &P, Cand *c, 
             c[KC + i] = x;
         }
         __syncthreads();
-        if (FULL) {
-            block_sort_cands(c, static_cast<int>(n));
-            if (threadIdx.x == 0 && c[KC].a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, c[KC].s);
+        block_sort_cands(c, static_cast<int>(n));
+    }
+}
+
+// Fast-pass selection state (shared memory).
+struct SelShared {
+    uint32_t prefix;    // radix select: key bits fixed so far
+    uint32_t need;      // candidates still to take among keys matching the prefix
+    uint32_t nsel;      // candidates gathered
+    uint32_t neq;       // candidates seen at the threshold key
+    uint32_t dropkey;   // best key left out (0: none)
+    uint32_t hist[256];
+};
+constexpr uint32_t kSelCache = 8192;   // keys of the tile lists kept in LDS between passes
+
+template <int KC>
+__device__ __forceinline__ uint32_t list_key(const GArgs &A, const QueryPlan &P, uint32_t i) {
+    const uint32_t tile = P.tile_base + i / KC, k = i % KC;
+    return k < A.hdr[tile].count ? fkey(A.cands[static_cast<uint64_t>(tile) * KC + k].s) : 0u;
+}
+
+// The fast pass's best KC over the query's tile lists (nvalid candidates in
+// all), into c[0..KC) sorted by score, highest first, sentinels after the
+// last; returns the best score left out (-inf when none).  Scores are
+// compared by their order-preserving 32-bit keys (never 0 for a real score;
+// 0 marks an empty slot).  A radix select, 8 key bits per pass from the top,
+// finds the KC-th largest key T; a last pass gathers every candidate above T
+// and as many at T as fit (which of equal keys is arbitrary: the score decides
+// everything that follows).
+template <int KC>
+__device__ float select_top(const GArgs &A, const QueryPlan &P, uint32_t nvalid, Cand *c, uint64_t *keys,
+                            uint32_t *cache, SelShared *ss) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t N = P.ntiles * static_cast<uint32_t>(KC);
+    const bool cached = N <= kSelCache;
+    if (tid == 0) {
+        ss->prefix = 0;
+        ss->nsel = 0;
+        ss->neq = 0;
+        ss->dropkey = 0;
+        ss->need = nvalid > static_cast<uint32_t>(KC) ? static_cast<uint32_t>(KC) : 0u;
+    }
+    __syncthreads();
+    uint32_t T = 0;   // with nvalid <= KC every real key is above T
+    if (nvalid > static_cast<uint32_t>(KC)) {
+        uint32_t pmask = 0;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (uint32_t i = tid; i < 256; i += kBlock) ss->hist[i] = 0;
             __syncthreads();
-        } else {
-            for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-                keys[i] = (static_cast<uint64_t>(fkey(c[i].s)) << 32) | i;
-            __syncthreads();
-            block_sort_keys_desc(keys, n);
-            if (threadIdx.x == 0) {
-                const Cand &f = c[static_cast<uint32_t>(keys[KC])];
-                if (f.a != 0xFFFFFFFFu) *s_drop = fmaxf(*s_drop, f.s);
+            const uint32_t prefix = ss->prefix;
+            for (uint32_t i = tid; i < N; i += kBlock) {
+                uint32_t key;
+                if (shift == 24) {
+                    key = list_key<KC>(A, P, i);
+                    if (cached) cache[i] = key;
+                } else {
+                    key = cached ? cache[i] : list_key<KC>(A, P, i);
+                }
+                if (key != 0 && (key & pmask) == prefix) atomicAdd(&ss->hist[(key >> shift) & 255u], 1u);
             }
-            Cand x = cand_sentinel();
-            if (threadIdx.x < static_cast<uint32_t>(KC)) x = c[static_cast<uint32_t>(keys[threadIdx.x])];
             __syncthreads();
-            if (threadIdx.x < static_cast<uint32_t>(KC)) c[threadIdx.x] = x;
+            if (tid < kWave) {
+                // lane l holds bins 4l..4l+3; the bin where the count from the
+                // top reaches `need` fixes the next 8 bits
+                const uint32_t lane = tid;
+                const uint32_t h0 = ss->hist[4 * lane], h1 = ss->hist[4 * lane + 1], h2 = ss->hist[4 * lane + 2],
+                               h3 = ss->hist[4 * lane + 3];
+                const uint32_t own = h0 + h1 + h2 + h3;
+                uint32_t incl = own;   // count in this lane's bins and all higher ones
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const uint32_t t = __shfl_down(incl, off, kWave);
+                    if (lane + off < static_cast<uint32_t>(kWave)) incl += t;
+                }
+                const uint32_t above = incl - own;
+                const uint32_t need = ss->need;
+                if (above < need && need <= incl) {
+                    uint32_t acc = above, b;
+                    if (acc + h3 >= need) b = 3;
+                    else if (acc += h3, acc + h2 >= need) b = 2;
+                    else if (acc += h2, acc + h1 >= need) b = 1;
+                    else { acc += h1; b = 0; }
+                    ss->prefix = prefix | ((4 * lane + b) << shift);
+                    ss->need = need - acc;
+                }
+            }
+            pmask |= 255u << shift;
             __syncthreads();
         }
+        T = ss->prefix;
     }
+    const uint32_t need_eq = ss->need;   // candidates to take at key T
+    uint32_t drop = 0;
+    for (uint32_t i = tid; i < N; i += kBlock) {
+        const uint32_t key = cached && nvalid > static_cast<uint32_t>(KC) ? cache[i] : list_key<KC>(A, P, i);
+        if (key == 0) continue;
+        bool take = key > T;
+        if (!take && key == T) take = atomicAdd(&ss->neq, 1u) < need_eq;
+        if (take) {
+            const uint32_t slot = atomicAdd(&ss->nsel, 1u);
+            c[slot] = A.cands[static_cast<uint64_t>(P.tile_base + i / KC) * KC + i % KC];
+        } else {
+            drop = max(drop, key);
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) drop = max(drop, static_cast<uint32_t>(__shfl_xor(drop, off, kWave)));
+    if ((tid & (kWave - 1)) == 0 && drop) atomicMax(&ss->dropkey, drop);
+    __syncthreads();
+    const uint32_t nsel = ss->nsel;
+    // sort the KC by key, highest first
+    if (tid < static_cast<uint32_t>(KC))
+        keys[tid] = tid < nsel ? (static_cast<uint64_t>(fkey(c[tid].s)) << 32) | tid : 0ull;
+    __syncthreads();
+    block_sort_keys_desc(keys, KC);
+    Cand x = cand_sentinel();
+    if (tid < nsel) x = c[static_cast<uint32_t>(keys[tid])];
+    __syncthreads();
+    if (tid < static_cast<uint32_t>(KC)) c[tid] = x;
+    const uint32_t dk = ss->dropkey;
+    __syncthreads();
+    if (dk == 0) return -__builtin_huge_valf();
+    return __uint_as_float((dk & 0x80000000u) ? (dk & 0x7FFFFFFFu) : ~dk);
 }
 
 template <bool BF16, int KC>
@@ -1565,9 +1661,12 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
                                                        uint64_t *out_total, uint32_t *out_status, uint32_t kmax) {
     extern __shared__ __align__(16) unsigned char smem[];
     Cand *c = reinterpret_cast<Cand *>(smem);
-    __shared__ uint32_t s_n, s_over, s_nb;
-    __shared__ float s_eps, s_drop;
-    __shared__ uint64_t s_tot;
+    uint64_t *keys = reinterpret_cast<uint64_t *>(c + KC);
+    uint32_t *cache = reinterpret_cast<uint32_t *>(keys + KC);
+    __shared__ SelShared ss;
+    __shared__ uint32_t red32[kBlock / kWave];
+    __shared__ uint64_t red64[kBlock / kWave];
+    __shared__ float redf[kBlock / kWave];
     const uint32_t q = blockIdx.x;
     const QueryPlan P = A.plans[q];
     mhr_path *row = out + static_cast<uint64_t>(q) * kmax;
@@ -1580,59 +1679,51 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
         write_sentinels(row, 0, kmax);
         return;
     }
-    if (threadIdx.x == 0) {
-        uint32_t n = 0;
-        float eps = 0.0f;
-        uint64_t tot = 0;
-        for (uint32_t j = 0; j < P.ntiles; ++j) {
-            const TileHeader &h = A.hdr[P.tile_base + j];
-            n += h.count;
-            eps = fmaxf(eps, h.eps);
-            tot += h.npaths;
-        }
-        s_n = n;
-        s_eps = eps;
-        s_tot = tot;
+    // tile headers: candidates, largest error bound, paths
+    uint32_t n_part = 0;
+    float e_part = 0.0f;
+    uint64_t t_part = 0;
+    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kBlock) {
+        const TileHeader &h = A.hdr[P.tile_base + j];
+        n_part += h.count;
+        e_part = fmaxf(e_part, h.eps);
+        t_part += h.npaths;
     }
-    collect_top<KC, false>(A, P, c, &s_drop, reinterpret_cast<uint64_t *>(c + kMergeSlots));
-    const uint32_t cnt = s_n;
+    const uint32_t cnt = block_sum<uint32_t>(n_part, red32);
+    const float eps = block_max(e_part, redf);
+    const uint64_t tot = block_sum<uint64_t>(t_part, red64);
+    const float s_drop = select_top<KC>(A, P, cnt, c, keys, cache, &ss);
     const uint32_t kept = min(cnt, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, cnt);
     if (kk == 0) {
         if (threadIdx.x == 0) {
             out_count[q] = 0;
-            if (out_total) out_total[q] = s_tot;
+            if (out_total) out_total[q] = tot;
             if (out_status) out_status[q] = 0;
         }
         write_sentinels(row, 0, kmax);
         return;
     }
     const float theta = c[kk - 1].s;
-    const float eps = s_eps;
     // band threshold, rounded down generously
     const float thr = (theta - fmaxf(2.0f * eps, A.band_abs)) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
-    if (threadIdx.x == 0) {
-        uint32_t over = s_drop >= thr ? 1u : 0u;
-        for (uint32_t j = 0; j < P.ntiles && !over; ++j) {
-            const TileHeader &h = A.hdr[P.tile_base + j];
-            if (h.truncated && h.cutoff >= thr) over = 1;
-        }
-        uint32_t nb = 0;
-        while (nb < kept && c[nb].s >= thr) ++nb;
-        s_over = over;
-        s_nb = nb;
+    // overflow: a candidate above the threshold was dropped, here or by a tile
+    int over_part = (threadIdx.x == 0 && s_drop >= thr) ? 1 : 0;
+    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kBlock) {
+        const TileHeader &h = A.hdr[P.tile_base + j];
+        if (h.truncated && h.cutoff >= thr) over_part = 1;
     }
-    __syncthreads();
-    if (s_over) {
+    // the band: the sorted prefix at or above the threshold
+    const uint32_t nb = static_cast<uint32_t>(__syncthreads_count(threadIdx.x < kept && c[threadIdx.x].s >= thr));
+    if (__syncthreads_or(over_part)) {
         if (threadIdx.x == 0) {
             A.plans[q].flags = kNeedExact;
             A.plans[q].thr = thr;
-            A.plans[q].total = s_tot;
+            A.plans[q].total = tot;
             atomicAdd(&A.ctrl->exact_n, 1u);
         }
         return;
     }
-    const uint32_t nb = s_nb;
     // a group of kRescoreLanes lanes rescores one band candidate
     for (uint32_t i = threadIdx.x / kRescoreLanes; i < nb; i += blockDim.x / kRescoreLanes) {
         Cand x = c[i];
@@ -1651,7 +1742,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
     write_result(row, c, nb, kk, kmax);
     if (threadIdx.x == 0) {
         out_count[q] = kk;
-        if (out_total) out_total[q] = s_tot;
+        if (out_total) out_total[q] = tot;
         if (out_status) out_status[q] = 0;
     }
 }
@@ -1665,7 +1756,6 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
     extern __shared__ __align__(16) unsigned char smem[];
     Cand *c = reinterpret_cast<Cand *>(smem);
     __shared__ uint32_t s_n;
-    __shared__ float s_drop;
     const uint32_t q = blockIdx.x;
     const QueryPlan P = A.plans[q];
     if (P.status != 0 || !(P.flags & kNeedExact)) return;
@@ -1675,7 +1765,7 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
         for (uint32_t j = 0; j < P.ntiles; ++j) n += A.hdr[P.tile_base + j].count;
         s_n = n;
     }
-    collect_top<KC, true>(A, P, c, &s_drop, nullptr);
+    collect_top_exact<KC>(A, P, c);
     const uint32_t kept = min(s_n, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, kept);
     write_result(row, c, kept, kk, kmax);
@@ -1828,7 +1918,8 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     hipLaunchKernelGGL(gk, dim3(grid), dim3(kBlock), GL.total, st, A);
     MHR_HIP_TRY(rec(ev ? ev->gather_end : nullptr));
     const size_t msmem = size_t(kMergeSlots) * sizeof(Cand);
-    const size_t msmem_keys = msmem + size_t(kMergeSlots) * sizeof(uint64_t);   // fast merge: + sort keys
+    // fast merge: KC candidates, their sort keys, the key cache
+    const size_t msmem_keys = size_t(KC) * (sizeof(Cand) + sizeof(uint64_t)) + size_t(kSelCache) * sizeof(uint32_t);
     auto mk = merge_kernel<BF16, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(mk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem_keys)));

@@ -144,6 +144,48 @@ def test_tiling_and_grid_do_not_change_results():
         assert np.array_equal(a, b[::-1])
 
 
+def _tiles_per_query(n, h, t, src, dst, tile_edges, nq):
+    """Tile counts the schedule gives each query: the scan cost of the
+    cheaper direction over distinct (u, v) pairs, tiles of tile_edges entries
+    (at most 4096 per query), the tile size doubled while the batch exceeds
+    the workspace's max(4 nq, 16384) tiles."""
+    pairs = np.unique(np.stack([h, t], 1).astype(np.int64), axis=0)
+    u, v = pairs[:, 0], pairs[:, 1]
+    outdeg = np.bincount(u, minlength=n)
+    indeg = np.bincount(v, minlength=n)
+    cost = []
+    for s_, t_ in zip(src, dst):
+        cb = int(indeg[u[v == t_]].sum())
+        cf = int(outdeg[v[u == s_]].sum())
+        probe = outdeg[s_] if cf >= cb else indeg[t_]
+        cost.append(min(cf, cb) if probe > 0 else 0)
+    cost = np.array(cost, np.int64)
+    te, cap = tile_edges, max(4 * nq, 16384)
+    while True:
+        nt = np.where(cost > 0, np.minimum((cost + te - 1) // te, 4096), 0)
+        if nt.sum() <= cap:
+            return nt
+        te *= 2
+
+
+def test_merge_selects_over_many_tiles():
+    """The fast merge's radix select over the tile lists, with the keys held
+    in LDS (at most 8192 list slots) and streamed from memory (more), against
+    the oracle and the default tiling."""
+    import paper_2406_07727_amd as mhr
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    n, R = cfg.graph.n, cfg.graph.R
+    nt = _tiles_per_query(n, h, t, s, d, 4, len(s))
+    say(f"case many tiles: max tiles/query {nt.max()}, queries with 2..128 tiles {int(((nt > 1) & (nt <= 128)).sum())}")
+    assert nt.max() > 128 and ((nt > 1) & (nt <= 128)).any()
+    g = gpu_graph(n, R, h, r, t, X, Y)
+    ref = run_gpu(g, s, d, 16)
+    got = run_gpu(g, s, d, 16, opts=mhr.QueryOpts(0, 4, 0, 0))
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    compare(got, run_oracle(n, R, h, r, t, X, Y, s, d, 16))
+
+
 def test_bad_queries_and_empty_results():
     import paper_2406_07727_amd as mhr
     cfg, (h, r, t), (X, Y), _ = workload("tiny")
