@@ -470,7 +470,8 @@ struct GatherShared {
     uint32_t truncated;
     uint32_t E;           // entries in the current row batch
     uint32_t rowvals;
-    uint32_t pad[3];
+    uint32_t vn;          // values in the current sub-batch's slab
+    uint32_t pad[2];
     Cand thr;             // current worst kept candidate (sentinel until the list fills)
     uint64_t red64[kBlock / kWave];
     uint32_t red32[kBlock / kWave];
@@ -481,7 +482,7 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_
 
 struct GatherLayout {
     size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, qy, sub, slab, list, stage,
-        ymax, rowrel, slab_rel, agg, shared, total;
+        ymax, rowrel, slab_rel, mkeys, shared, total;
 };
 
 constexpr int kSubFields = 7;  // pos, y, mp, mm, row, voff, first item
@@ -502,7 +503,7 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     L.qmp = o; o = align16(o + kQueue * 4);
     L.qy = o; o = align16(o + kQueue * 4);
     L.sub = o; o = align16(o + kBlock * kSubFields * 4);
-    L.agg = o; o = align16(o + kBlock * 6 * 4);
+    L.mkeys = o; o = align16(o + size_t(next_pow2(kStage + kc)) * 8);
     L.slab = o; o = align16(o + kSlab * 4);
     L.list = o; o = align16(o + size_t(kc) * sizeof(Cand));
     L.stage = o; o = align16(o + size_t(next_pow2(kStage + kc)) * sizeof(Cand));
@@ -776,10 +777,12 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     Cand *stage = reinterpret_cast<Cand *>(smem + Lo.stage);
     GatherShared *sh = reinterpret_cast<GatherShared *>(smem + Lo.shared);
     float *ymax = reinterpret_cast<float *>(smem + Lo.ymax);
-    float *agg = reinterpret_cast<float *>(smem + Lo.agg);  // per match: max f, max |f|, max eps (probe, mid)
+    uint64_t *mkeys = reinterpret_cast<uint64_t *>(smem + Lo.mkeys);  // stage-merge sort keys
     uint8_t *rowrel = reinterpret_cast<uint8_t *>(smem + Lo.rowrel);
     uint8_t *slab_rel = reinterpret_cast<uint8_t *>(smem + Lo.slab_rel);
-    uint32_t *sub_pos = sub, *sub_y = sub + kBlock, *sub_mp = sub + 2 * kBlock, *sub_mm = sub + 3 * kBlock,
+    float *sub_su_p = reinterpret_cast<float *>(sub);   // sum_k |up_k| per match (scoring)
+    float *sub_su_m = reinterpret_cast<float *>(sub + 6 * kBlock);   // sum_k |um_k| (scoring; then sub_item)
+    uint32_t *sub_y = sub + kBlock, *sub_mp = sub + 2 * kBlock, *sub_mm = sub + 3 * kBlock,
              *sub_row = sub + 4 * kBlock, *sub_voff = sub + 5 * kBlock, *sub_item = sub + 6 * kBlock;
 
     const uint32_t tid = threadIdx.x;
@@ -1088,12 +1091,12 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     const bool take = (mi < nmatch) && vincl <= static_cast<uint32_t>(kSlab);
                     const uint32_t ncnt = block_sum<uint32_t>(take ? 1u : 0u, sh->red32);
                     if (take) {
-                        sub_pos[tid] = pos;
                         sub_y[tid] = y;
                         sub_mp[tid] = mp;
                         sub_mm[tid] = mm;
                         sub_row[tid] = row;
                         sub_voff[tid] = vincl - nv2;
+                        if (tid + 1 == ncnt) sh->vn = vincl;   // the taken matches are a prefix
                     }
                     __syncthreads();
                     // scoring on the matrix cores: a wave takes 16 matches at a time.
@@ -1116,9 +1119,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         const int mrow = lane & 15, kq = lane >> 4;
                         const uint32_t KCH = d >> 2;
                         const uint32_t nrb = (R + 15) / 16;
-                        // FP32 operands: d products, each rounded once, then the sum.
-                        // bfloat16 operands: 2d exact products (hi and lo halves), then the sum.
-                        const float gam = gamma_n(static_cast<int>(BF16 ? 2 * d : d) + 3) * 1.001f;
                         for (uint32_t t0 = static_cast<uint32_t>(wv) * 16; t0 < ncnt; t0 += (kBlock / kWave) * 16) {
                             const uint32_t mi = t0 + mrow;
                             const bool mval = mi < ncnt;
@@ -1225,80 +1225,48 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             sup += __shfl_xor(sup, 32, kWave);
                             sum_ += __shfl_xor(sum_, 16, kWave);
                             sum_ += __shfl_xor(sum_, 32, kWave);
+                            if (kq == 0 && mval) {
+                                sub_su_p[mi] = sup;
+                                sub_su_m[mi] = sum_;
+                            }
                             // lane holds D[4*kq + i][mrow] of each relation block: match
-                            // t0 + 4*kq + i, relation 16*rb + mrow.  Keep the relations in
-                            // the match's masks (in relation order) and reduce per-match
-                            // maxima over the 16 lanes of the row.
+                            // t0 + 4*kq + i, relation 16*rb + mrow.  The dot products of
+                            // the relations in the match's masks go to the slab in
+                            // relation order (probe edge, then middle edge).
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const uint32_t m = t0 + 4 * static_cast<uint32_t>(kq) + static_cast<uint32_t>(i);
-                                const bool mv = m < ncnt;
-                                const uint32_t smp = mv ? sub_mp[m] : 0u, smm = mv ? sub_mm[m] : 0u;
-                                const uint32_t vo = mv ? sub_voff[m] : 0u, np = __popc(smp);
-                                // |up| and |um| sums of match 4*kq + i live in lane 4*kq + i
-                                const float su_p = __shfl(sup, 4 * kq + i, kWave);
-                                const float su_m = __shfl(sum_, 4 * kq + i, kWave);
-                                float fP[2], fM[2], eP[2], eM[2];
-#pragma unroll
-                                for (uint32_t rb = 0; rb < 2; ++rb) {
-                                    fP[rb] = -__builtin_huge_valf();
-                                    fM[rb] = -__builtin_huge_valf();
-                                    eP[rb] = 0.0f;
-                                    eM[rb] = 0.0f;
-                                    const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
-                                    if (rb < nrb && mv && r < R) {
-                                        if ((smp >> r) & 1u) {
-                                            float fe;
-                                            fP[rb] = centred_logsigmoid_e(aP[rb][i], fe);
-                                            eP[rb] = gam * ymax[r] * su_p + fe;
-                                        }
-                                        if ((smm >> r) & 1u) {
-                                            float fe;
-                                            fM[rb] = centred_logsigmoid_e(aM[rb][i], fe);
-                                            eM[rb] = gam * ymax[r] * su_m + fe;
-                                        }
-                                    }
-                                }
-                                float mxp = -__builtin_huge_valf(), axp = 0.0f, exp_ = 0.0f;
-                                float mxm = -__builtin_huge_valf(), axm = 0.0f, exm = 0.0f;
+                                if (m >= ncnt) continue;
+                                const uint32_t smp = sub_mp[m], smm = sub_mm[m];
+                                const uint32_t vo = sub_voff[m], np = __popc(smp);
 #pragma unroll
                                 for (uint32_t rb = 0; rb < 2; ++rb) {
                                     const uint32_t r = rb * 16 + static_cast<uint32_t>(mrow);
-                                    if (rb < nrb && mv && r < R) {
+                                    if (rb < nrb && r < R) {
                                         const uint32_t below = (1u << r) - 1u;   // relations before r
                                         if ((smp >> r) & 1u) {
                                             const uint32_t ix = vo + __popc(smp & below);
-                                            slab[ix] = fP[rb];
+                                            slab[ix] = aP[rb][i];
                                             slab_rel[ix] = static_cast<uint8_t>(r);
-                                            mxp = fmaxf(mxp, fP[rb]);
-                                            axp = fmaxf(axp, fabsf(fP[rb]));
-                                            exp_ = fmaxf(exp_, eP[rb]);
                                         }
                                         if ((smm >> r) & 1u) {
                                             const uint32_t ix = vo + np + __popc(smm & below);
-                                            slab[ix] = fM[rb];
+                                            slab[ix] = aM[rb][i];
                                             slab_rel[ix] = static_cast<uint8_t>(r);
-                                            mxm = fmaxf(mxm, fM[rb]);
-                                            axm = fmaxf(axm, fabsf(fM[rb]));
-                                            exm = fmaxf(exm, eM[rb]);
                                         }
                                     }
                                 }
-                                mxp = row16_max(mxp);
-                                axp = row16_max(axp);
-                                exp_ = row16_max(exp_);
-                                mxm = row16_max(mxm);
-                                axm = row16_max(axm);
-                                exm = row16_max(exm);
-                                if (mv && mrow == 0) {
-                                    agg[m] = mxp;
-                                    agg[kBlock + m] = axp;
-                                    agg[2 * kBlock + m] = exp_;
-                                    agg[3 * kBlock + m] = mxm;
-                                    agg[4 * kBlock + m] = axm;
-                                    agg[5 * kBlock + m] = exm;
-                                }
                             }
+                        }
+                    }
+                    __syncthreads();
+                    // centred log-sigmoids of the sub-batch's dot products, dense
+                    // over the block
+                    {
+                        const uint32_t vn = sh->vn;
+                        for (uint32_t ix = tid; ix < vn; ix += kBlock) {
+                            float fe;
+                            slab[ix] = centred_logsigmoid_e(slab[ix], fe);
                         }
                     }
                     __syncthreads();
@@ -1317,12 +1285,39 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         if (take) {
                             const RowInfo &ri = rows[sub_row[tid]];
                             const uint32_t np = __popc(sub_mp[tid]), nm = __popc(sub_mm[tid]);
-                            const float ap = agg[kBlock + tid], ep = agg[2 * kBlock + tid];
-                            const float am = agg[4 * kBlock + tid], em = agg[5 * kBlock + tid];
-                            eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (ap + am + ri.famax));
+                            const uint32_t vo = sub_voff[tid];
+                            // per edge of the match: largest value, largest |value|, and
+                            // the largest error bound.  A value's bound is
+                            // gam * ymax[r] * sum_k |u_k| (the dot product) plus the
+                            // log-sigmoid's own error, at most 24 u |f| + 1e-10 on
+                            // either of its paths (the series path's
+                            // 16 u (|x|/2 + x^2/4) + 1e-10 with |x|/2 <= 1.15 |f| and
+                            // x^2/4 <= 0.29 |f| for |x| <= 1/2; the library path's
+                            // 16 u |f|).
+                            float mxp = -__builtin_huge_valf(), axp = 0.0f, yp = 0.0f;
+                            float mxm = -__builtin_huge_valf(), axm = 0.0f, ym = 0.0f;
+                            for (uint32_t k = 0; k < np; ++k) {
+                                const float f = slab[vo + k];
+                                mxp = fmaxf(mxp, f);
+                                axp = fmaxf(axp, fabsf(f));
+                                yp = fmaxf(yp, ymax[slab_rel[vo + k]]);
+                            }
+                            for (uint32_t k = np; k < np + nm; ++k) {
+                                const float f = slab[vo + k];
+                                mxm = fmaxf(mxm, f);
+                                axm = fmaxf(axm, fabsf(f));
+                                ym = fmaxf(ym, ymax[slab_rel[vo + k]]);
+                            }
+                            // FP32 operands: d products, each rounded once, then the
+                            // sum; bfloat16 operands: 2d exact products (hi and lo
+                            // halves), then the sum
+                            const float gam = gamma_n(static_cast<int>(BF16 ? 2 * d : d) + 3) * 1.001f;
+                            const float ep = gam * yp * sub_su_p[tid] + 24.0f * kUnit * axp + 1e-10f;
+                            const float em = gam * ym * sub_su_m[tid] + 24.0f * kUnit * axm + 1e-10f;
+                            eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (axp + axm + ri.famax));
                             npaths += static_cast<uint64_t>(np) * nm * __popc(ri.mask);
                             const float tS0 = EXACT ? thr_exact : sh->thr.s;
-                            if (combine3(fwd, agg[tid], agg[3 * kBlock + tid], ri.fmax) >= tS0)
+                            if (combine3(fwd, mxp, mxm, ri.fmax) >= tS0)
                                 nitems = np * nm;
                             else
                                 sh->truncated = 1;   // no path through this match can be kept
@@ -1343,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         while (nact > 0) {
                             // the free stage slots are shared by the threads still
                             // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT>(list, stage, sh, reinterpret_cast<uint64_t *>(agg));
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT>(list, stage, sh, mkeys);
                             uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
@@ -1450,7 +1445,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         // ---- tile end: final merge and output
         __syncthreads();
-        if (sh->stage_n > 0) merge_stage<KC, EXACT>(list, stage, sh, reinterpret_cast<uint64_t *>(agg));
+        if (sh->stage_n > 0) merge_stage<KC, EXACT>(list, stage, sh, mkeys);
         float em = block_max(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
