@@ -470,6 +470,7 @@ struct GatherShared {
     uint32_t truncated;
     uint32_t E;           // entries in the current row batch
     uint32_t rowvals;
+    uint32_t sel_prefix, sel_need, sel_hi, sel_eq;   // stage-merge selection
     uint32_t vn;          // values in the current sub-batch's slab
     uint32_t pad[2];
     Cand thr;             // current worst kept candidate (sentinel until the list fills)
@@ -503,7 +504,7 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     L.qmp = o; o = align16(o + kQueue * 4);
     L.qy = o; o = align16(o + kQueue * 4);
     L.sub = o; o = align16(o + kBlock * kSubFields * 4);
-    L.mkeys = o; o = align16(o + size_t(next_pow2(kStage + kc)) * 8);
+    L.mkeys = o; o = align16(o + 256 * 4);
     L.slab = o; o = align16(o + kSlab * 4);
     L.list = o; o = align16(o + size_t(kc) * sizeof(Cand));
     L.stage = o; o = align16(o + size_t(next_pow2(kStage + kc)) * sizeof(Cand));
@@ -624,21 +625,19 @@ __device__ inline void block_sort_keys_desc(uint64_t *keys, uint32_t n2) {
 }
 
 // Merges the staged candidates into the tile's list.
-// Fast pass: the best KC of list + stage by fast-pass score, in descending
-// score order (ties in any order: a tie at the list's end marks the tile
-// truncated at that score, and the band is re-sorted by the total order
-// after rescoring).  The bitonic sort runs on 8-byte keys (score key, slot)
-// in `keys` (next_pow2(kStage + KC) entries); only the KC winners are
-// gathered.
+// Fast pass: the best KC of list + stage by fast-pass score (ties at the
+// KC-th score in any order: dropping one marks the tile truncated at that
+// score, and the band is re-sorted by the total order after rescoring); see
+// below.  `hist` is scratch of 256 words.
 // Exhaustive pass (EXACT): the scores are final, so the list keeps the best
 // KC under the total order (score, then ids) and the whole candidates are
 // sorted.
 template <int KC, bool EXACT>
-__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint64_t *keys) {
+__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint32_t *hist) {
     const uint32_t ns = sh->stage_n;
-    const uint32_t tot = ns + KC;
-    const uint32_t n2 = next_pow2(tot);
     if (EXACT) {
+        const uint32_t tot = ns + KC;
+        const uint32_t n2 = next_pow2(tot);
         for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
             if (i >= ns && i < tot) stage[i] = list[i - ns];
             else if (i >= tot) stage[i] = cand_sentinel();
@@ -656,25 +655,83 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, ui
         __syncthreads();
         return;
     }
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) stage[ns + i] = list[i];
+    // fast pass: the best KC of the staged and kept candidates, in no
+    // particular order except that the last slot holds a kept minimum (the
+    // threshold for later candidates).  A radix select over the 32-bit score
+    // keys, 8 bits per pass from the top, finds the KC-th largest key T; every
+    // candidate above T is kept, and as many at T as fit.
+    const uint32_t ln = sh->list_n;
+    const uint32_t real = ns + ln;
+    for (uint32_t i = threadIdx.x; i < ln; i += blockDim.x) stage[ns + i] = list[i];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x)
-        keys[i] = i < tot ? (static_cast<uint64_t>(fkey(stage[i].s)) << 32) | i : 0ull;
+    if (real < static_cast<uint32_t>(KC)) {
+        for (uint32_t i = threadIdx.x; i < real; i += blockDim.x) list[i] = stage[i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh->list_n = real;
+            sh->stage_n = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    uint32_t prefix = 0, pmask = 0, need = KC;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < real; i += blockDim.x) {
+            const uint32_t key = fkey(stage[i].s);
+            if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < static_cast<uint32_t>(kWave)) {
+            // lane l holds bins 4l..4l+3; the bin where the count from the top
+            // reaches `need` fixes the next 8 bits
+            const uint32_t lane = threadIdx.x;
+            const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2],
+                           h3 = hist[4 * lane + 3];
+            const uint32_t own = h0 + h1 + h2 + h3;
+            uint32_t incl = own;   // this lane's bins and all higher ones
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t t = __shfl_down(incl, off, kWave);
+                if (lane + off < static_cast<uint32_t>(kWave)) incl += t;
+            }
+            const uint32_t above = incl - own;
+            if (above < need && need <= incl) {
+                uint32_t acc = above, b;
+                if (acc + h3 >= need) b = 3;
+                else if (acc += h3, acc + h2 >= need) b = 2;
+                else if (acc += h2, acc + h1 >= need) b = 1;
+                else { acc += h1; b = 0; }
+                sh->sel_prefix = prefix | ((4 * lane + b) << shift);
+                sh->sel_need = need - acc;
+            }
+        }
+        if (threadIdx.x == 0) {
+            sh->sel_hi = 0;
+            sh->sel_eq = 0;
+        }
+        __syncthreads();
+        prefix = sh->sel_prefix;
+        need = sh->sel_need;
+        pmask |= 255u << shift;
+    }
+    // keys above T fill the list from the front, the kept ones at T from the back
+    for (uint32_t i = threadIdx.x; i < real; i += blockDim.x) {
+        const uint32_t key = fkey(stage[i].s);
+        if (key > prefix) {
+            list[atomicAdd(&sh->sel_hi, 1u)] = stage[i];
+        } else if (key == prefix) {
+            const uint32_t e = atomicAdd(&sh->sel_eq, 1u);
+            if (e < need) list[KC - 1 - e] = stage[i];
+        }
+    }
     __syncthreads();
-    block_sort_keys_desc(keys, n2);
     if (threadIdx.x == 0) {
-        const uint64_t kk = keys[KC];
-        if (kk != 0ull && stage[static_cast<uint32_t>(kk)].a != 0xFFFFFFFFu) sh->truncated = 1;  // a real candidate fell off
-        uint32_t cnt = sh->list_n + ns;
-        sh->list_n = cnt < static_cast<uint32_t>(KC) ? cnt : KC;
+        if (real > static_cast<uint32_t>(KC)) sh->truncated = 1;   // a real candidate fell off
+        sh->list_n = KC;
         sh->stage_n = 0;
+        sh->thr = list[KC - 1];
     }
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(KC); i += blockDim.x) {
-        const uint64_t kk = keys[i];
-        list[i] = kk != 0ull ? stage[static_cast<uint32_t>(kk)] : cand_sentinel();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) sh->thr = (sh->list_n == static_cast<uint32_t>(KC)) ? list[KC - 1] : cand_sentinel();
     __syncthreads();
 }
 
@@ -777,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     Cand *stage = reinterpret_cast<Cand *>(smem + Lo.stage);
     GatherShared *sh = reinterpret_cast<GatherShared *>(smem + Lo.shared);
     float *ymax = reinterpret_cast<float *>(smem + Lo.ymax);
-    uint64_t *mkeys = reinterpret_cast<uint64_t *>(smem + Lo.mkeys);  // stage-merge sort keys
+    uint32_t *mkeys = reinterpret_cast<uint32_t *>(smem + Lo.mkeys);  // stage-merge histogram
     uint8_t *rowrel = reinterpret_cast<uint8_t *>(smem + Lo.rowrel);
     uint8_t *slab_rel = reinterpret_cast<uint8_t *>(smem + Lo.slab_rel);
     float *sub_su_p = reinterpret_cast<float *>(sub);   // sum_k |up_k| per match (scoring)
@@ -1294,19 +1351,33 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             // 16 u (|x|/2 + x^2/4) + 1e-10 with |x|/2 <= 1.15 |f| and
                             // x^2/4 <= 0.29 |f| for |x| <= 1/2; the library path's
                             // 16 u |f|).
+                            // (four values per step, their loads issued together)
                             float mxp = -__builtin_huge_valf(), axp = 0.0f, yp = 0.0f;
                             float mxm = -__builtin_huge_valf(), axm = 0.0f, ym = 0.0f;
-                            for (uint32_t k = 0; k < np; ++k) {
-                                const float f = slab[vo + k];
-                                mxp = fmaxf(mxp, f);
-                                axp = fmaxf(axp, fabsf(f));
-                                yp = fmaxf(yp, ymax[slab_rel[vo + k]]);
-                            }
-                            for (uint32_t k = np; k < np + nm; ++k) {
-                                const float f = slab[vo + k];
-                                mxm = fmaxf(mxm, f);
-                                axm = fmaxf(axm, fabsf(f));
-                                ym = fmaxf(ym, ymax[slab_rel[vo + k]]);
+                            for (uint32_t k0 = 0; k0 < np + nm; k0 += 4) {
+                                float f[4], yv[4];
+                                uint32_t rr[4];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const bool ok = k0 + j < np + nm;
+                                    f[j] = ok ? slab[vo + k0 + j] : 0.0f;
+                                    rr[j] = ok ? slab_rel[vo + k0 + j] : 0u;
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) yv[j] = ymax[rr[j]];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const uint32_t k = k0 + j;
+                                    if (k < np) {
+                                        mxp = fmaxf(mxp, f[j]);
+                                        axp = fmaxf(axp, fabsf(f[j]));
+                                        yp = fmaxf(yp, yv[j]);
+                                    } else if (k < np + nm) {
+                                        mxm = fmaxf(mxm, f[j]);
+                                        axm = fmaxf(axm, fabsf(f[j]));
+                                        ym = fmaxf(ym, yv[j]);
+                                    }
+                                }
                             }
                             // FP32 operands: d products, each rounded once, then the
                             // sum; bfloat16 operands: 2d exact products (hi and lo
@@ -1844,6 +1915,9 @@ WsLayout ws_layout(uint32_t nq, uint32_t kc) {
 int g_num_cus = 0;
 
 constexpr size_t kLdsBytes = 160 * 1024;
+// dynamic LDS a gather workgroup may take: the CU's LDS less a reserve for
+// the kernels' own static shared variables (a few hundred bytes)
+constexpr size_t kDynLdsBytes = kLdsBytes - 1024;
 
 // The probe-table size: the caller's choice, else the largest table of at
 // most 2^kDefaultHashLog2 slots whose gather workgroup fits in LDS (large
@@ -1851,7 +1925,7 @@ constexpr size_t kLdsBytes = 160 * 1024;
 uint32_t hash_log2_for(const mhr_graph *g, const mhr_query_opts *o, uint32_t kmax) {
     if (o && o->hash_log2) return o->hash_log2;
     uint32_t h = kDefaultHashLog2;
-    while (h > 10 && gather_layout(h, g->R, g->dim, kc_for(kmax)).total > kLdsBytes) --h;
+    while (h > 10 && gather_layout(h, g->R, g->dim, kc_for(kmax)).total > kDynLdsBytes) --h;
     return h;
 }
 
@@ -1990,8 +2064,8 @@ mhr_status topk_impl(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, c
         return MHR_ERR_WORKSPACE_TOO_SMALL;
     }
     const size_t lds = gather_lds_bytes(g, hash_log2_for(g, o, kmax), kmax);
-    if (lds > kLdsBytes) {
-        set_error("LDS demand " + std::to_string(lds) + " exceeds 160 KiB (reduce hash_log2)");
+    if (lds > kDynLdsBytes) {
+        set_error("LDS demand " + std::to_string(lds) + " exceeds 159 KiB (reduce hash_log2)");
         return MHR_ERR_UNSUPPORTED;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
