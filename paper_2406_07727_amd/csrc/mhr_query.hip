@@ -1020,18 +1020,25 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             // positions and column ids of a chunk's entries; a chunk's ids are
             // loaded while the previous chunk is probed
             auto chunk_entries = [&](uint32_t cb, uint32_t (&ps)[kEPT], uint32_t (&ys)[kEPT]) {
+                // the last row with pref <= e, by halving steps of fixed count
+                // (kRowBatch = 32 rows) taken for all of the thread's entries
+                // together
+                uint32_t lo[kEPT];
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) lo[k] = 0;
+#pragma unroll
+                for (uint32_t step = kRowBatch / 2; step > 0; step >>= 1) {
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        const uint32_t e = cb + k * kBlock + tid;
+                        const uint32_t c = lo[k] + step;
+                        if (c < nrows && rows[c].pref <= e) lo[k] = c;
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
-                    uint32_t e = cb + k * kBlock + tid;
-                    ps[k] = kEmpty;
-                    if (e < E) {
-                        uint32_t lo = 0, hi = nrows;  // last row with pref <= e
-                        while (hi - lo > 1) {
-                            uint32_t mid = (lo + hi) >> 1;
-                            if (rows[mid].pref <= e) lo = mid; else hi = mid;
-                        }
-                        ps[k] = rows[lo].beg + (e - rows[lo].pref);
-                    }
+                    const uint32_t e = cb + k * kBlock + tid;
+                    ps[k] = e < E ? rows[lo[k]].beg + (e - rows[lo[k]].pref) : kEmpty;
                 }
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) ys[k] = (ps[k] != kEmpty) ? Lcol[ps[k]] : kEmpty;
@@ -1049,18 +1056,26 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 }
                 if (!last) chunk_entries(cb + kChunk, ps_n, ys_n);
                 if (!heavy) {
+                    // first probe of every entry together, then the rare
+                    // collision chains
+                    uint32_t slot[kEPT], key[kEPT];
 #pragma unroll
                     for (int k = 0; k < kEPT; ++k) {
+                        slot[k] = (ys[k] * 0x9E3779B1u) >> (32 - A.hash_log2);
+                        key[k] = ps[k] != kEmpty ? hkeys[slot[k]] : kEmpty;
+                    }
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        const uint32_t y = ys[k];
                         hits[k] = false;
                         mps[k] = 0;
-                        if (ps[k] == kEmpty) continue;
-                        const uint32_t y = ys[k];
-                        uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
-                        for (;;) {
-                            uint32_t key = hkeys[slot];
-                            if (key == y) { hits[k] = true; mps[k] = hvals[slot]; break; }
-                            if (key == kEmpty) break;
-                            slot = (slot + 1) & smask;
+                        while (key[k] != kEmpty && key[k] != y) {
+                            slot[k] = (slot[k] + 1) & smask;
+                            key[k] = hkeys[slot[k]];
+                        }
+                        if (ps[k] != kEmpty && key[k] == y) {
+                            hits[k] = true;
+                            mps[k] = hvals[slot[k]];
                         }
                     }
                 } else {
@@ -1105,20 +1120,30 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         mps[k] = hits[k] ? Pmask[P.probe_beg + at[k]] : 0u;
                     }
                 }
-                const int lane = tid & (kWave - 1);
+                {
+                    // one queue reservation per wave for all of its hits
+                    const int lane = tid & (kWave - 1);
+                    uint64_t bal[kEPT];
+                    uint32_t wtot = 0;
 #pragma unroll
-                for (int k = 0; k < kEPT; ++k) {
-                    uint64_t bal = __ballot(hits[k]);
-                    if (bal) {
+                    for (int k = 0; k < kEPT; ++k) {
+                        bal[k] = __ballot(hits[k]);
+                        wtot += static_cast<uint32_t>(__popcll(bal[k]));
+                    }
+                    if (wtot) {
                         uint32_t base = 0;
-                        if (lane == 0) base = atomicAdd(&sh->qcount, static_cast<uint32_t>(__popcll(bal)));
+                        if (lane == 0) base = atomicAdd(&sh->qcount, wtot);
                         base = __shfl(base, 0, kWave);
-                        if (hits[k]) {
-                            uint64_t lt = lane ? (bal & (~0ull >> (kWave - lane))) : 0ull;
-                            uint32_t slotq = base + __popcll(lt);
-                            qpos[slotq] = ps[k];
-                            qmp[slotq] = mps[k];
-                            qy[slotq] = ys[k];
+                        const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;   // lanes below this one
+#pragma unroll
+                        for (int k = 0; k < kEPT; ++k) {
+                            if (hits[k]) {
+                                const uint32_t slotq = base + static_cast<uint32_t>(__popcll(bal[k] & lt));
+                                qpos[slotq] = ps[k];
+                                qmp[slotq] = mps[k];
+                                qy[slotq] = ys[k];
+                            }
+                            base += static_cast<uint32_t>(__popcll(bal[k]));
                         }
                     }
                 }
@@ -1135,10 +1160,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         mp = qmp[mi];
                         y = qy[mi];
                         mm = Lmask[pos];
-                        uint32_t lo = 0, hi = nrows;  // row holding pos
-                        while (hi - lo > 1) {
-                            uint32_t mid = (lo + hi) >> 1;
-                            if (rows[mid].beg <= pos) lo = mid; else hi = mid;
+                        uint32_t lo = 0;  // row holding pos (the last with beg <= pos)
+#pragma unroll
+                        for (uint32_t step = kRowBatch / 2; step > 0; step >>= 1) {
+                            const uint32_t c = lo + step;
+                            if (c < nrows && rows[c].beg <= pos) lo = c;
                         }
                         row = lo;
                         nv2 = __popc(mp) + __popc(mm);
