@@ -39,7 +39,7 @@ namespace mhr {
 namespace {
 
 constexpr int kBlock = 512;
-constexpr int kEPT = 4;                   // scan entries per thread per chunk
+constexpr int kEPT = 8;                   // scan entries per thread per chunk
 constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
 constexpr int kSlab = 2560;               // scored edge values per sub-batch
@@ -482,7 +482,7 @@ struct GatherShared {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 struct GatherLayout {
-    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, qy, sub, slab, list, stage,
+    size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, sub, slab, list, stage,
         ymax, rowrel, slab_rel, mkeys, shared, total;
 };
 
@@ -502,7 +502,6 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     L.roweps = o; o = align16(o + size_t(kRowBatch) * R * 4);
     L.qpos = o; o = align16(o + kQueue * 4);
     L.qmp = o; o = align16(o + kQueue * 4);
-    L.qy = o; o = align16(o + kQueue * 4);
     L.sub = o; o = align16(o + kBlock * kSubFields * 4);
     L.mkeys = o; o = align16(o + 256 * 4);
     L.slab = o; o = align16(o + kSlab * 4);
@@ -827,7 +826,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     float *roweps = reinterpret_cast<float *>(smem + Lo.roweps);
     uint32_t *qpos = reinterpret_cast<uint32_t *>(smem + Lo.qpos);
     uint32_t *qmp = reinterpret_cast<uint32_t *>(smem + Lo.qmp);
-    uint32_t *qy = reinterpret_cast<uint32_t *>(smem + Lo.qy);
     uint32_t *sub = reinterpret_cast<uint32_t *>(smem + Lo.sub);
     float *slab = reinterpret_cast<float *>(smem + Lo.slab);
     Cand *list = reinterpret_cast<Cand *>(smem + Lo.list);
@@ -1141,7 +1139,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 const uint32_t slotq = base + static_cast<uint32_t>(__popcll(bal[k] & lt));
                                 qpos[slotq] = ps[k];
                                 qmp[slotq] = mps[k];
-                                qy[slotq] = ys[k];
                             }
                             base += static_cast<uint32_t>(__popcll(bal[k]));
                         }
@@ -1158,7 +1155,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     if (mi < nmatch) {
                         pos = qpos[mi];
                         mp = qmp[mi];
-                        y = qy[mi];
+                        y = Lcol[pos];
                         mm = Lmask[pos];
                         uint32_t lo = 0;  // row holding pos (the last with beg <= pos)
 #pragma unroll
@@ -1522,17 +1519,15 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 // queue's front; the next chunk appends after them
                 const uint32_t rem = nmatch - m0;
                 if (rem > 0 && m0 > 0) {
-                    uint32_t p_ = 0, mp_ = 0, y_ = 0;
+                    uint32_t p_ = 0, mp_ = 0;
                     if (tid < rem) {
                         p_ = qpos[m0 + tid];
                         mp_ = qmp[m0 + tid];
-                        y_ = qy[m0 + tid];
                     }
                     __syncthreads();
                     if (tid < rem) {
                         qpos[tid] = p_;
                         qmp[tid] = mp_;
-                        qy[tid] = y_;
                     }
                 }
                 if (tid == 0) sh->qcount = rem;
