@@ -160,28 +160,39 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
         if (threadIdx.x == 0) A.plans[q] = P;
         return;
     }
+    // Summed degrees of a list row's neighbours (their scanned rows), over
+    // entries [base, base + kPlanSpan) of the list: each thread loads its
+    // entries' ids together, then their row bounds together.
+    constexpr int kPlanU = 4;
+    constexpr uint32_t kPlanSpan = kPlanU * kBlock;
+    auto span_cost = [&](const uint32_t *rp, const uint32_t *col, uint32_t beg, uint32_t len, const uint8_t *keep,
+                         uint32_t base) -> uint64_t {
+        uint32_t x[kPlanU];
+        bool ok[kPlanU];
+#pragma unroll
+        for (int u = 0; u < kPlanU; ++u) {
+            const uint32_t i = base + u * kBlock + threadIdx.x;
+            ok[u] = i < len && (!keep || keep[i]);
+            x[u] = ok[u] ? col[beg + i] : 0u;
+        }
+        uint64_t p = 0;
+#pragma unroll
+        for (int u = 0; u < kPlanU; ++u)
+            if (ok[u]) p += rp[x[u] + 1] - rp[x[u]];
+        return p;
+    };
     // backward: list N-(t) (reverse CSR row of t), scanned rows in the reverse CSR
     const uint32_t lb_beg = A.in_rp[P.t], lb_len = A.in_rp[P.t + 1] - lb_beg;
     const uint8_t *kb = keep_row(A, q, P.s, true), *kf = keep_row(A, q, P.s, false);
     uint64_t part = 0;
-    for (uint32_t i = threadIdx.x; i < lb_len; i += kBlock) {
-        uint32_t b = A.in_col[lb_beg + i];
-        if (!kb || kb[i]) part += A.in_rp[b + 1] - A.in_rp[b];
-    }
+    for (uint32_t base = 0; base < lb_len; base += kPlanSpan) part += span_cost(A.in_rp, A.in_col, lb_beg, lb_len, kb, base);
     const uint64_t cost_b = block_sum<uint64_t>(part, red64);
     // forward: list N+(s), scanned rows in the forward CSR; stop once it
     // cannot beat the backward cost
     const uint32_t lf_beg = A.out_rp[P.s], lf_len = A.out_rp[P.s + 1] - lf_beg;
     uint64_t cost_f = 0;
-    for (uint32_t base = 0; base < lf_len && cost_f < cost_b; base += kBlock) {
-        uint64_t p = 0;
-        uint32_t i = base + threadIdx.x;
-        if (i < lf_len && (!kf || kf[i])) {
-            uint32_t a = A.out_col[lf_beg + i];
-            p = A.out_rp[a + 1] - A.out_rp[a];
-        }
-        cost_f += block_sum<uint64_t>(p, red64);
-    }
+    for (uint32_t base = 0; base < lf_len && cost_f < cost_b; base += kPlanSpan)
+        cost_f += block_sum<uint64_t>(span_cost(A.out_rp, A.out_col, lf_beg, lf_len, kf, base), red64);
     const bool fwd = cost_f < cost_b;
     P.dir = fwd ? 1u : 0u;
     P.cost = fwd ? cost_f : cost_b;
@@ -249,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
         tile *= 2;
     }
     if (threadIdx.x == 0) carry = 0;
+    for (uint32_t i = threadIdx.x; i < kOrderClasses; i += kBlock) cls_base[i] = 0;   // tiles per class
     __syncthreads();
     for (uint32_t base = 0; base < A.nq; base += kBlock) {
         const uint32_t q = base + threadIdx.x;
@@ -262,25 +274,19 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
         const uint32_t c = carry;
         if (q < A.nq) {
             const uint32_t tb = c + incl - nt;
+            const uint32_t len = nt ? static_cast<uint32_t>(tile_len_for(A.plans[q].cost, tile)) : 0u;
             A.plans[q].ntiles = nt;
             A.plans[q].tile_base = tb;
             A.plans[q].flags = 0;
-            A.plans[q].pad[0] = nt ? static_cast<uint32_t>(tile_len_for(A.plans[q].cost, tile)) : 0u;  // tile length
+            A.plans[q].pad[0] = len;  // tile length
             for (uint32_t j = 0; j < nt; ++j) A.tile_q[tb + j] = q;
+            if (nt) atomicAdd(&cls_base[kOrderClasses - 1 - order_class(len, A.plans[q].probe_len)], nt);
         }
         __syncthreads();
         if (threadIdx.x == 0) carry = c + tot;
         __syncthreads();
     }
-    // tiles per class, highest class first
-    for (uint32_t i = threadIdx.x; i < kOrderClasses; i += kBlock) cls_base[i] = 0;
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
-        const QueryPlan &P = A.plans[q];
-        if (P.status == 0 && P.ntiles)
-            atomicAdd(&cls_base[kOrderClasses - 1 - order_class(P.pad[0], P.probe_len)], P.ntiles);
-    }
-    __syncthreads();
+    // class bases, highest class first
     {
         static_assert(kOrderClasses <= kBlock, "one class per thread");
         const uint32_t v = threadIdx.x < kOrderClasses ? cls_base[threadIdx.x] : 0u;
