@@ -6,15 +6,17 @@
 //             meet-in-the-middle costs (backward: sum of in-degrees of
 //             N-(t); forward: sum of out-degrees of N+(s)), picks the
 //             cheaper direction and cuts the scan into tiles.
-//   schedule  one workgroup: prefix of tile counts, tile -> query map.
+//   schedule  one workgroup: prefix of tile counts, tile -> query map, and
+//             the order the gather takes tiles in (longest expected first).
 //   gather    persistent workgroups pulling tiles from an atomic counter.
 //             A tile builds a membership table of the probe side (LDS hash
 //             or, for long rows, the graph's bucket directory), streams the
 //             CSR rows of its list slice, tests each scanned vertex, scores
 //             every matched middle edge and the two outer edges in FP32 with
 //             a rigorous error bound, enumerates the paths through it and
-//             keeps the best KC by the total order.
-//   merge     one workgroup per query: merges the tile lists, takes every
+//             keeps the best KC by fast-pass score.
+//   merge     one workgroup per query: selects the best KC over the tile
+//             lists, takes every
 //             candidate whose score lies within twice the error bound of the
 //             K-th, rescores them in float-float and writes the ranked
 //             result.  If a truncated tile could still hold a band member
@@ -25,8 +27,9 @@
 // The paper's CPU design (thread-private K-heaps merged by a tree
 // reduction, section 3.3; level-synchronous frontier expansion, section 5)
 // is the prior art this replaces: here the per-thread heap becomes a
-// per-workgroup LDS candidate list fed by block-wide threshold filtering,
-// and the reduction tree becomes the per-query merge of tile lists.
+// per-workgroup LDS candidate list fed by block-wide threshold filtering
+// and trimmed by radix selection, and the reduction tree becomes the
+// per-query selection over tile lists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -181,15 +184,17 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
             if (ok[u]) p += rp[x[u] + 1] - rp[x[u]];
         return p;
     };
-    // backward: list N-(t) (reverse CSR row of t), scanned rows in the reverse CSR
-    const uint32_t lb_beg = A.in_rp[P.t], lb_len = A.in_rp[P.t + 1] - lb_beg;
+    // the endpoints' rows: N-(t) in the reverse CSR, N+(s) in the forward CSR
+    const uint32_t lb_beg = A.in_rp[P.t], lb_end = A.in_rp[P.t + 1];
+    const uint32_t lf_beg = A.out_rp[P.s], lf_end = A.out_rp[P.s + 1];
+    const uint32_t lb_len = lb_end - lb_beg, lf_len = lf_end - lf_beg;
+    // backward: list N-(t), scanned rows in the reverse CSR
     const uint8_t *kb = keep_row(A, q, P.s, true), *kf = keep_row(A, q, P.s, false);
     uint64_t part = 0;
     for (uint32_t base = 0; base < lb_len; base += kPlanSpan) part += span_cost(A.in_rp, A.in_col, lb_beg, lb_len, kb, base);
     const uint64_t cost_b = block_sum<uint64_t>(part, red64);
     // forward: list N+(s), scanned rows in the forward CSR; stop once it
     // cannot beat the backward cost
-    const uint32_t lf_beg = A.out_rp[P.s], lf_len = A.out_rp[P.s + 1] - lf_beg;
     uint64_t cost_f = 0;
     for (uint32_t base = 0; base < lf_len && cost_f < cost_b; base += kPlanSpan)
         cost_f += block_sum<uint64_t>(span_cost(A.out_rp, A.out_col, lf_beg, lf_len, kf, base), red64);
@@ -198,8 +203,8 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
     P.cost = fwd ? cost_f : cost_b;
     P.list_beg = fwd ? lf_beg : lb_beg;
     P.list_len = fwd ? lf_len : lb_len;
-    P.probe_beg = fwd ? A.in_rp[P.t] : A.out_rp[P.s];
-    P.probe_len = fwd ? (A.in_rp[P.t + 1] - P.probe_beg) : (A.out_rp[P.s + 1] - P.probe_beg);
+    P.probe_beg = fwd ? lb_beg : lf_beg;
+    P.probe_len = fwd ? lb_len : lf_len;
     // tile count from the scan cost; the schedule may coarsen it to fit the
     // workspace
     P.ntiles = (P.cost > 0 && P.probe_len > 0) ? 1u : 0u;
@@ -212,16 +217,21 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(GArgs A, const uint32_t *s
 // Tile length for a query: about `tile` scan entries, at most
 // kMaxTilesPerQuery tiles.  The tile count is then ceil(cost / length), so
 // every tile start j * length lies below cost.
+// ceil(a / b), in 32-bit arithmetic when both fit
+__device__ inline uint64_t div_up(uint64_t a, uint64_t b) {
+    if (((a + b) >> 32) == 0) return (static_cast<uint32_t>(a) + static_cast<uint32_t>(b) - 1u) / static_cast<uint32_t>(b);
+    return (a + b - 1) / b;
+}
+
 __device__ inline uint64_t tile_len_for(uint64_t cost, uint64_t tile) {
-    uint64_t nt = (cost + tile - 1) / tile;
+    uint64_t nt = div_up(cost, tile);
     if (nt > kMaxTilesPerQuery) nt = kMaxTilesPerQuery;
-    return (cost + nt - 1) / nt;
+    return div_up(cost, nt);
 }
 
 __device__ inline uint32_t tiles_for(uint64_t cost, uint64_t tile) {
     if (cost == 0) return 0u;
-    const uint64_t L = tile_len_for(cost, tile);
-    return static_cast<uint32_t>((cost + L - 1) / L);
+    return static_cast<uint32_t>(div_up(cost, tile_len_for(cost, tile)));
 }
 
 // Order class of a query's tiles, larger for longer expected tiles.  A
@@ -243,18 +253,57 @@ __device__ inline uint32_t order_class(uint64_t tile_len, uint32_t probe_len) {
 // and the order in which the gather takes the tiles: longest expected first,
 // so that the last tiles to start are short ones (a counting sort over the
 // order classes; tiles of one class in any order).
+// Batches of up to kSchedCache queries keep each query's scan cost, probe
+// length and tile fields in LDS, read from the plans in one round of loads;
+// larger batches read the plans again in each pass.
+constexpr uint32_t kSchedCache = 4096;
+constexpr size_t kSchedLds = size_t(kSchedCache) * (8 + 4 * 4);
+
 __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
     __shared__ uint32_t red[kBlock / kWave];
     __shared__ uint64_t red64[kBlock / kWave];
     __shared__ uint32_t carry;
     __shared__ uint32_t cls_base[kOrderClasses];
+    extern __shared__ __align__(16) unsigned char sched_smem[];
+    uint64_t *c_cost = reinterpret_cast<uint64_t *>(sched_smem);   // 0: no tiles
+    uint32_t *c_probe = reinterpret_cast<uint32_t *>(c_cost + kSchedCache);
+    uint32_t *c_nt = c_probe + kSchedCache, *c_tb = c_nt + kSchedCache, *c_len = c_tb + kSchedCache;
+    const bool cached = A.nq <= kSchedCache;
+    if (cached) {
+        constexpr int U = kSchedCache / kBlock;
+        uint64_t cs[U];
+        uint32_t pl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t q = u * kBlock + threadIdx.x;
+            cs[u] = 0;
+            pl[u] = 0;
+            if (q < A.nq) {
+                const QueryPlan &P = A.plans[q];
+                const bool has = P.status == 0 && P.ntiles;
+                cs[u] = has ? P.cost : 0u;
+                pl[u] = P.probe_len;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t q = u * kBlock + threadIdx.x;
+            if (q < A.nq) {
+                c_cost[q] = cs[u];
+                c_probe[q] = pl[u];
+            }
+        }
+        __syncthreads();
+    }
+    auto qcost = [&](uint32_t q) -> uint64_t {
+        if (cached) return c_cost[q];
+        const QueryPlan &P = A.plans[q];
+        return (P.status == 0 && P.ntiles) ? P.cost : 0u;
+    };
     uint64_t tile = A.tile_edges;
     for (;;) {
         uint64_t part = 0;
-        for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
-            const QueryPlan &P = A.plans[q];
-            if (P.status == 0 && P.ntiles) part += tiles_for(P.cost, tile);
-        }
+        for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) part += tiles_for(qcost(q), tile);
         const uint64_t tot = block_sum<uint64_t>(part, red64);
         if (tot <= A.tcap) break;
         tile *= 2;
@@ -264,23 +313,28 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
     __syncthreads();
     for (uint32_t base = 0; base < A.nq; base += kBlock) {
         const uint32_t q = base + threadIdx.x;
-        uint32_t nt = 0;
-        if (q < A.nq) {
-            const QueryPlan &P = A.plans[q];
-            if (P.status == 0 && P.ntiles) nt = tiles_for(P.cost, tile);
-        }
+        const uint64_t cost = q < A.nq ? qcost(q) : 0u;
+        const uint32_t nt = tiles_for(cost, tile);
         uint32_t tot;
         const uint32_t incl = block_incl_scan<uint32_t>(nt, red, &tot);
         const uint32_t c = carry;
         if (q < A.nq) {
             const uint32_t tb = c + incl - nt;
-            const uint32_t len = nt ? static_cast<uint32_t>(tile_len_for(A.plans[q].cost, tile)) : 0u;
+            const uint32_t len = nt ? static_cast<uint32_t>(tile_len_for(cost, tile)) : 0u;
             A.plans[q].ntiles = nt;
             A.plans[q].tile_base = tb;
             A.plans[q].flags = 0;
             A.plans[q].pad[0] = len;  // tile length
             for (uint32_t j = 0; j < nt; ++j) A.tile_q[tb + j] = q;
-            if (nt) atomicAdd(&cls_base[kOrderClasses - 1 - order_class(len, A.plans[q].probe_len)], nt);
+            if (nt) {
+                const uint32_t pl = cached ? c_probe[q] : A.plans[q].probe_len;
+                atomicAdd(&cls_base[kOrderClasses - 1 - order_class(len, pl)], nt);
+            }
+            if (cached) {
+                c_nt[q] = nt;
+                c_tb[q] = tb;
+                c_len[q] = len;
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) carry = c + tot;
@@ -296,10 +350,22 @@ __global__ __launch_bounds__(kBlock) void schedule_kernel(GArgs A) {
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < A.nq; q += kBlock) {
-        const QueryPlan &P = A.plans[q];
-        if (P.status == 0 && P.ntiles) {
-            const uint32_t at = atomicAdd(&cls_base[kOrderClasses - 1 - order_class(P.pad[0], P.probe_len)], P.ntiles);
-            for (uint32_t j = 0; j < P.ntiles; ++j) A.tile_order[at + j] = P.tile_base + j;
+        uint32_t nt, tb, len, pl;
+        if (cached) {
+            nt = c_nt[q];
+            tb = c_tb[q];
+            len = c_len[q];
+            pl = c_probe[q];
+        } else {
+            const QueryPlan &P = A.plans[q];
+            nt = P.status == 0 ? P.ntiles : 0u;
+            tb = P.tile_base;
+            len = P.pad[0];
+            pl = P.probe_len;
+        }
+        if (nt) {
+            const uint32_t at = atomicAdd(&cls_base[kOrderClasses - 1 - order_class(len, pl)], nt);
+            for (uint32_t j = 0; j < nt; ++j) A.tile_order[at + j] = tb + j;
         }
     }
     if (threadIdx.x == 0) {
@@ -855,6 +921,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     const int gid = static_cast<int>(tid) / G, glane = static_cast<int>(tid) % G;
     const int ngroups = kBlock / G;
 
+    if (EXACT && A.ctrl->exact_n == 0) return;   // no query needs the exhaustive pass
     const uint32_t ystr = d + 4;  // padded row stride of the relation table in LDS
     for (uint32_t i = tid; i < R * d; i += kBlock) Ys[(i / d) * ystr + i % d] = load1<BF16>(A.Y, i);
     __syncthreads();
@@ -2005,7 +2072,9 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
 
     MHR_HIP_TRY(rec(ev ? ev->begin : nullptr));
     hipLaunchKernelGGL(plan_kernel, dim3(nq), dim3(kBlock), 0, st, A, src, dst, k, kdef, kmax);
-    hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kBlock), 0, st, A);
+    MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(schedule_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kSchedLds)));
+    hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kBlock), nq <= kSchedCache ? kSchedLds : 0, st, A);
     hipLaunchKernelGGL(tile_starts_kernel, dim3(nq), dim3(kBlock), 0, st, A);
     auto gk = gather_kernel<BF16, false, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(gk),
