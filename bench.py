@@ -230,8 +230,8 @@ def main():
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(queries would shard by query across GPUs; see DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(queries are independent and would be dealt out across GPUs by planning cost).", file=sys.stderr)
         sys.exit(2)
 
     if args.calibrate_copy:

@@ -269,7 +269,7 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
  * The generic search of section 5 bounds each level's frontier by a per-
  * parent top-K; here a small network ranks a query's frontier candidates
  * instead, so that cold ones are skipped, and the exact search stays as the
- * fallback and as the judge of its recall.  Candidates of a query (s, t):
+ * fallback and as the reference for its recall.  Candidates of a query (s, t):
  *   first hop   one per relation r1 of each entry a of s's out-row (edge s -r1-> a)
  *   second hop  one per relation r3 of each entry b of t's in-row  (edge b -r3-> t)
  * Network input f = [X[u], X[w], X[v], Y[r]]: v the candidate vertex (a or
