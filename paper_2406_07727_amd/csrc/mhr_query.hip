@@ -889,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const GatherLayout Lo = gather_layout(A.hash_log2, A.R, A.d, KC);
     uint32_t *hkeys = reinterpret_cast<uint32_t *>(smem + Lo.hkeys);
-    uint32_t *hvals = reinterpret_cast<uint32_t *>(smem + Lo.hvals);
+    uint32_t *hvals = reinterpret_cast<uint32_t *>(smem + Lo.hvals);   // probe-row index of each key
     float *Ys = reinterpret_cast<float *>(smem + Lo.Y);
     float *anc_p = reinterpret_cast<float *>(smem + Lo.anc_p);
     float *anc_l = reinterpret_cast<float *>(smem + Lo.anc_l);
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     float *rowval = reinterpret_cast<float *>(smem + Lo.rowval);
     float *roweps = reinterpret_cast<float *>(smem + Lo.roweps);
     uint32_t *qpos = reinterpret_cast<uint32_t *>(smem + Lo.qpos);
-    uint32_t *qmp = reinterpret_cast<uint32_t *>(smem + Lo.qmp);
+    uint32_t *qmp = reinterpret_cast<uint32_t *>(smem + Lo.qmp);   // queued hit's index in the probe row
     uint32_t *sub = reinterpret_cast<uint32_t *>(smem + Lo.sub);
     float *slab = reinterpret_cast<float *>(smem + Lo.slab);
     Cand *list = reinterpret_cast<Cand *>(smem + Lo.list);
@@ -997,11 +997,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             for (uint32_t i = tid; i < P.probe_len; i += kBlock) {
                 if (kp && !kp[i]) continue;   // pruned away
                 uint32_t y = Pcol[P.probe_beg + i];
-                uint32_t m = Pmask[P.probe_beg + i];
                 uint32_t slot = (y * 0x9E3779B1u) >> (32 - A.hash_log2);
                 for (;;) {
                     uint32_t old = atomicCAS(&hkeys[slot], kEmpty, y);
-                    if (old == kEmpty) { hvals[slot] = m; break; }
+                    if (old == kEmpty) { hvals[slot] = i; break; }   // the entry's index in the probe row
                     slot = (slot + 1) & smask;
                 }
             }
@@ -1118,7 +1117,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             chunk_entries(0, ps_n, ys_n);
             for (uint32_t cb = 0; cb < E; cb += kChunk) {
                 const bool last = cb + kChunk >= E;
-                uint32_t ys[kEPT], ps[kEPT], mps[kEPT];
+                uint32_t ys[kEPT], ps[kEPT], mps[kEPT];   // mps: index of the hit in the probe row
                 bool hits[kEPT];
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
@@ -1188,7 +1187,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
 #pragma unroll
                     for (int k = 0; k < kEPT; ++k) {
                         hits[k] = at[k] != kEmpty && (!kp || kp[at[k]]);
-                        mps[k] = hits[k] ? Pmask[P.probe_beg + at[k]] : 0u;
+                        mps[k] = at[k];
                     }
                 }
                 {
@@ -1227,7 +1226,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     uint32_t pos = 0, y = 0, mp = 0, mm = 0, row = 0, nv2 = 0;
                     if (mi < nmatch) {
                         pos = qpos[mi];
-                        mp = qmp[mi];
+                        // the probe edge's relation mask, the scanned entry's id
+                        // and the middle edge's mask, in one round of loads
+                        mp = Pmask[P.probe_beg + qmp[mi]];
                         y = Lcol[pos];
                         mm = Lmask[pos];
                         uint32_t lo = 0;  // row holding pos (the last with beg <= pos)
