@@ -229,15 +229,6 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Maximum over each row of 16 lanes (every lane of the row receives it).
-__device__ __forceinline__ float row16_max(float v) {
-    v = fmaxf(v, dpp_f<0xB1>(v));
-    v = fmaxf(v, dpp_f<0x4E>(v));
-    v = fmaxf(v, dpp_f<0x141>(v));
-    v = fmaxf(v, dpp_f<0x140>(v));
-    return v;
-}
-
 // Sum over an aligned group of G lanes (G a power of two, 4..64); every lane
 // of the group receives the total.  Within a row: lane^1 and lane^2 by quad
 // permutes, then the other quad of each half-row (half mirror), then the

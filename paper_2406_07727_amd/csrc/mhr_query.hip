@@ -91,11 +91,6 @@ constexpr int kRescoreLanes = 16;           // lanes that rescore one band candi
 // Tiles the workspace holds for nq queries.
 __host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
 
-__device__ inline uint32_t nth_bit(uint32_t m, uint32_t k) {
-    for (uint32_t i = 0; i < k; ++i) m &= m - 1;
-    return static_cast<uint32_t>(__ffs(m) - 1);
-}
-
 // Block reductions / scans (blockDim.x == kBlock).
 template <class T>
 __device__ inline T block_sum(T v, T *lds) {
