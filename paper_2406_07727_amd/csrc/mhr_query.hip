@@ -87,12 +87,13 @@ constexpr uint32_t kMaxTilesPerQuery = 4096;
 constexpr uint32_t kMergeSlots = 2048;      // LDS candidates per merge step
 constexpr uint32_t kSpan = 16;              // embedding elements a scoring lane holds per step
 constexpr int kRescoreLanes = 16;           // lanes that rescore one band candidate together
+constexpr int kMergeBlock = 256;            // threads of a per-query merge workgroup (>= the largest KC)
 
 // Tiles the workspace holds for nq queries.
 __host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
 
-// Block reductions / scans (blockDim.x == kBlock).
-template <class T>
+// Block reductions / scans (blockDim.x == NT, kBlock unless stated).
+template <class T, int NT = kBlock>
 __device__ inline T block_sum(T v, T *lds) {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -100,11 +101,12 @@ __device__ inline T block_sum(T v, T *lds) {
     if (lane == 0) lds[wave] = v;
     __syncthreads();
     T s = 0;
-    for (int w = 0; w < kBlock / kWave; ++w) s += lds[w];
+    for (int w = 0; w < NT / kWave; ++w) s += lds[w];
     __syncthreads();
     return s;
 }
 
+template <int NT = kBlock>
 __device__ inline float block_max(float v, float *lds) {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
@@ -112,7 +114,7 @@ __device__ inline float block_max(float v, float *lds) {
     if (lane == 0) lds[wave] = v;
     __syncthreads();
     float s = lds[0];
-    for (int w = 1; w < kBlock / kWave; ++w) s = fmaxf(s, lds[w]);
+    for (int w = 1; w < NT / kWave; ++w) s = fmaxf(s, lds[w]);
     __syncthreads();
     return s;
 }
@@ -1607,7 +1609,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         // ---- tile end: final merge and output
         __syncthreads();
         if (sh->stage_n > 0) merge_stage<KC, EXACT>(list, stage, sh, mkeys);
-        float em = block_max(eps_local, sh->redf);
+        float em = block_max<>(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
         for (uint32_t i = tid; i < static_cast<uint32_t>(KC); i += kBlock) out[i] = list[i];
@@ -1736,10 +1738,10 @@ __device__ float select_top(const GArgs &A, const QueryPlan &P, uint32_t nvalid,
     if (nvalid > static_cast<uint32_t>(KC)) {
         uint32_t pmask = 0;
         for (int shift = 24; shift >= 0; shift -= 8) {
-            for (uint32_t i = tid; i < 256; i += kBlock) ss->hist[i] = 0;
+            for (uint32_t i = tid; i < 256; i += kMergeBlock) ss->hist[i] = 0;
             __syncthreads();
             const uint32_t prefix = ss->prefix;
-            for (uint32_t i = tid; i < N; i += kBlock) {
+            for (uint32_t i = tid; i < N; i += kMergeBlock) {
                 uint32_t key;
                 if (shift == 24) {
                     key = list_key<KC>(A, P, i);
@@ -1781,7 +1783,7 @@ __device__ float select_top(const GArgs &A, const QueryPlan &P, uint32_t nvalid,
     }
     const uint32_t need_eq = ss->need;   // candidates to take at key T
     uint32_t drop = 0;
-    for (uint32_t i = tid; i < N; i += kBlock) {
+    for (uint32_t i = tid; i < N; i += kMergeBlock) {
         const uint32_t key = cached && nvalid > static_cast<uint32_t>(KC) ? cache[i] : list_key<KC>(A, P, i);
         if (key == 0) continue;
         bool take = key > T;
@@ -1813,8 +1815,9 @@ __device__ float select_top(const GArgs &A, const QueryPlan &P, uint32_t nvalid,
 }
 
 template <bool BF16, int KC>
-__global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, uint32_t *out_count,
+__global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *out, uint32_t *out_count,
                                                        uint64_t *out_total, uint32_t *out_status, uint32_t kmax) {
+    static_assert(KC <= kMergeBlock, "one thread per kept candidate");
     extern __shared__ __align__(16) unsigned char smem[];
     Cand *c = reinterpret_cast<Cand *>(smem);
     uint64_t *keys = reinterpret_cast<uint64_t *>(c + KC);
@@ -1839,15 +1842,15 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
     uint32_t n_part = 0;
     float e_part = 0.0f;
     uint64_t t_part = 0;
-    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kBlock) {
+    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kMergeBlock) {
         const TileHeader &h = A.hdr[P.tile_base + j];
         n_part += h.count;
         e_part = fmaxf(e_part, h.eps);
         t_part += h.npaths;
     }
-    const uint32_t cnt = block_sum<uint32_t>(n_part, red32);
-    const float eps = block_max(e_part, redf);
-    const uint64_t tot = block_sum<uint64_t>(t_part, red64);
+    const uint32_t cnt = block_sum<uint32_t, kMergeBlock>(n_part, red32);
+    const float eps = block_max<kMergeBlock>(e_part, redf);
+    const uint64_t tot = block_sum<uint64_t, kMergeBlock>(t_part, red64);
     const float s_drop = select_top<KC>(A, P, cnt, c, keys, cache, &ss);
     const uint32_t kept = min(cnt, static_cast<uint32_t>(KC));
     const uint32_t kk = min(P.k, cnt);
@@ -1865,7 +1868,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GArgs A, mhr_path *out, u
     const float thr = (theta - fmaxf(2.0f * eps, A.band_abs)) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
     // overflow: a candidate above the threshold was dropped, here or by a tile
     int over_part = (threadIdx.x == 0 && s_drop >= thr) ? 1 : 0;
-    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kBlock) {
+    for (uint32_t j = threadIdx.x; j < P.ntiles; j += kMergeBlock) {
         const TileHeader &h = A.hdr[P.tile_base + j];
         if (h.truncated && h.cutoff >= thr) over_part = 1;
     }
@@ -2084,7 +2087,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     auto mk = merge_kernel<BF16, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(mk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem_keys)));
-    hipLaunchKernelGGL(mk, dim3(nq), dim3(kBlock), msmem_keys, st, A, out, out_count, out_total, out_status, kmax);
+    hipLaunchKernelGGL(mk, dim3(nq), dim3(kMergeBlock), msmem_keys, st, A, out, out_count, out_total, out_status, kmax);
     auto xk = gather_kernel<BF16, true, KC>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(xk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(GL.total)));
