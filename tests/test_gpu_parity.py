@@ -186,6 +186,26 @@ def test_merge_selects_over_many_tiles():
     compare(got, run_oracle(n, R, h, r, t, X, Y, s, d, 16))
 
 
+def test_large_batch_matches_split_batches():
+    """Batches above 4,096 queries schedule from the plans in HBM, smaller
+    ones from a copy in LDS: one batch of 5,000 queries and the same queries
+    in two halves give identical results."""
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    n, R = cfg.graph.n, cfg.graph.R
+    rng = np.random.Generator(np.random.PCG64(7))
+    pick = rng.integers(0, len(s), 5000)
+    s5, d5 = s[pick].copy(), d[pick].copy()
+    say("case large batch vs split batches (5000 queries)")
+    g = gpu_graph(n, R, h, r, t, X, Y)
+    whole = run_gpu(g, s5, d5, 16)
+    a = run_gpu(g, s5[:2500].copy(), d5[:2500].copy(), 16)
+    b = run_gpu(g, s5[2500:].copy(), d5[2500:].copy(), 16)
+    for w, x, y in zip(whole, a, b):
+        assert np.array_equal(w, np.concatenate([x, y]))
+    sub = np.arange(0, 5000, 250)
+    compare(tuple(arr[sub] for arr in whole), run_oracle(n, R, h, r, t, X, Y, s5[sub], d5[sub], 16))
+
+
 def test_bad_queries_and_empty_results():
     import paper_2406_07727_amd as mhr
     cfg, (h, r, t), (X, Y), _ = workload("tiny")
