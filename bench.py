@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--no-bytes", action="store_true")
     ap.add_argument("--train-queries", type=int, default=200000, help="learned-pruner form: training queries")
     ap.add_argument("--hidden", type=int, default=512, help="learned-pruner form: hidden width")
+    ap.add_argument("--band-abs", type=float, default=0.0,
+                    help="absolute rescoring band below the K-th score (0: the rigorous band alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -316,10 +318,11 @@ def main():
         batched["per_query_launch_sample"] = nper
         gather_avg = None
     else:
-        res = g.topk(sd, dd, kk, k_max=k_max)
+        qo = mhr.QueryOpts(0, 0, 0, 0, args.band_abs) if args.band_abs > 0 else None
+        res = g.topk(sd, dd, kk, k_max=k_max, opts=qo)
         torch.cuda.synchronize()
         for _ in range(args.warmup):
-            g.topk(sd, dd, kk, k_max=k_max, out=res)
+            g.topk(sd, dd, kk, k_max=k_max, out=res, opts=qo)
         torch.cuda.synchronize()
 
         evs = [mhr.PhaseEvents(ev.create().value, ev.create().value, ev.create().value, ev.create().value)
@@ -327,7 +330,7 @@ def main():
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for i in range(args.steps):
-            g.topk(sd, dd, kk, k_max=k_max, out=res, events=evs[i])
+            g.topk(sd, dd, kk, k_max=k_max, out=res, events=evs[i], opts=qo)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         step_ms = ev.elapsed_ms(ctypes.c_void_p(evs[0].begin), ctypes.c_void_p(evs[-1].end)) / args.steps
@@ -380,7 +383,8 @@ def main():
         "config": {"workload": f"{args.config}: Chung-Lu typed KG {cfg.graph.n} vertices, {cfg.graph.R} relations, "
                                f"{cfg.graph.m} edges, d={cfg.emb.d} {cfg.emb.dtype}, {len(s)} queries, "
                                f"K={'/'.join(map(str, cfg.query.k_choices)) if per_query_k else cfg.query.k}",
-                   "queries": len(s), "k": k_max, "dim": cfg.emb.d},
+                   "queries": len(s), "k": k_max, "dim": cfg.emb.d,
+                   "band_abs": args.band_abs},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
