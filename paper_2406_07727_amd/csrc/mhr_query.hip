@@ -700,10 +700,24 @@ __device__ inline void block_sort_keys_desc(uint64_t *keys, uint32_t n2) {
 // Exhaustive pass (EXACT): the scores are final, so the list keeps the best
 // KC under the total order (score, then ids) and the whole candidates are
 // sorted.
-template <int KC, bool EXACT>
-__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint32_t *hist) {
+template <int KC, bool EXACT, bool BF16>
+__device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint32_t *hist, const GArgs &A,
+                                   uint32_t s, uint32_t t) {
     const uint32_t ns = sh->stage_n;
     if (EXACT) {
+        // staged candidates carry their fast-pass score: take the float-float
+        // score of each, one candidate per thread
+        for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x) {
+            Cand c = stage[i];
+            float e;
+            const ff sc = path_score_ff<BF16, 1>(A, s, c.a, c.b, t, (c.rel >> 16) & 0xFF, (c.rel >> 8) & 0xFF,
+                                                 c.rel & 0xFF, &e);
+            c.s = sc.hi;
+            c.s_lo = sc.lo;
+            c.eps = e;
+            stage[i] = c;
+        }
+        __syncthreads();
         const uint32_t tot = ns + KC;
         const uint32_t n2 = next_pow2(tot);
         for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
@@ -1479,7 +1493,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             const float gam = gamma_n(static_cast<int>(BF16 ? 2 * d : d) + 3) * 1.001f;
                             const float ep = gam * yp * sub_su_p[tid] + 24.0f * kUnit * axp + 1e-10f;
                             const float em = gam * ym * sub_su_m[tid] + 24.0f * kUnit * axm + 1e-10f;
-                            eps_local = fmaxf(eps_local, ep + em + ri.emax + 2.01f * kUnit * (axp + axm + ri.famax));
+                            const float perr = ep + em + ri.emax + 2.01f * kUnit * (axp + axm + ri.famax);
+                            eps_local = fmaxf(eps_local, perr);
+                            sub_su_p[tid] = perr;   // now: the bound on a path's fast-score error
                             npaths += static_cast<uint64_t>(np) * nm * __popc(ri.mask);
                             const float tS0 = EXACT ? thr_exact : sh->thr.s;
                             if (combine3(fwd, mxp, mxm, ri.fmax) >= tS0)
@@ -1497,13 +1513,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         uint32_t it = tid;
                         bool have = false;
                         uint32_t il = 0, nl = 0, lb = 0, sx = 0, sy = 0, rp_ = 0, rm_ = 0;
+                        float perr_it = 0.0f;   // fast-score error bound of the current item's paths
                         float fp = 0.0f, fm = 0.0f;
                         // threads that still hold items (bounds the emitters of a round)
                         uint32_t nact = ntot < static_cast<uint32_t>(kBlock) ? ntot : static_cast<uint32_t>(kBlock);
                         while (nact > 0) {
                             // the free stage slots are shared by the threads still
                             // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT>(list, stage, sh, mkeys);
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT, BF16>(list, stage, sh, mkeys, A, P.s, P.t);
                             uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
@@ -1538,6 +1555,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     nl = __popc(ri.mask);
                                     sx = ri.x;
                                     sy = sub_y[m];
+                                    perr_it = sub_su_p[m];
                                     il = 0;
                                     have = true;
                                 }
@@ -1564,14 +1582,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 cd.s = S;
                                 cd.s_lo = 0.0f;
                                 cd.eps = 0.0f;
-                                if (EXACT) {
-                                    float e2;
-                                    ff sc = path_score_ff<BF16, 1>(A, P.s, cd.a, cd.b, P.t, r1, rm_, r3, &e2);
-                                    cd.s = sc.hi;
-                                    cd.s_lo = sc.lo;
-                                    cd.eps = e2;
-                                }
-                                if (cand_better(cd, thr)) {
+                                // exhaustive pass: the path is staged with its fast score
+                                // unless even its error bound cannot reach the kept
+                                // list's threshold (its float-float score is taken when
+                                // the stage is merged); fast pass: the total order
+                                const bool keep = EXACT ? (thr.a == 0xFFFFFFFFu ||
+                                                           S + perr_it >= thr.s - 1e-6f * fabsf(thr.s))
+                                                        : cand_better(cd, thr);
+                                if (keep) {
                                     uint32_t slot = atomicAdd(&sh->stage_n, 1u);
                                     stage[slot] = cd;
                                     ++emitted;
@@ -1608,7 +1626,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         // ---- tile end: final merge and output
         __syncthreads();
-        if (sh->stage_n > 0) merge_stage<KC, EXACT>(list, stage, sh, mkeys);
+        if (sh->stage_n > 0) merge_stage<KC, EXACT, BF16>(list, stage, sh, mkeys, A, P.s, P.t);
         float em = block_max<>(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
