@@ -424,13 +424,20 @@ template <bool BF16>
 __device__ inline ff edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
     ff acc = {0.0f, 0.0f};
     float as = 0.0f;
-    const size_t d = A.d;
-    for (uint32_t i = 0; i < A.d; ++i) {
-        float at;
-        const ff t = distmult_term_ff(load1<BF16>(A.X, u * d + i), load1<BF16>(A.Y, r * d + i),
-                                      load1<BF16>(A.X, v * d + i), &at);
-        acc = ff_add(acc, t);
-        as += at;
+    // eight elements per 16-byte load (d is a power of two >= 8), summed in
+    // ascending order as one at a time
+    for (uint32_t i0 = 0; i0 < A.d; i0 += 8) {
+        float xu[8], yr[8], xv[8];
+        load8<BF16>(A.X, u, A.d, i0, xu);
+        load8<BF16>(A.Y, r, A.d, i0, yr);
+        load8<BF16>(A.X, v, A.d, i0, xv);
+#pragma unroll
+        for (int l = 0; l < 8; ++l) {
+            float at;
+            const ff t = distmult_term_ff(xu[l], yr[l], xv[l], &at);
+            acc = ff_add(acc, t);
+            as += at;
+        }
     }
     *abs_sum = as;
     return acc;
