@@ -960,8 +960,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     for (;;) {
                         const uint32_t u = atomicAdd(&A.ctrl->exact_ctr, 1u);
                         if (u >= A.ctrl->total_tiles) break;
-                        const uint32_t q = A.tile_q[u];
-                        if (A.plans[q].flags & kNeedExact) { t = u; sh->q = q; sh->j = u - A.plans[q].tile_base; break; }
+                        const uint32_t tt = A.tile_order[u];   // longest expected first, as in the fast pass
+                        const uint32_t q = A.tile_q[tt];
+                        if (A.plans[q].flags & kNeedExact) { t = tt; sh->q = q; sh->j = tt - A.plans[q].tile_base; break; }
                     }
                 }
             } else {
@@ -1532,6 +1533,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
                             const float tS = EXACT ? thr_exact : thr.s;
+                            // exhaustive pass: a path whose fast score plus its error
+                            // bound stays below the kept list's threshold cannot enter
+                            // the list either
+                            const float tL = (EXACT && thr.a != 0xFFFFFFFFu) ? thr.s - 1e-6f * fabsf(thr.s)
+                                                                           : -__builtin_huge_valf();
                             uint32_t emitted = 0;
                             bool dropped = false;
                             while (emitted < quota) {
@@ -1551,7 +1557,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     fp = slab[vo + ip];
                                     fm = slab[vo + np + im];
                                     const RowInfo &ri = rows[sub_row[m]];
-                                    if (combine3(fwd, fp, fm, ri.fmax) < tS) {
+                                    perr_it = sub_su_p[m];
+                                    if (combine3(fwd, fp, fm, ri.fmax) < fmaxf(tS, tL - perr_it)) {
                                         dropped = true;   // every path of this pair of values
                                         it += kBlock;
                                         continue;
@@ -1562,7 +1569,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     nl = __popc(ri.mask);
                                     sx = ri.x;
                                     sy = sub_y[m];
-                                    perr_it = sub_su_p[m];
                                     il = 0;
                                     have = true;
                                 }
@@ -1573,7 +1579,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 }
                                 const float fl = rowval[lb + il];
                                 const float S = combine3(fwd, fp, fm, fl);
-                                if (S < tS) {
+                                if (S < fmaxf(tS, tL - perr_it)) {
                                     dropped = true;   // this and every later list value
                                     have = false;
                                     it += kBlock;
@@ -1593,9 +1599,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 // unless even its error bound cannot reach the kept
                                 // list's threshold (its float-float score is taken when
                                 // the stage is merged); fast pass: the total order
-                                const bool keep = EXACT ? (thr.a == 0xFFFFFFFFu ||
-                                                           S + perr_it >= thr.s - 1e-6f * fabsf(thr.s))
-                                                        : cand_better(cd, thr);
+                                const bool keep = EXACT || cand_better(cd, thr);
                                 if (keep) {
                                     uint32_t slot = atomicAdd(&sh->stage_n, 1u);
                                     stage[slot] = cd;
