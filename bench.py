@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # fetched (scale 2.0), WRITE_SIZE read 1048576 KiB (scale 1.0).  Valid only
 # for the kernel sources they were taken on (sha256 over the query sources).
 TRAFFIC = {
-    "sources_sha256": "4e60ba9823ed9b4addce3452b584963df59689ab6295dcb136e978356cff7f82",
-    "fetch_kib": 476268.4,
+    "sources_sha256": "2a6fcb3dcc7d737914b4fcd456ec76e69a5d5e2d0979dc03792baeef7749c810",
+    "fetch_kib": 470421.0,
     "write_kib": 3019.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
