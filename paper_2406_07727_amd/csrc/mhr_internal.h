@@ -85,7 +85,7 @@ struct QueryPlan {
     uint32_t tile_base;
     uint32_t flags;         // kNeedExact
     float thr;              // exact pass: centred-score threshold
-    float eps;              // fast pass: largest error bound over scored paths
+    float kth_low;          // exhaustive pass: a lower bound on the query's true K-th score
     uint64_t cost;          // scan entries
     uint64_t total;         // |P(s,t)|
     uint32_t pad[2];

@@ -1505,7 +1505,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             eps_local = fmaxf(eps_local, perr);
                             sub_su_p[tid] = perr;   // now: the bound on a path's fast-score error
                             npaths += static_cast<uint64_t>(np) * nm * __popc(ri.mask);
-                            const float tS0 = EXACT ? thr_exact : sh->thr.s;
+                            // exhaustive pass: no path of this match can be returned
+                            // unless its fast score plus the bound reaches the K-th
+                            // score's lower bound
+                            const float tS0 = EXACT ? fmaxf(thr_exact, P.kth_low - perr) : sh->thr.s;
                             if (combine3(fwd, mxp, mxm, ri.fmax) >= tS0)
                                 nitems = np * nm;
                             else
@@ -1536,8 +1539,12 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             // exhaustive pass: a path whose fast score plus its error
                             // bound stays below the kept list's threshold cannot enter
                             // the list either
-                            const float tL = (EXACT && thr.a != 0xFFFFFFFFu) ? thr.s - 1e-6f * fabsf(thr.s)
-                                                                           : -__builtin_huge_valf();
+                            // (and none below the lower bound on the query's true K-th
+                            // score can be returned)
+                            const float tL = !EXACT ? -__builtin_huge_valf()
+                                                    : fmaxf(P.kth_low, thr.a != 0xFFFFFFFFu
+                                                                            ? thr.s - 1e-6f * fabsf(thr.s)
+                                                                            : -__builtin_huge_valf());
                             uint32_t emitted = 0;
                             bool dropped = false;
                             while (emitted < quota) {
@@ -1907,6 +1914,9 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *o
         if (threadIdx.x == 0) {
             A.plans[q].flags = kNeedExact;
             A.plans[q].thr = thr;
+            // K candidates have fast scores >= theta and errors <= eps, so the
+            // true K-th score is at least theta - eps (rounded down generously)
+            A.plans[q].kth_low = (theta - eps) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
             A.plans[q].total = tot;
             atomicAdd(&A.ctrl->exact_n, 1u);
         }
