@@ -21,8 +21,10 @@
 //             K-th, rescores them in float-float and writes the ranked
 //             result.  If a truncated tile could still hold a band member
 //             the query is marked for the exhaustive pass.
-//   exact     gather again for marked queries, scoring every path above the
-//             band threshold in float-float, then a merge of those lists.
+//   exact     gather again for marked queries, scoring in float-float every
+//             path above the band threshold that can still be returned (its
+//             fast score plus error bound reaches both the kept list and a
+//             lower bound on the K-th score), then a merge of those lists.
 //
 // The paper's CPU design (thread-private K-heaps merged by a tree
 // reduction, section 3.3; level-synchronous frontier expansion, section 5)
