@@ -142,19 +142,56 @@ def gather_bytes(csr_out, csr_in, src, dst, d, elem):
     return total, matches
 
 
-def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample, gpu_result=None, per_core_queries=32):
+    """The FP64 oracle timed on the host cores (OpenMP over queries, threads
+    pinned close to cores), on the first nsample queries; then a
+    single-thread run on the first per_core_queries for a per-core rate.
+    When gpu_result is given, the GPU's results on the sampled queries are
+    compared with the oracle's, path by path."""
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    os.environ.setdefault("OMP_PLACES", "cores")
     import oracle
+    from tests.parity import parity_summary, run_oracle
     oracle.build(force=False)
     og = oracle.Graph(cfg.graph.n, cfg.graph.R, h, r, t)
-    Xf = oracle.as_f32_table(X, cfg.emb.dtype)
-    Yf = oracle.as_f32_table(Y, cfg.emb.dtype)
     threads = oracle.max_threads()
     t0 = time.perf_counter()
-    _, _, tot = og.topk(Xf, Yf, s[:nsample], d[:nsample], k[:nsample])
+    orc = run_oracle(cfg.graph.n, cfg.graph.R, h, r, t, X, Y, s[:nsample], d[:nsample], k[:nsample],
+                     cfg.emb.dtype, og=og)
     dt = time.perf_counter() - t0
-    return {"value": float(tot.sum()) / dt, "unit": "paths/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {nsample} of the {len(s)} queries (K={int(k[0])}); FP64 brute-force enumeration, "
-                      f"OpenMP over queries; {dt:.1f} s; {int(tot.sum())} paths; queries/s {nsample / dt:.2f}"}
+    npaths = int(orc.total.sum())
+    parity = None
+    if gpu_result is not None:
+        parity = parity_summary(gpu_result, orc, range(nsample))
+        if parity["first_mismatch"] is None:
+            del parity["first_mismatch"]
+    n1 = min(per_core_queries, nsample)
+    Xf = oracle.as_f32_table(X, cfg.emb.dtype)
+    Yf = oracle.as_f32_table(Y, cfg.emb.dtype)
+    t1 = time.perf_counter()
+    _, _, tot1 = og.topk(Xf, Yf, s[:n1], d[:n1], k[:n1], nthreads=1)
+    dt1 = time.perf_counter() - t1
+    out = {"value": npaths / dt, "unit": "paths/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"first {nsample} of the {len(s)} queries (K={int(k[0])}); FP64 brute-force enumeration, "
+                     f"OpenMP over queries (OMP_PROC_BIND={os.environ['OMP_PROC_BIND']}, "
+                     f"OMP_PLACES={os.environ['OMP_PLACES']}); {dt:.1f} s; {npaths} paths; "
+                     f"queries/s {nsample / dt:.2f}",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "queries_per_s": nsample / dt,
+           "per_core": {"paths_per_s": float(tot1.sum()) / dt1, "queries_per_s": n1 / dt1, "queries": n1,
+                        "seconds": round(dt1, 2)}}
+    return out, parity
 
 
 def calibrate_copy(nbytes=1 << 30, reps=3):
@@ -221,7 +258,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="realistic")
-    ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="queries the oracle baseline runs (default: 1024 realistic, 256 precision, 512 batched)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bytes", action="store_true")
     ap.add_argument("--train-queries", type=int, default=200000, help="learned-pruner form: training queries")
@@ -359,10 +397,13 @@ def main():
         log(f"gather algorithmic bytes {nbytes / 1e6:.1f} MB ({matches} matched middle pairs) "
             f"in {time.perf_counter() - t1:.1f} s")
 
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, h, r, t, X, Y, s, d, k, min(args.cpu_sample, len(s)))
+        nsample = args.cpu_sample or {"realistic": 1024, "precision": 256, "batched": 512}.get(args.config, 256)
+        cpu, parity = cpu_baseline(cfg, h, r, t, X, Y, s, d, k, min(nsample, len(s)),
+                                   gpu_result=(p, cnt, tot, st))
         log(f"cpu baseline: {cpu}")
+        log(f"parity against the oracle: {parity}")
 
     value = paths / (step_ms * 1e-3)
     out = {
@@ -387,6 +428,7 @@ def main():
                    "band_abs": args.band_abs},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "parity": parity,
     }
     if batched:
         out["batched"] = batched
