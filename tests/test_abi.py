@@ -55,11 +55,27 @@ def test_host_side_validation(lib):
 
 
 def test_binding_record_layout():
+    """The binding's record dtype has the field offsets a C compiler gives
+    struct mhr_path (laid out here by ctypes from the header's member list)."""
     import numpy as np
     text = open(HEADER).read()
-    assert "uint16_t r1, r2, r3, flags;" in text
-    # a, b (2x4) + 4x2 + score + err_bound
-    assert 2 * 4 + 4 * 2 + 4 + 4 == 24
+    body = re.search(r"typedef struct mhr_path \{(.*?)\} mhr_path;", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    ctype = {"uint32_t": ctypes.c_uint32, "uint16_t": ctypes.c_uint16, "float": ctypes.c_float}
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, names = decl.split(None, 1)
+        fields += [(nm.strip(), ctype[typ]) for nm in names.split(",")]
+
+    class CPath(ctypes.Structure):
+        _fields_ = fields
     import paper_2406_07727_amd as mhr
-    assert mhr.PATH_DTYPE.itemsize == 24
-    assert np.dtype(mhr.PATH_DTYPE)["score"] == np.float32
+    dt = np.dtype(mhr.PATH_DTYPE)
+    assert ctypes.sizeof(CPath) == dt.itemsize == 24
+    assert [f for f, _ in fields] == list(dt.names)
+    for name, _ in fields:
+        assert getattr(CPath, name).offset == dt.fields[name][1], name
+    assert dt["score"] == np.float32 and dt["err_bound"] == np.float32
