@@ -13,8 +13,12 @@ Two independent implementations of the same plain definition:
   for tiny graphs only.
 
 The definition (what both compute):
-  edge weight  w(u,r,v) = logsigmoid( sum_i (X[u,i]*Y[r,i])*X[v,i] )  in FP64,
+  edge weight  scorer "distmult" (the default):
+               w(u,r,v) = logsigmoid( sum_i (X[u,i]*Y[r,i])*X[v,i] )  in FP64,
                logsigmoid(x) = min(x,0) - log1p(exp(-|x|));
+               scorer "transe_l1" (the paper's own score, section 3.3):
+               w(u,r,v) = gamma - sum_i |(X[u,i] + Y[r,i]) - X[v,i]|  in FP64,
+               gamma = 1.0 by default as in the paper;
   path score   S = w(s,r1,a) + w(a,r2,b) + w(b,r3,t), the exact sum rounded
                once to FP64, over walks of exactly three edges (the
                three-hop query of section 3.1);
@@ -72,6 +76,10 @@ def _load():
         lib.og_logsigmoid.restype = ctypes.c_double
         lib.og_logsigmoid.argtypes = [ctypes.c_double]
         lib.og_edge_weights.argtypes = [u32, vp, vp, u64, vp, vp, vp, vp, vp]
+        lib.og_edge_weights_s.argtypes = [ctypes.c_int, ctypes.c_double, u32, vp, vp, u64, vp, vp, vp, vp, vp]
+        lib.og_topk_s.restype = ctypes.c_int
+        lib.og_topk_s.argtypes = [vp, ctypes.c_int, ctypes.c_double, u32, vp, vp, u32, vp, vp, vp, u32,
+                                  ctypes.c_int, vp, vp, vp]
         lib.og_topk.restype = ctypes.c_int
         lib.og_topk.argtypes = [vp, u32, vp, vp, u32, vp, vp, vp, u32, ctypes.c_int,
                                 vp, vp, vp]
@@ -80,6 +88,15 @@ def _load():
         lib.og_fsum.argtypes = [vp, ctypes.c_int]
         _lib = lib
     return _lib
+
+
+SCORERS = {"distmult": 0, "transe_l1": 1}
+
+
+def _scorer(name):
+    if name not in SCORERS:
+        raise ValueError(f"unknown scorer {name!r}")
+    return SCORERS[name]
 
 
 def _ptr(a: np.ndarray):
@@ -133,7 +150,9 @@ class Graph:
         _load().og_graph_export(self._g, _ptr(rp), _ptr(t), _ptr(r))
         return rp, t, r
 
-    def edge_weights(self, X, Y, u, r, v):
+    def edge_weights(self, X, Y, u, r, v, scorer: str = "distmult", gamma: float = 1.0):
+        """(x, w) of arbitrary edges: the scorer's raw value (DistMult score
+        or L1 distance) and the edge weight, in FP64."""
         X = np.ascontiguousarray(X, np.float32)
         Y = np.ascontiguousarray(Y, np.float32)
         u = np.ascontiguousarray(u, np.uint32)
@@ -141,11 +160,11 @@ class Graph:
         v = np.ascontiguousarray(v, np.uint32)
         x = np.empty(len(u), np.float64)
         w = np.empty(len(u), np.float64)
-        _load().og_edge_weights(X.shape[1], _ptr(X), _ptr(Y), len(u), _ptr(u), _ptr(r),
-                                _ptr(v), _ptr(x), _ptr(w))
+        _load().og_edge_weights_s(_scorer(scorer), float(gamma), X.shape[1], _ptr(X), _ptr(Y), len(u),
+                                  _ptr(u), _ptr(r), _ptr(v), _ptr(x), _ptr(w))
         return x, w
 
-    def topk(self, X, Y, src, dst, k, nthreads: int = 0):
+    def topk(self, X, Y, src, dst, k, nthreads: int = 0, scorer: str = "distmult", gamma: float = 1.0):
         """Top-K paths for each query.  X, Y: float32 tables (use
         ``as_f32_table`` for bfloat16 storage).  k: scalar or per-query array.
         Returns (paths[nq][kmax] structured array, count[nq], total[nq])."""
@@ -163,8 +182,9 @@ class Graph:
         out = np.zeros((nq, kmax), PATH_DTYPE)
         cnt = np.zeros(nq, np.uint32)
         tot = np.zeros(nq, np.uint64)
-        rc = _load().og_topk(self._g, X.shape[1], _ptr(X), _ptr(Y), nq, _ptr(src), _ptr(dst),
-                             _ptr(kk), kmax, int(nthreads), _ptr(out), _ptr(cnt), _ptr(tot))
+        rc = _load().og_topk_s(self._g, _scorer(scorer), float(gamma), X.shape[1], _ptr(X), _ptr(Y), nq,
+                               _ptr(src), _ptr(dst), _ptr(kk), kmax, int(nthreads), _ptr(out), _ptr(cnt),
+                               _ptr(tot))
         if rc != 0:
             raise ValueError("oracle query failed (bad id, k out of range, or out of memory)")
         return out, cnt, tot

@@ -8,11 +8,17 @@
  *  - Canonical graph: the input triples (h, r, t) of the problem statement
  *    (section 3.1, the three inputs) sorted and with identical triples
  *    removed.  Edges are directed h -> t.
- *  - Edge weight: the DistMult score x(u,r,v) = sum_i (X[u,i]*Y[r,i])*X[v,i],
- *    summed in ascending i, passed through the log-sigmoid
- *    w = min(x,0) - log1p(exp(-|x|)).  (The paper only says edge weights come
- *    from learned vertex and relation embeddings, section 1; the DistMult +
- *    log-sigmoid scorer is the reading this project takes.)
+ *  - Edge weight, one of two scorers:
+ *    DistMult: the score x(u,r,v) = sum_i (X[u,i]*Y[r,i])*X[v,i], summed in
+ *      ascending i, passed through the log-sigmoid
+ *      w = min(x,0) - log1p(exp(-|x|)).  (The paper only says edge weights
+ *      come from learned vertex and relation embeddings, section 1; this is
+ *      the reading the project takes for its main workloads.)
+ *    TransE-L1: the paper's own score (section 3.3, the person and
+ *      affiliation scoring algorithms): the L1 distance
+ *      x(u,r,v) = sum_i |(X[u,i] + Y[r,i]) - X[v,i]| of the head plus the
+ *      relation from the tail, summed in ascending i, subtracted from the
+ *      constant gamma (1.0 in the paper): w = gamma - x.
  *  - Paths: every walk s -r1-> a -r2-> b -r3-> t of exactly three edges
  *    (the three-hop query of section 3.1); a and b may repeat s, t or each
  *    other.  Score S = w1 + w2 + w3, the exact sum rounded once to FP64
@@ -120,6 +126,22 @@ double og_logsigmoid(double x)
     return fmin(x, 0.0) - log1p(exp(-fabs(x)));
 }
 
+/* Scorer selection: 0 = DistMult + log-sigmoid, 1 = TransE-L1 with gamma. */
+enum { OG_DISTMULT = 0, OG_TRANSE_L1 = 1 };
+typedef struct { int kind; double gamma; } og_scorer;
+
+/* TransE-L1 distance of (u, r, v): sum over i ascending of
+ * |(X[u,i] + Y[r,i]) - X[v,i]|, every operation in FP64. */
+static double og_l1(uint32_t d, const float *X, const float *Y,
+                    uint32_t u, uint32_t r, uint32_t v)
+{
+    const float *xu = X + (size_t)u * d, *yr = Y + (size_t)r * d, *xv = X + (size_t)v * d;
+    double acc = 0.0;
+    for (uint32_t i = 0; i < d; ++i)
+        acc += fabs(((double)xu[i] + (double)yr[i]) - (double)xv[i]);
+    return acc;
+}
+
 /* DistMult score of (u, r, v): sum over i ascending of (X[u,i]*Y[r,i])*X[v,i]. */
 static double og_x(uint32_t d, const float *X, const float *Y,
                    uint32_t u, uint32_t r, uint32_t v)
@@ -131,21 +153,43 @@ static double og_x(uint32_t d, const float *X, const float *Y,
     return acc;
 }
 
-double og_edge_weight(uint32_t d, const float *X, const float *Y,
-                      uint32_t u, uint32_t r, uint32_t v)
+/* The scorer's raw value x (DistMult score or L1 distance) of (u, r, v). */
+static double og_raw(og_scorer sc, uint32_t d, const float *X, const float *Y,
+                     uint32_t u, uint32_t r, uint32_t v)
 {
-    return og_logsigmoid(og_x(d, X, Y, u, r, v));
+    return sc.kind == OG_TRANSE_L1 ? og_l1(d, X, Y, u, r, v) : og_x(d, X, Y, u, r, v);
+}
+
+/* The edge weight from the raw value. */
+static double og_weight(og_scorer sc, double x)
+{
+    return sc.kind == OG_TRANSE_L1 ? sc.gamma - x : og_logsigmoid(x);
+}
+
+static double og_edge_weight(og_scorer sc, uint32_t d, const float *X, const float *Y,
+                             uint32_t u, uint32_t r, uint32_t v)
+{
+    return og_weight(sc, og_raw(sc, d, X, Y, u, r, v));
+}
+
+/* Raw values and weights of ne arbitrary edges (u[i], r[i], v[i]). */
+void og_edge_weights_s(int scorer, double gamma, uint32_t d, const float *X, const float *Y,
+                       uint64_t ne, const uint32_t *u, const uint32_t *r, const uint32_t *v,
+                       double *out_x, double *out_w)
+{
+    og_scorer sc = {scorer, gamma};
+    for (uint64_t i = 0; i < ne; ++i) {
+        double x = og_raw(sc, d, X, Y, u[i], r[i], v[i]);
+        if (out_x) out_x[i] = x;
+        out_w[i] = og_weight(sc, x);
+    }
 }
 
 void og_edge_weights(uint32_t d, const float *X, const float *Y, uint64_t ne,
                      const uint32_t *u, const uint32_t *r, const uint32_t *v,
                      double *out_x, double *out_w)
 {
-    for (uint64_t i = 0; i < ne; ++i) {
-        double x = og_x(d, X, Y, u[i], r[i], v[i]);
-        if (out_x) out_x[i] = x;
-        out_w[i] = og_logsigmoid(x);
-    }
+    og_edge_weights_s(OG_DISTMULT, 0.0, d, X, Y, ne, u, r, v, out_x, out_w);
 }
 
 /* ------------------------------------------------------------------ */
@@ -246,22 +290,22 @@ static void vec_push(og_vec *v, og_path x)
 
 /* One query: all paths s -> a -> b -> t, sorted; keeps the first K.
  * Returns the number of paths |P(s,t)|, or UINT64_MAX on allocation failure. */
-static uint64_t og_query(const og_graph *g, uint32_t d, const float *X, const float *Y,
+static uint64_t og_query(const og_graph *g, og_scorer sc, uint32_t d, const float *X, const float *Y,
                          uint32_t s, uint32_t t, uint32_t K, og_path *out, uint32_t *count)
 {
     og_vec v = {0};
     for (uint64_t e1 = g->rowptr[s]; e1 < g->rowptr[s + 1]; ++e1) {
         uint32_t a = g->tail[e1], r1 = g->rel[e1];
-        double w1 = og_edge_weight(d, X, Y, s, r1, a);
+        double w1 = og_edge_weight(sc, d, X, Y, s, r1, a);
         for (uint64_t e2 = g->rowptr[a]; e2 < g->rowptr[a + 1]; ++e2) {
             uint32_t b = g->tail[e2], r2 = g->rel[e2];
             uint64_t lo = lower_tail(g->tail, g->rowptr[b], g->rowptr[b + 1], t);
             uint64_t e3 = lo;
             if (e3 >= g->rowptr[b + 1] || g->tail[e3] != t) continue;
-            double w2 = og_edge_weight(d, X, Y, a, r2, b);
+            double w2 = og_edge_weight(sc, d, X, Y, a, r2, b);
             for (; e3 < g->rowptr[b + 1] && g->tail[e3] == t; ++e3) {
                 uint32_t r3 = g->rel[e3];
-                double w3 = og_edge_weight(d, X, Y, b, r3, t);
+                double w3 = og_edge_weight(sc, d, X, Y, b, r3, t);
                 og_path p;
                 p.s = og_path_score(w1, w2, w3);
                 p.a = a; p.b = b; p.r1 = r1; p.r2 = r2; p.r3 = r3;
@@ -282,11 +326,13 @@ static uint64_t og_query(const og_graph *g, uint32_t d, const float *X, const fl
 /* Batch of queries; OpenMP over queries (dynamic schedule).  out has
  * nq * kmax records; k[q] <= kmax.  Returns 0, or -1 on a bad argument or
  * allocation failure. */
-int og_topk(const og_graph *g, uint32_t d, const float *X, const float *Y,
-            uint32_t nq, const uint32_t *src, const uint32_t *dst,
-            const uint32_t *k, uint32_t kmax, int nthreads,
-            og_path *out, uint32_t *out_count, uint64_t *out_total)
+int og_topk_s(const og_graph *g, int scorer, double gamma, uint32_t d, const float *X,
+              const float *Y, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+              const uint32_t *k, uint32_t kmax, int nthreads,
+              og_path *out, uint32_t *out_count, uint64_t *out_total)
 {
+    og_scorer sc = {scorer, gamma};
+    if (scorer != OG_DISTMULT && scorer != OG_TRANSE_L1) return -1;
     for (uint32_t q = 0; q < nq; ++q)
         if (src[q] >= g->n || dst[q] >= g->n || k[q] == 0 || k[q] > kmax) return -1;
     int fail = 0;
@@ -295,12 +341,21 @@ int og_topk(const og_graph *g, uint32_t d, const float *X, const float *Y,
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int64_t q = 0; q < (int64_t)nq; ++q) {
-        uint64_t tot = og_query(g, d, X, Y, src[q], dst[q], k[q],
+        uint64_t tot = og_query(g, sc, d, X, Y, src[q], dst[q], k[q],
                                 out + (size_t)q * kmax, &out_count[q]);
         if (tot == UINT64_MAX) fail = 1;
         out_total[q] = tot;
     }
     return fail ? -1 : 0;
+}
+
+int og_topk(const og_graph *g, uint32_t d, const float *X, const float *Y,
+            uint32_t nq, const uint32_t *src, const uint32_t *dst,
+            const uint32_t *k, uint32_t kmax, int nthreads,
+            og_path *out, uint32_t *out_count, uint64_t *out_total)
+{
+    return og_topk_s(g, OG_DISTMULT, 0.0, d, X, Y, nq, src, dst, k, kmax, nthreads,
+                     out, out_count, out_total);
 }
 
 int og_max_threads(void)

@@ -5,8 +5,10 @@ adjacency over the distinct triples, a literal triple loop over the edges
 s->a, a->b and b->t, math.log1p / math.exp for the log-sigmoid, and one full
 sort by the key tuple (-S, a, b, r1, r2, r3).  S is the correctly rounded
 sum of the three weights (math.fsum), so it depends only on their multiset.  See ``oracle/__init__.py``
-for the definition; edge weights follow the DistMult + log-sigmoid reading,
-path scores the sum of the three weights of a three-hop walk (section 3.1).
+for the definition; edge weights follow the DistMult + log-sigmoid reading
+or the paper's TransE-L1 score (gamma minus the L1 distance between head
+plus relation and tail, section 3.3), path scores the sum of the three
+weights of a three-hop walk (section 3.1).
 """
 
 from __future__ import annotations
@@ -19,14 +21,20 @@ def logsigmoid(x: float) -> float:
     return min(x, 0.0) - math.log1p(math.exp(-abs(x)))
 
 
-def edge_weight(X, Y, u, r, v) -> float:
+def edge_weight(X, Y, u, r, v, scorer="distmult", gamma=1.0) -> float:
     acc = 0.0
+    if scorer == "transe_l1":
+        for i in range(len(X[u])):
+            acc += abs((float(X[u][i]) + float(Y[r][i])) - float(X[v][i]))
+        return gamma - acc
+    if scorer != "distmult":
+        raise ValueError(scorer)
     for i in range(len(X[u])):
         acc += (float(X[u][i]) * float(Y[r][i])) * float(X[v][i])
     return logsigmoid(acc)
 
 
-def topk_paths(edges, X, Y, s, t, K, keep_first=None, keep_last=None):
+def topk_paths(edges, X, Y, s, t, K, keep_first=None, keep_last=None, scorer="distmult", gamma=1.0):
     """edges: iterable of (h, r, t) triples (duplicates allowed; they are
     merged).  X, Y: nested sequences of floats.  Returns (paths, total) with
     paths a list of (S, a, b, r1, r2, r3), best first.
@@ -42,15 +50,15 @@ def topk_paths(edges, X, Y, s, t, K, keep_first=None, keep_last=None):
     for (r1, a) in out[s]:
         if keep_first is not None and a not in keep_first:
             continue
-        w1 = edge_weight(X, Y, s, r1, a)
+        w1 = edge_weight(X, Y, s, r1, a, scorer, gamma)
         for (r2, b) in out[a]:
-            w2 = edge_weight(X, Y, a, r2, b)
+            w2 = edge_weight(X, Y, a, r2, b, scorer, gamma)
             if keep_last is not None and b not in keep_last:
                 continue
             for (r3, tt) in out[b]:
                 if tt != t:
                     continue
-                w3 = edge_weight(X, Y, b, r3, t)
+                w3 = edge_weight(X, Y, b, r3, t, scorer, gamma)
                 paths.append((math.fsum((w1, w2, w3)), a, b, r1, r2, r3))
     paths.sort(key=lambda p: (-p[0], p[1], p[2], p[3], p[4], p[5]))
     return paths[:K], len(paths)
