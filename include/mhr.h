@@ -181,6 +181,26 @@ mhr_status mhr_topk_paths(const mhr_graph *g, const mhr_query_opts *opts, uint32
                           uint64_t *out_total, uint32_t *out_status,
                           void *workspace, size_t ws_bytes, void *stream);
 
+/* Allocation-free form of mhr_topk_paths, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments and results as mhr_topk_paths
+ * without the workspace: the workspace is a fixed array of
+ * MHR_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends.  The call allocates nothing (no hipMalloc / hipFree).
+ *  - Limit: the batch's workspace, mhr_workspace_size(g, opts, nq, k_max),
+ *    must not exceed MHR_NOALLOC_SCRATCH_BYTES (e.g. up to 4,096 queries at
+ *    k_max <= 96); larger batches return MHR_ERR_WORKSPACE_TOO_SMALL before
+ *    anything is enqueued.
+ *  - Every call on one GPU shares that GPU's array: calls that overlap in
+ *    time on one GPU (other streams, other threads) race and must not be
+ *    issued.  Calls on one stream are ordered and safe.
+ *  - The current device must be the graph's device. */
+#define MHR_NOALLOC_SCRATCH_BYTES (64u << 20)
+mhr_status mhr_topk_paths_noalloc(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
+                                  const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                  uint32_t k_max, mhr_path *out, uint32_t *out_count,
+                                  uint64_t *out_total, uint32_t *out_status, void *stream);
+
 /* Events recorded on `stream` around the phases of one mhr_topk_paths call,
  * for timing the kernels on the stream they run on.  Each member is a
  * hipEvent_t created by the caller, or NULL to skip it. */

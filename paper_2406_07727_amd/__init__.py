@@ -33,6 +33,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MHR_OK = 0
 MHR_MAX_K = 224
+NOALLOC_SCRATCH_BYTES = 64 << 20
 Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS, Q_OVERFLOW = 1, 2, 4, 8
 PATH_RESCORED, PATH_PRECISION_TIE = 1, 2
 DTYPE_F32, DTYPE_BF16 = 0, 1
@@ -89,6 +90,9 @@ _lib.mhr_topk_paths.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, 
 _lib.mhr_topk_paths_profiled.restype = _i
 _lib.mhr_topk_paths_profiled.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp,
                                          _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(PhaseEvents)]
+_lib.mhr_topk_paths_noalloc.restype = _i
+_lib.mhr_topk_paths_noalloc.argtypes = [_vp, ctypes.POINTER(QueryOpts), _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp,
+                                        _vp, _vp]
 _lib.mhr_edge_weights.restype = _i
 _lib.mhr_edge_weights.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_plan_create.restype = _i
@@ -328,6 +332,20 @@ class Graph:
                                                 _ptr(out.paths), _ptr(out.count), _ptr(out.total),
                                                 _ptr(out.status), _ptr(ws), ws.numel(), _stream_ptr(stream),
                                                 ctypes.byref(events)), "mhr_topk_paths_profiled")
+        out._keep = (s, d, kt)
+        return out
+
+    def topk_noalloc(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
+                     out: Optional[TopK] = None, stream=None) -> TopK:
+        """topk through mhr_topk_paths_noalloc: the library's fixed scratch
+        array serves as the workspace (nothing is allocated by the call; the
+        batch's workspace must fit NOALLOC_SCRATCH_BYTES)."""
+        s, d, kt, nq, o, k_max = self._queries(src, dst, k, k_max, opts)
+        if out is None:
+            out = self._new_out(nq, k_max)
+        _check(_lib.mhr_topk_paths_noalloc(self._h, ctypes.byref(o), nq, _ptr(s), _ptr(d), _ptr(kt), k_max,
+                                           _ptr(out.paths), _ptr(out.count), _ptr(out.total), _ptr(out.status),
+                                           _stream_ptr(stream)), "mhr_topk_paths_noalloc")
         out._keep = (s, d, kt)
         return out
 

@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "mhr_device.h"
 #include "mhr_internal.h"
@@ -2257,4 +2258,69 @@ extern "C" mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const ui
         hipLaunchKernelGGL(edge_weight_kernel<false>, dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
     MHR_HIP_TRY(hipGetLastError());
     return MHR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free query entry point.  The workspace is a fixed device array
+// of this library (one copy per GPU, held until the process ends) instead of
+// a caller buffer.  Host code never passes the array's name to a kernel: its
+// device address is looked up once per device with hipGetSymbolAddress and
+// that address is used as the workspace.
+// ---------------------------------------------------------------------------
+namespace mhr {
+namespace {
+
+__device__ __align__(256) unsigned char scratch[MHR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on the current device (resolved on the
+// first call on each device), or nullptr with the error set.
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("mhr_topk_paths_noalloc: device index out of range");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace mhr
+
+extern "C" mhr_status mhr_topk_paths_noalloc(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq,
+                                             const uint32_t *src, const uint32_t *dst, const uint32_t *k,
+                                             uint32_t kmax, mhr_path *out, uint32_t *out_count,
+                                             uint64_t *out_total, uint32_t *out_status, void *stream) {
+    MHR_ARG_CHECK(g != nullptr, "mhr_topk_paths_noalloc: null graph");
+    if (!g->X) {
+        set_error("embeddings not set");
+        return MHR_ERR_NO_EMBEDDINGS;
+    }
+    MHR_ARG_CHECK(kmax >= 1 && kmax <= MHR_MAX_K, "k_max must be in [1, MHR_MAX_K]");
+    if (nq == 0) return MHR_OK;
+    const size_t need = ws_layout(nq, kc_for(kmax)).total;
+    if (need > MHR_NOALLOC_SCRATCH_BYTES) {
+        set_error("mhr_topk_paths_noalloc: the batch needs a larger workspace than the fixed scratch array holds "
+                  "(use mhr_topk_paths with a caller workspace, or fewer queries / a smaller k_max)");
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    int dev = -1;
+    MHR_HIP_TRY(hipGetDevice(&dev));
+    MHR_ARG_CHECK(dev == g->device, "mhr_topk_paths_noalloc: the graph lives on another device than the current one");
+    void *ws = scratch_address(dev);
+    if (!ws) return MHR_ERR_DEVICE;
+    return topk_impl(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, ws,
+                     MHR_NOALLOC_SCRATCH_BYTES, stream, nullptr, nullptr, nullptr);
 }
