@@ -153,7 +153,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample, gpu_result=None, per_core_queries=32):
+def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample, gpu_result=None, per_core_queries=32, scorer="distmult"):
     """The FP64 oracle timed on the host cores (OpenMP over queries, threads
     pinned close to cores), on the first nsample queries; then a
     single-thread run on the first per_core_queries for a per-core rate.
@@ -168,7 +168,7 @@ def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample, gpu_result=None, per_core
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     orc = run_oracle(cfg.graph.n, cfg.graph.R, h, r, t, X, Y, s[:nsample], d[:nsample], k[:nsample],
-                     cfg.emb.dtype, og=og)
+                     cfg.emb.dtype, og=og, scorer=scorer)
     dt = time.perf_counter() - t0
     npaths = int(orc.total.sum())
     parity = None
@@ -180,7 +180,7 @@ def cpu_baseline(cfg, h, r, t, X, Y, s, d, k, nsample, gpu_result=None, per_core
     Xf = oracle.as_f32_table(X, cfg.emb.dtype)
     Yf = oracle.as_f32_table(Y, cfg.emb.dtype)
     t1 = time.perf_counter()
-    _, _, tot1 = og.topk(Xf, Yf, s[:n1], d[:n1], k[:n1], nthreads=1)
+    _, _, tot1 = og.topk(Xf, Yf, s[:n1], d[:n1], k[:n1], nthreads=1, scorer=scorer)
     dt1 = time.perf_counter() - t1
     out = {"value": npaths / dt, "unit": "paths/s", "cores": int(threads), "kind": "oracle",
            "sample": f"first {nsample} of the {len(s)} queries (K={int(k[0])}); FP64 brute-force enumeration, "
@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--no-bytes", action="store_true")
     ap.add_argument("--train-queries", type=int, default=200000, help="learned-pruner form: training queries")
     ap.add_argument("--hidden", type=int, default=512, help="learned-pruner form: hidden width")
+    ap.add_argument("--scorer", default="distmult", choices=["distmult", "transe_l1"],
+                    help="edge scorer (transe_l1: gamma = 1 minus the L1 distance, the paper's score)")
     ap.add_argument("--band-abs", type=float, default=0.0,
                     help="absolute rescoring band below the K-th score (0: the rigorous band alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -292,6 +294,8 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     g = mhr.Graph(h, r, t, cfg.graph.n, cfg.graph.R)
+    if args.scorer != "distmult":
+        g.set_scorer(args.scorer, 1.0)
     if cfg.emb.dtype == "bf16":
         Xd = torch.from_numpy(X.view(np.int16)).cuda()
         Yd = torch.from_numpy(Y.view(np.int16)).cuda()
@@ -401,7 +405,7 @@ def main():
     if not args.no_cpu_baseline:
         nsample = args.cpu_sample or {"realistic": 1024, "precision": 256, "batched": 512}.get(args.config, 256)
         cpu, parity = cpu_baseline(cfg, h, r, t, X, Y, s, d, k, min(nsample, len(s)),
-                                   gpu_result=(p, cnt, tot, st))
+                                   gpu_result=(p, cnt, tot, st), scorer=args.scorer)
         log(f"cpu baseline: {cpu}")
         log(f"parity against the oracle: {parity}")
 
@@ -425,7 +429,7 @@ def main():
                                f"{cfg.graph.m} edges, d={cfg.emb.d} {cfg.emb.dtype}, {len(s)} queries, "
                                f"K={'/'.join(map(str, cfg.query.k_choices)) if per_query_k else cfg.query.k}",
                    "queries": len(s), "k": k_max, "dim": cfg.emb.d,
-                   "band_abs": args.band_abs},
+                   "band_abs": args.band_abs, "scorer": args.scorer},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -8,11 +8,14 @@
  * return the K best paths from s to t.  This library fixes the three-hop
  * case: a path is a walk s -r1-> a -r2-> b -r3-> t of exactly three edges
  * (a and b may repeat s, t or each other).  Edge weights come from the
- * learned embeddings (section 1 leaves the function open; this library uses
- * the DistMult score passed through a log-sigmoid):
+ * learned embeddings (section 1 leaves the function open).  Two scorers:
  *
+ *   DistMult + log-sigmoid (the default):
  *     x(u,r,v) = sum_i X[u][i] * Y[r][i] * X[v][i]
  *     w(u,r,v) = logsigmoid(x) = min(x,0) - log1p(exp(-|x|))
+ *   TransE-L1, the paper's own score (section 3.3; gamma = 1.0 there):
+ *     w(u,r,v) = gamma - sum_i |(X[u][i] + Y[r][i]) - X[v][i]|
+ *
  *     S        = w(s,r1,a) + w(a,r2,b) + w(b,r3,t)
  *
  * Results are ranked by S descending, then a, b, r1, r2, r3 ascending (a
@@ -61,6 +64,12 @@ typedef enum mhr_dtype {
     MHR_DTYPE_F32 = 0,   /* IEEE binary32 */
     MHR_DTYPE_BF16 = 1   /* bfloat16 bit patterns (uint16) */
 } mhr_dtype;
+
+/* Edge scorer (the weight of an edge from the embeddings). */
+typedef enum mhr_scorer {
+    MHR_SCORER_DISTMULT = 0,   /* logsigmoid(sum_i X[u][i] Y[r][i] X[v][i]); matrix-core scoring */
+    MHR_SCORER_TRANSE_L1 = 1   /* gamma - sum_i |X[u][i] + Y[r][i] - X[v][i]|; vector-unit scoring */
+} mhr_scorer;
 
 #define MHR_MAX_K 224u
 #define MHR_MAX_RELATIONS 32u
@@ -131,6 +140,14 @@ mhr_status mhr_graph_create(const mhr_graph_desc *desc, void *stream, mhr_graph 
  * in [8, 512].  Enqueues nothing (`stream` is unused). */
 mhr_status mhr_graph_set_embeddings(mhr_graph *g, mhr_dtype dtype, uint32_t dim,
                                     const void *entity, const void *relation, void *stream);
+
+/* Selects the edge scorer for every later query on g (default: DistMult).
+ * TransE-L1 is the score of the paper's experiments (section 3.3, the person
+ * and affiliation scoring algorithms): the L1 distance between head plus
+ * relation and tail, subtracted from gamma (1.0 in the paper).  The weight
+ * is directed (w(u,r,v) != w(v,r,u) in general).  gamma must be finite.
+ * Enqueues nothing.  Errors: INVALID_ARGUMENT. */
+mhr_status mhr_graph_set_scorer(mhr_graph *g, mhr_scorer scorer, float gamma);
 
 mhr_status mhr_graph_get_stats(const mhr_graph *g, mhr_graph_stats *out);
 
@@ -424,9 +441,10 @@ mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint32_t kmax, c
 
 /* Edge-weight kernel on its own (for checking the scorer):
  * for each i < ne, the edge (u[i], r[i], v[i]) (it need not exist in the
- * graph): w_f32[i] = FP32 log-sigmoid of the DistMult score and err_f32[i] a
- * rigorous bound on its error; w_hi[i] + w_lo[i] = the compensated
- * (float-float) value.  Any output pointer may be NULL.  Device arrays. */
+ * graph): w_f32[i] = the graph's scorer evaluated in FP32 as the fast pass
+ * does it and err_f32[i] a rigorous bound on its error; w_hi[i] + w_lo[i] =
+ * the compensated (float-float) value.  Any output pointer may be NULL.
+ * Device arrays. */
 mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const uint32_t *u,
                             const uint32_t *r, const uint32_t *v, float *w_f32,
                             float *err_f32, float *w_hi, float *w_lo, void *stream);

@@ -37,6 +37,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS, Q_OVERFLOW = 1, 2, 4, 8
 PATH_RESCORED, PATH_PRECISION_TIE = 1, 2
 DTYPE_F32, DTYPE_BF16 = 0, 1
+SCORERS = {"distmult": 0, "transe_l1": 1}
 
 PATH_DTYPE = np.dtype([("a", np.uint32), ("b", np.uint32), ("r1", np.uint16), ("r2", np.uint16),
                        ("r3", np.uint16), ("flags", np.uint16), ("score", np.float32),
@@ -76,6 +77,8 @@ _lib.mhr_graph_create.restype = _i
 _lib.mhr_graph_create.argtypes = [ctypes.POINTER(_GraphDesc), _vp, ctypes.POINTER(_vp)]
 _lib.mhr_graph_set_embeddings.restype = _i
 _lib.mhr_graph_set_embeddings.argtypes = [_vp, _i, _u32, _vp, _vp, _vp]
+_lib.mhr_graph_set_scorer.restype = _i
+_lib.mhr_graph_set_scorer.argtypes = [_vp, _i, ctypes.c_float]
 _lib.mhr_graph_get_stats.restype = _i
 _lib.mhr_graph_get_stats.argtypes = [_vp, ctypes.POINTER(_GraphStats)]
 _lib.mhr_graph_export_csr.restype = _i
@@ -260,6 +263,15 @@ class Graph:
                                              _stream_ptr(stream)), "mhr_graph_set_embeddings")
         self._emb = (X, Y)
         self.dim = int(X.shape[1])
+
+    def set_scorer(self, scorer: str = "distmult", gamma: float = 1.0):
+        """Edge scorer for later queries: "distmult" (logsigmoid of the
+        DistMult score, the default) or "transe_l1" (gamma minus the L1
+        distance of head plus relation from tail)."""
+        if scorer not in SCORERS:
+            raise ValueError(f"unknown scorer {scorer!r}")
+        _check(_lib.mhr_graph_set_scorer(self._h, SCORERS[scorer], float(gamma)), "mhr_graph_set_scorer")
+        self.scorer, self.gamma = scorer, float(gamma)
 
     def stats(self) -> dict:
         s = _GraphStats()

@@ -463,6 +463,15 @@ extern "C" mhr_status mhr_graph_destroy(mhr_graph *g) {
     return MHR_OK;
 }
 
+extern "C" mhr_status mhr_graph_set_scorer(mhr_graph *g, mhr_scorer scorer, float gamma) {
+    MHR_ARG_CHECK(g != nullptr, "mhr_graph_set_scorer: null graph");
+    MHR_ARG_CHECK(scorer == MHR_SCORER_DISTMULT || scorer == MHR_SCORER_TRANSE_L1, "unknown scorer");
+    MHR_ARG_CHECK(gamma == gamma && gamma <= 3.0e38f && gamma >= -3.0e38f, "gamma must be finite");
+    g->scorer = scorer;
+    g->gamma = gamma;
+    return MHR_OK;
+}
+
 extern "C" mhr_status mhr_graph_get_stats(const mhr_graph *g, mhr_graph_stats *o) {
     MHR_ARG_CHECK(g && o, "mhr_graph_get_stats: null argument");
     mhr_graph_stats s{};

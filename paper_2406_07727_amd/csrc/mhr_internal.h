@@ -67,6 +67,8 @@ struct mhr_graph {
     const void *Y = nullptr;
     uint32_t dim = 0;
     mhr_dtype dtype = MHR_DTYPE_F32;
+    mhr_scorer scorer = MHR_SCORER_DISTMULT;
+    float gamma = 1.0f;           // TransE-L1 constant
     uint64_t device_bytes = 0;
     int device = 0;
 };

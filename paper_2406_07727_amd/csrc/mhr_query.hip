@@ -71,6 +71,7 @@ struct GArgs {
     uint32_t *exact_list;
     uint32_t tcap, hash_log2, nq, kc, tile_edges;
     float band_abs;              // minimum rescoring band width below the K-th score
+    float gamma;                 // TransE-L1 scorer: the constant the L1 distance is subtracted from
     const uint8_t *keep;         // pruned search: keep flags (nullptr: every entry kept)
     const uint64_t *keep_off;    // per query: offset of its flags in keep
 };
@@ -474,18 +475,87 @@ __device__ inline ff group_edge_x_ff(const GArgs &A, uint32_t u, uint32_t r, uin
     return acc;
 }
 
+// TransE-L1 term |(X[u,i] + Y[r,i]) - X[v,i]| in float-float: TwoSum makes
+// X[u,i] + Y[r,i] exact; subtracting X[v,i] (double-word plus float) errs by
+// at most 2u^2 of the result; the absolute value is exact.
+__device__ __forceinline__ ff transe_term_ff(float xu, float yr, float xv) {
+    const ff t = ff_add_f(two_sum(xu, yr), -xv);
+    return t.hi < 0.0f ? ff_neg(t) : t;
+}
+
+// The L1 distance sum_i |(X[u,i] + Y[r,i]) - X[v,i]| of the TransE score in
+// float-float, in ascending i (the terms are non-negative, so each
+// double-word addition errs by at most 3u^2 of a partial sum <= the total).
+// *abs_sum receives the FP32 sum of the terms' leading parts (for bounds).
+template <bool BF16>
+__device__ inline ff edge_l1_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
+    ff acc = {0.0f, 0.0f};
+    float as = 0.0f;
+    for (uint32_t i0 = 0; i0 < A.d; i0 += 8) {
+        float xu[8], yr[8], xv[8];
+        load8<BF16>(A.X, u, A.d, i0, xu);
+        load8<BF16>(A.Y, r, A.d, i0, yr);
+        load8<BF16>(A.X, v, A.d, i0, xv);
+#pragma unroll
+        for (int l = 0; l < 8; ++l) {
+            const ff t = transe_term_ff(xu[l], yr[l], xv[l]);
+            acc = ff_add(acc, t);
+            as += t.hi;
+        }
+    }
+    *abs_sum = as;
+    return acc;
+}
+
+// The same distance computed by an aligned group of G lanes (strided terms,
+// then a butterfly of symmetric float-float additions; every lane of the
+// group ends with the same bits).
+template <bool BF16, int G>
+__device__ inline ff group_edge_l1_ff(const GArgs &A, uint32_t u, uint32_t r, uint32_t v, float *abs_sum) {
+    ff acc = {0.0f, 0.0f};
+    float as = 0.0f;
+    const size_t d = A.d;
+    for (uint32_t i = threadIdx.x & (G - 1); i < A.d; i += G) {
+        const ff t = transe_term_ff(load1<BF16>(A.X, u * d + i), load1<BF16>(A.Y, r * d + i),
+                                    load1<BF16>(A.X, v * d + i));
+        acc = ff_add(acc, t);
+        as += t.hi;
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const ff w = {__shfl_xor(acc.hi, o, kWave), __shfl_xor(acc.lo, o, kWave)};
+        acc = ff_add(acc, w);
+        as += __shfl_xor(as, o, kWave);
+    }
+    *abs_sum = as;
+    return acc;
+}
+
 // S = w(s,r1,a) + w(a,r2,b) + w(b,r3,t) in float-float, with a bound on
-// its error: per edge, the dot product (about 4 d u^2 sum|t|) plus the
-// log-sigmoid; then the two additions.
+// its error.  DistMult (TE = false): w = logsigmoid(x) of the dot product;
+// per edge, the dot product (about 4 d u^2 sum|t|) plus the log-sigmoid.
+// TransE-L1 (TE = true): w = gamma - L1 distance; per edge, the distance
+// (at most (3d + 2) u^2 of its value) and the subtraction from gamma.  Then
+// the two additions of the weights.
 // G = 1: one thread alone; G > 1 (a power of two, >= 4): an aligned group
 // of G lanes computes the score together and every lane returns it.
-template <bool BF16, int G>
+template <bool BF16, int G, bool TE>
 __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint32_t b, uint32_t t, uint32_t r1,
                                    uint32_t r2, uint32_t r3, float *eps) {
     const float u2 = kUnit * kUnit;
     float as1, as2, as3;
     ff x1, x2, x3;
-    if (G > 1) {
+    if constexpr (TE) {
+        if (G > 1) {
+            x1 = group_edge_l1_ff<BF16, G>(A, s, r1, a, &as1);
+            x2 = group_edge_l1_ff<BF16, G>(A, a, r2, b, &as2);
+            x3 = group_edge_l1_ff<BF16, G>(A, b, r3, t, &as3);
+        } else {
+            x1 = edge_l1_ff<BF16>(A, s, r1, a, &as1);
+            x2 = edge_l1_ff<BF16>(A, a, r2, b, &as2);
+            x3 = edge_l1_ff<BF16>(A, b, r3, t, &as3);
+        }
+    } else if (G > 1) {
         x1 = group_edge_x_ff<BF16, G>(A, s, r1, a, &as1);
         x2 = group_edge_x_ff<BF16, G>(A, a, r2, b, &as2);
         x3 = group_edge_x_ff<BF16, G>(A, b, r3, t, &as3);
@@ -495,7 +565,11 @@ __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint3
         x3 = edge_x_ff<BF16>(A, b, r3, t, &as3);
     }
     ff w1, w2, w3;
-    if (G > 1) {
+    if constexpr (TE) {
+        w1 = ff_add_f(ff_neg(x1), A.gamma);
+        w2 = ff_add_f(ff_neg(x2), A.gamma);
+        w3 = ff_add_f(ff_neg(x3), A.gamma);
+    } else if (G > 1) {
         // the group's lanes 0, 1, 2 (mod 3) take one log-sigmoid each; every
         // lane then reads all three
         const int lane = static_cast<int>(threadIdx.x & (kWave - 1));
@@ -527,8 +601,15 @@ __device__ inline ff path_score_ff(const GArgs &A, uint32_t s, uint32_t a, uint3
     order(v1, v2);
     ff S = ff_add(ff_add(v1, v2), v3);
     float dd = static_cast<float>(A.d);
-    float e = 4.04f * dd * u2 * (as1 + as2 + as3) * 1.01f + ff_logsigmoid_err(w1.hi) + ff_logsigmoid_err(w2.hi) +
-              ff_logsigmoid_err(w3.hi) + 8.0f * u2 * (fabsf(w1.hi) + fabsf(w2.hi) + fabsf(w3.hi));
+    float e;
+    if constexpr (TE) {
+        const float g = fabsf(A.gamma);
+        e = (3.0f * dd + 4.0f) * u2 * 1.01f * ((as1 + g) + (as2 + g) + (as3 + g)) +
+            8.0f * u2 * (fabsf(w1.hi) + fabsf(w2.hi) + fabsf(w3.hi));
+    } else {
+        e = 4.04f * dd * u2 * (as1 + as2 + as3) * 1.01f + ff_logsigmoid_err(w1.hi) + ff_logsigmoid_err(w2.hi) +
+            ff_logsigmoid_err(w3.hi) + 8.0f * u2 * (fabsf(w1.hi) + fabsf(w2.hi) + fabsf(w3.hi));
+    }
     *eps = e;
     return S;
 }
@@ -562,7 +643,7 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~static_
 
 struct GatherLayout {
     size_t hkeys, hvals, Y, anc_p, anc_l, rows, rowval, roweps, qpos, qmp, sub, slab, list, stage,
-        ymax, rowrel, slab_rel, mkeys, shared, total;
+        ymax, ysum, rowrel, slab_rel, mkeys, shared, total;
 };
 
 constexpr int kSubFields = 7;  // pos, y, mp, mm, row, voff, first item
@@ -587,6 +668,7 @@ __host__ __device__ inline GatherLayout gather_layout(uint32_t hash_log2, uint32
     L.list = o; o = align16(o + size_t(kc) * sizeof(Cand));
     L.stage = o; o = align16(o + size_t(next_pow2(kStage + kc)) * sizeof(Cand));
     L.ymax = o; o = align16(o + size_t(R) * 4);
+    L.ysum = o; o = align16(o + size_t(R) * 4);
     L.rowrel = o; o = align16(o + size_t(kRowBatch) * R);
     L.slab_rel = o; o = align16(o + kSlab);
     L.shared = o; o = align16(o + sizeof(GatherShared));
@@ -674,6 +756,69 @@ __device__ inline void score_values(const float (&a)[8], float suma, uint32_t ma
     }
 }
 
+// TransE-L1 values of the edges of one match (or one list row) held by a
+// group of G lanes, lane glane owning elements [glane*epl, glane*epl + epl).
+// For each relation r in maskA the value is f = gamma - sum_i |(pa[i] +
+// Y[r][i]) - qa[i]| (pa the head's slice, qa the tail's), then for each r in
+// maskB the same with pb, qb; values go to out[k] in that order (maskA bits
+// ascending, then maskB bits), their error bounds to out_eps[k] (unless
+// out_eps is null).  Four
+// values at a time, lane j of the group finishing value j.
+//
+// Error bound: per element, the rounded head + relation and the rounded
+// difference err by at most 2u(1 + u)(|p_i| + |Y_ri| + |q_i|); the sum adds
+// at most epl - 1 + log2 G roundings of non-negative terms, and subtracting
+// from gamma one more, so
+// |f_fp32 - f| <= gamma_{d+3} (sum|p| + sum|Y_r| + sum|q|) + 2u |f|
+// with sum|p| + sum|q| in tsumA / tsumB and sum|Y_r| in ysum[r].
+__device__ inline void score_values_te(const float (&pa)[8], const float (&qa)[8], float tsumA, uint32_t maskA,
+                                       const float (&pb)[8], const float (&qb)[8], float tsumB, uint32_t maskB,
+                                       const float *Ys, const float *ysum, uint32_t ys, float gamma, float gamT,
+                                       int G, int epl, int glane, float *out, float *out_eps, uint8_t *out_rel) {
+    const uint32_t na = __popc(maskA), nv = na + __popc(maskB);
+    uint32_t ra = maskA, rb = maskB;
+    const int off = glane * epl;
+    for (uint32_t c = 0; c < nv; c += 4) {
+        float part[4];
+        uint32_t rel[4];
+        bool isa[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t v = c + j;
+            part[j] = 0.0f;
+            rel[j] = 0;
+            isa[j] = false;
+            if (v < nv) {
+                if (v < na) {
+                    rel[j] = static_cast<uint32_t>(__ffs(ra) - 1);
+                    ra &= ra - 1;
+                    isa[j] = true;
+                } else {
+                    rel[j] = static_cast<uint32_t>(__ffs(rb) - 1);
+                    rb &= rb - 1;
+                }
+                const float *yr = Ys + rel[j] * ys + off;
+                float acc = 0.0f;
+#pragma unroll
+                for (int l = 0; l < 8; ++l)
+                    if (l < epl) acc += fabsf(((isa[j] ? pa[l] : pb[l]) + yr[l]) - (isa[j] ? qa[l] : qb[l]));
+                part[j] = acc;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] = group_sum(part[j], G);
+        if (glane < 4 && c + glane < nv) {
+            const float x = glane == 0 ? part[0] : glane == 1 ? part[1] : glane == 2 ? part[2] : part[3];
+            const uint32_t r = glane == 0 ? rel[0] : glane == 1 ? rel[1] : glane == 2 ? rel[2] : rel[3];
+            const bool ia = glane == 0 ? isa[0] : glane == 1 ? isa[1] : glane == 2 ? isa[2] : isa[3];
+            const float f = gamma - x;
+            out[c + glane] = f;
+            if (out_eps) out_eps[c + glane] = gamT * ((ia ? tsumA : tsumB) + ysum[r]) + 2.0f * kUnit * fabsf(f);
+            out_rel[c + glane] = static_cast<uint8_t>(r);
+        }
+    }
+}
+
 // Merge the staged candidates into the kept list (whole block).
 // Order-preserving integer key of an FP32 score.
 __device__ __forceinline__ uint32_t fkey(float x) {
@@ -710,7 +855,7 @@ __device__ inline void block_sort_keys_desc(uint64_t *keys, uint32_t n2) {
 // Exhaustive pass (EXACT): the scores are final, so the list keeps the best
 // KC under the total order (score, then ids) and the whole candidates are
 // sorted.
-template <int KC, bool EXACT, bool BF16>
+template <int KC, bool EXACT, bool BF16, bool TE>
 __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, uint32_t *hist, const GArgs &A,
                                    uint32_t s, uint32_t t) {
     const uint32_t ns = sh->stage_n;
@@ -720,7 +865,7 @@ __device__ inline void merge_stage(Cand *list, Cand *stage, GatherShared *sh, ui
         for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x) {
             Cand c = stage[i];
             float e;
-            const ff sc = path_score_ff<BF16, 1>(A, s, c.a, c.b, t, (c.rel >> 16) & 0xFF, (c.rel >> 8) & 0xFF,
+            const ff sc = path_score_ff<BF16, 1, TE>(A, s, c.a, c.b, t, (c.rel >> 16) & 0xFF, (c.rel >> 8) & 0xFF,
                                                  c.rel & 0xFF, &e);
             c.s = sc.hi;
             c.s_lo = sc.lo;
@@ -905,7 +1050,8 @@ __device__ __forceinline__ float combine3(bool fwd, float fp, float fm, float fl
     return fwd ? (fl + fm) + fp : (fp + fm) + fl;
 }
 
-template <bool BF16, bool EXACT, int KC>
+// TE: the TransE-L1 scorer (VALU); otherwise DistMult (matrix cores).
+template <bool BF16, bool EXACT, int KC, bool TE>
 __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const GatherLayout Lo = gather_layout(A.hash_log2, A.R, A.d, KC);
@@ -925,6 +1071,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     Cand *stage = reinterpret_cast<Cand *>(smem + Lo.stage);
     GatherShared *sh = reinterpret_cast<GatherShared *>(smem + Lo.shared);
     float *ymax = reinterpret_cast<float *>(smem + Lo.ymax);
+    float *ysum = reinterpret_cast<float *>(smem + Lo.ysum);   // sum_i |Y[r][i]| (TransE bounds)
     uint32_t *mkeys = reinterpret_cast<uint32_t *>(smem + Lo.mkeys);  // stage-merge histogram
     uint8_t *rowrel = reinterpret_cast<uint8_t *>(smem + Lo.rowrel);
     uint8_t *slab_rel = reinterpret_cast<uint8_t *>(smem + Lo.slab_rel);
@@ -947,10 +1094,15 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     for (uint32_t i = tid; i < R * d; i += kBlock) Ys[(i / d) * ystr + i % d] = load1<BF16>(A.Y, i);
     __syncthreads();
     for (uint32_t r = tid; r < R; r += kBlock) {
-        float m = 0.0f;
-        for (uint32_t i = 0; i < d; ++i) m = fmaxf(m, fabsf(Ys[r * ystr + i]));
+        float m = 0.0f, sa = 0.0f;
+        for (uint32_t i = 0; i < d; ++i) {
+            m = fmaxf(m, fabsf(Ys[r * ystr + i]));
+            sa += fabsf(Ys[r * ystr + i]);
+        }
         ymax[r] = m;
+        ysum[r] = sa * (1.0f + static_cast<float>(d) * kUnit * 1.01f);   // rounded up
     }
+    const float gamT = gamma_n(static_cast<int>(d) + 3) * 1.001f;   // TransE value bounds
 
     for (;;) {
         __syncthreads();
@@ -1078,15 +1230,29 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             for (uint32_t r = gid; r < nrows; r += ngroups) {
                 float ex[8], z[8];
                 load_lane<BF16>(A.X, rows[r].x, d, glane * epl, epl, ex);
-                float sz = 0.0f;
+                if constexpr (TE) {
+                    // the list edge is x -r-> t (backward) or s -r-> x (forward)
+                    float av[8], sz = 0.0f;
 #pragma unroll
-                for (int l = 0; l < 8; ++l) {
-                    z[l] = (l < epl) ? ex[l] * anc_l[glane * epl + l] : 0.0f;
-                    sz += fabsf(z[l]);
+                    for (int l = 0; l < 8; ++l) {
+                        av[l] = (l < epl) ? anc_l[glane * epl + l] : 0.0f;
+                        sz += fabsf(av[l]) + fabsf(ex[l]);
+                    }
+                    sz = group_sum(sz, G) * (1.0f + static_cast<float>(2 * d + 2) * kUnit * 1.01f);   // rounded up
+                    score_values_te(fwd ? av : ex, fwd ? ex : av, sz, rows[r].mask, av, ex, sz, 0u, Ys, ysum, ystr,
+                                    A.gamma, gamT, G, epl, glane, rowval + rows[r].vbase, roweps + rows[r].vbase,
+                                    rowrel + rows[r].vbase);
+                } else {
+                    float sz = 0.0f;
+#pragma unroll
+                    for (int l = 0; l < 8; ++l) {
+                        z[l] = (l < epl) ? ex[l] * anc_l[glane * epl + l] : 0.0f;
+                        sz += fabsf(z[l]);
+                    }
+                    sz = group_sum(sz, G);
+                    score_values(z, sz, rows[r].mask, z, sz, 0u, Ys, ymax, ystr, G, epl, glane,
+                                 rowval + rows[r].vbase, roweps + rows[r].vbase, rowrel + rows[r].vbase);
                 }
-                sz = group_sum(sz, G);
-                score_values(z, sz, rows[r].mask, z, sz, 0u, Ys, ymax, ystr, G, epl, glane, rowval + rows[r].vbase,
-                             roweps + rows[r].vbase, rowrel + rows[r].vbase);
             }
             __syncthreads();
             if (tid < nrows) {
@@ -1290,7 +1456,43 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     // is exact and only the FP32 accumulation rounds.  The rounding
                     // error is at most gamma_n sum_k |up_k Y_rk| <= gamma_n max_k |Y_rk|
                     // sum_k |up_k|, with n = d + 3 (FP32) or 2d + 3 (bfloat16).
-                    {
+                    //
+                    // TransE-L1 (no products to batch): one group of G lanes per
+                    // match computes the distances of its probe edge and middle edge
+                    // for the relations in their masks on the vector units; the
+                    // values go to the slab in relation order (probe edge, then
+                    // middle edge), and the match's sums sum|head| + sum|tail| of both
+                    // edges to sub_su_p / sub_su_m for the bounds.
+                    if constexpr (TE) {
+                        for (uint32_t m = static_cast<uint32_t>(gid); m < ncnt; m += static_cast<uint32_t>(ngroups)) {
+                            float ey[8], ex[8], av[8];
+                            load_lane<BF16>(A.X, sub_y[m], d, glane * epl, epl, ey);
+                            load_lane<BF16>(A.X, rows[sub_row[m]].x, d, glane * epl, epl, ex);
+                            float sy = 0.0f, sx = 0.0f, sa = 0.0f;
+#pragma unroll
+                            for (int l = 0; l < 8; ++l) {
+                                av[l] = (l < epl) ? anc_p[glane * epl + l] : 0.0f;
+                                sy += fabsf(ey[l]);
+                                sx += fabsf(ex[l]);
+                                sa += fabsf(av[l]);
+                            }
+                            const float up = static_cast<float>(2 * d + 2) * kUnit * 1.01f;   // rounding up the sums
+                            sy = group_sum(sy, G);
+                            sx = group_sum(sx, G);
+                            sa = group_sum(sa, G);
+                            const float tp = (sy + sa) * (1.0f + up), tm = (sy + sx) * (1.0f + up);
+                            const uint32_t vo = sub_voff[m];
+                            // backward: probe edge s -> y, middle edge y -> x;
+                            // forward: probe edge y -> t, middle edge x -> y
+                            score_values_te(fwd ? ey : av, fwd ? av : ey, tp, sub_mp[m], fwd ? ex : ey, fwd ? ey : ex, tm,
+                                            sub_mm[m], Ys, ysum, ystr, A.gamma, gamT, G, epl, glane, slab + vo, nullptr,
+                                            slab_rel + vo);
+                            if (glane == 0) {
+                                sub_su_p[m] = tp;
+                                sub_su_m[m] = tm;
+                            }
+                        }
+                    } else {
                         const int lane = static_cast<int>(tid) & (kWave - 1), wv = static_cast<int>(tid) / kWave;
                         const int mrow = lane & 15, kq = lane >> 4;
                         const uint32_t KCH = d >> 2;
@@ -1438,7 +1640,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     __syncthreads();
                     // centred log-sigmoids of the sub-batch's dot products, dense
                     // over the block
-                    {
+                    if constexpr (!TE) {
                         const uint32_t vn = sh->vn;
                         for (uint32_t ix = tid; ix < vn; ix += kBlock) {
                             float fe;
@@ -1483,7 +1685,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     rr[j] = ok ? slab_rel[vo + k0 + j] : 0u;
                                 }
 #pragma unroll
-                                for (int j = 0; j < 4; ++j) yv[j] = ymax[rr[j]];
+                                for (int j = 0; j < 4; ++j) yv[j] = TE ? ysum[rr[j]] : ymax[rr[j]];
 #pragma unroll
                                 for (int j = 0; j < 4; ++j) {
                                     const uint32_t k = k0 + j;
@@ -1501,9 +1703,14 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             // FP32 operands: d products, each rounded once, then the
                             // sum; bfloat16 operands: 2d exact products (hi and lo
                             // halves), then the sum
+                            // (TransE-L1: gamma_{d+3} (sum|head| + sum|tail| + sum|Y_r|) +
+                            // 2u |f| per value, with the largest sum|Y_r| of the edge's
+                            // relations)
                             const float gam = gamma_n(static_cast<int>(BF16 ? 2 * d : d) + 3) * 1.001f;
-                            const float ep = gam * yp * sub_su_p[tid] + 24.0f * kUnit * axp + 1e-10f;
-                            const float em = gam * ym * sub_su_m[tid] + 24.0f * kUnit * axm + 1e-10f;
+                            const float ep = TE ? gamT * (sub_su_p[tid] + yp) + 2.0f * kUnit * axp
+                                                : gam * yp * sub_su_p[tid] + 24.0f * kUnit * axp + 1e-10f;
+                            const float em = TE ? gamT * (sub_su_m[tid] + ym) + 2.0f * kUnit * axm
+                                                : gam * ym * sub_su_m[tid] + 24.0f * kUnit * axm + 1e-10f;
                             const float perr = ep + em + ri.emax + 2.01f * kUnit * (axp + axm + ri.famax);
                             eps_local = fmaxf(eps_local, perr);
                             sub_su_p[tid] = perr;   // now: the bound on a path's fast-score error
@@ -1534,7 +1741,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         while (nact > 0) {
                             // the free stage slots are shared by the threads still
                             // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT, BF16>(list, stage, sh, mkeys, A, P.s, P.t);
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
                             uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
@@ -1647,7 +1854,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         // ---- tile end: final merge and output
         __syncthreads();
-        if (sh->stage_n > 0) merge_stage<KC, EXACT, BF16>(list, stage, sh, mkeys, A, P.s, P.t);
+        if (sh->stage_n > 0) merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
         float em = block_max<>(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
@@ -1853,7 +2060,7 @@ __device__ float select_top(const GArgs &A, const QueryPlan &P, uint32_t nvalid,
     return __uint_as_float((dk & 0x80000000u) ? (dk & 0x7FFFFFFFu) : ~dk);
 }
 
-template <bool BF16, int KC>
+template <bool BF16, int KC, bool TE>
 __global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *out, uint32_t *out_count,
                                                        uint64_t *out_total, uint32_t *out_status, uint32_t kmax) {
     static_assert(KC <= kMergeBlock, "one thread per kept candidate");
@@ -1930,7 +2137,7 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *o
         Cand x = c[i];
         const uint32_t r1 = (x.rel >> 16) & 0xFF, r2 = (x.rel >> 8) & 0xFF, r3 = x.rel & 0xFF;
         float e;
-        ff sc = path_score_ff<BF16, kRescoreLanes>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
+        ff sc = path_score_ff<BF16, kRescoreLanes, TE>(A, P.s, x.a, x.b, P.t, r1, r2, r3, &e);
         x.s = sc.hi;
         x.s_lo = sc.lo;
         x.eps = e;
@@ -1980,30 +2187,49 @@ __global__ __launch_bounds__(kBlock) void merge_exact_kernel(GArgs A, mhr_path *
 // ---------------------------------------------------------------------------
 // edge weights (unit entry point)
 // ---------------------------------------------------------------------------
-template <bool BF16>
+template <bool BF16, bool TE>
 __global__ void edge_weight_kernel(GArgs A, uint64_t ne, const uint32_t *u, const uint32_t *r, const uint32_t *v,
                                    float *w32, float *e32, float *whi, float *wlo) {
     uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= ne) return;
     const uint32_t uu = u[i], rr = r[i], vv = v[i];
     const size_t d = A.d;
-    float x = 0.0f, as = 0.0f;
-    for (uint32_t k = 0; k < A.d; ++k) {
-        float z = load1<BF16>(A.X, uu * d + k) * load1<BF16>(A.Y, rr * d + k);
-        float xv = load1<BF16>(A.X, vv * d + k);
-        x = __builtin_fmaf(z, xv, x);
-        as += fabsf(z * xv);
+    float w, err;
+    if (TE) {
+        // the fast pass's evaluation: gamma - sum_k |(X[u,k] + Y[r,k]) - X[v,k]|
+        float l1 = 0.0f, ts = 0.0f;
+        for (uint32_t k = 0; k < A.d; ++k) {
+            const float xu = load1<BF16>(A.X, uu * d + k), yr = load1<BF16>(A.Y, rr * d + k);
+            const float xv = load1<BF16>(A.X, vv * d + k);
+            l1 += fabsf((xu + yr) - xv);
+            ts += fabsf(xu) + fabsf(yr) + fabsf(xv);
+        }
+        w = A.gamma - l1;
+        err = gamma_n(static_cast<int>(A.d) + 3) * 1.001f * ts * (1.0f + 3.0f * static_cast<float>(A.d) * kUnit) +
+              2.0f * kUnit * fabsf(w);
+        float asf;
+        const ff wf = ff_add_f(ff_neg(edge_l1_ff<BF16>(A, uu, rr, vv, &asf)), A.gamma);
+        if (whi) whi[i] = wf.hi;
+        if (wlo) wlo[i] = wf.lo;
+    } else {
+        float x = 0.0f, as = 0.0f;
+        for (uint32_t k = 0; k < A.d; ++k) {
+            float z = load1<BF16>(A.X, uu * d + k) * load1<BF16>(A.Y, rr * d + k);
+            float xv = load1<BF16>(A.X, vv * d + k);
+            x = __builtin_fmaf(z, xv, x);
+            as += fabsf(z * xv);
+        }
+        float fe;
+        float f = centred_logsigmoid_e(x, fe);   // the fast pass's evaluation and bound
+        w = f - kLn2f;
+        err = gamma_n(static_cast<int>(A.d) + 2) * as + fe + kUnit * fabsf(w) + kUnit * kLn2f;
+        float asf;
+        ff wf = ff_logsigmoid(edge_x_ff<BF16>(A, uu, rr, vv, &asf));
+        if (whi) whi[i] = wf.hi;
+        if (wlo) wlo[i] = wf.lo;
     }
-    float fe;
-    float f = centred_logsigmoid_e(x, fe);   // the fast pass's evaluation and bound
-    float w = f - kLn2f;
-    float err = gamma_n(static_cast<int>(A.d) + 2) * as + fe + kUnit * fabsf(w) + kUnit * kLn2f;
     if (w32) w32[i] = w;
     if (e32) e32[i] = err;
-    float asf;
-    ff wf = ff_logsigmoid(edge_x_ff<BF16>(A, uu, rr, vv, &asf));
-    if (whi) whi[i] = wf.hi;
-    if (wlo) wlo[i] = wf.lo;
 }
 
 GArgs make_args(const mhr_graph *g) {
@@ -2014,6 +2240,7 @@ GArgs make_args(const mhr_graph *g) {
     A.in_dir_off = g->in.dir_off; A.in_dir_pool = g->in.dir_pool;
     A.X = g->X; A.Y = g->Y;
     A.n = g->n; A.R = g->R; A.d = g->dim; A.id_bits = g->id_bits;
+    A.gamma = g->gamma;
     return A;
 }
 
@@ -2064,7 +2291,7 @@ uint32_t hash_log2_for(const mhr_graph *g, const mhr_query_opts *o, uint32_t kma
     return h;
 }
 
-template <bool BF16, int KC>
+template <bool BF16, int KC, bool TE>
 mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, const uint32_t *src,
                       const uint32_t *dst, const uint32_t *k, uint32_t kmax, mhr_path *out, uint32_t *out_count,
                       uint64_t *out_total, uint32_t *out_status, void *ws, hipStream_t st,
@@ -2103,7 +2330,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
         // persistent: as many workgroups as can be resident at once
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(
-                                                             gather_kernel<BF16, false, KC>),
+                                                             gather_kernel<BF16, false, KC, TE>),
                                                          kBlock, GL.total) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -2117,7 +2344,7 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kSchedLds)));
     hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(kBlock), nq <= kSchedCache ? kSchedLds : 0, st, A);
     hipLaunchKernelGGL(tile_starts_kernel, dim3(nq), dim3(kBlock), 0, st, A);
-    auto gk = gather_kernel<BF16, false, KC>;
+    auto gk = gather_kernel<BF16, false, KC, TE>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(gk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(GL.total)));
     MHR_HIP_TRY(rec(ev ? ev->gather_begin : nullptr));
@@ -2126,11 +2353,11 @@ mhr_status launch_all(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, 
     const size_t msmem = size_t(kMergeSlots) * sizeof(Cand);
     // fast merge: KC candidates, their sort keys, the key cache
     const size_t msmem_keys = size_t(KC) * (sizeof(Cand) + sizeof(uint64_t)) + size_t(kSelCache) * sizeof(uint32_t);
-    auto mk = merge_kernel<BF16, KC>;
+    auto mk = merge_kernel<BF16, KC, TE>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(mk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(msmem_keys)));
     hipLaunchKernelGGL(mk, dim3(nq), dim3(kMergeBlock), msmem_keys, st, A, out, out_count, out_total, out_status, kmax);
-    auto xk = gather_kernel<BF16, true, KC>;
+    auto xk = gather_kernel<BF16, true, KC, TE>;
     MHR_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(xk),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(GL.total)));
     hipLaunchKernelGGL(xk, dim3(grid), dim3(kBlock), GL.total, st, A);
@@ -2207,14 +2434,22 @@ mhr_status topk_impl(const mhr_graph *g, const mhr_query_opts *o, uint32_t nq, c
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool bf = g->dtype == MHR_DTYPE_BF16;
+    const bool te = g->scorer == MHR_SCORER_TRANSE_L1;
+#define MHR_LAUNCH(BF, KCV, TEV)                                                                                   \
+    launch_all<BF, KCV, TEV>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, \
+                             keep, keep_off)
     switch (kc) {
-        case 64: return bf ? launch_all<true, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
-                           : launch_all<false, 64>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
-        case 128: return bf ? launch_all<true, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
-                            : launch_all<false, 128>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
-        default: return bf ? launch_all<true, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off)
-                           : launch_all<false, 256>(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, workspace, st, ev, keep, keep_off);
+        case 64:
+            return bf ? (te ? MHR_LAUNCH(true, 64, true) : MHR_LAUNCH(true, 64, false))
+                      : (te ? MHR_LAUNCH(false, 64, true) : MHR_LAUNCH(false, 64, false));
+        case 128:
+            return bf ? (te ? MHR_LAUNCH(true, 128, true) : MHR_LAUNCH(true, 128, false))
+                      : (te ? MHR_LAUNCH(false, 128, true) : MHR_LAUNCH(false, 128, false));
+        default:
+            return bf ? (te ? MHR_LAUNCH(true, 256, true) : MHR_LAUNCH(true, 256, false))
+                      : (te ? MHR_LAUNCH(false, 256, true) : MHR_LAUNCH(false, 256, false));
     }
+#undef MHR_LAUNCH
 }
 
 }  // namespace
@@ -2252,10 +2487,14 @@ extern "C" mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const ui
     GArgs A = make_args(g);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t blocks = static_cast<uint32_t>((ne + 255) / 256);
-    if (g->dtype == MHR_DTYPE_BF16)
-        hipLaunchKernelGGL(edge_weight_kernel<true>, dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
-    else
-        hipLaunchKernelGGL(edge_weight_kernel<false>, dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
+    const bool te = g->scorer == MHR_SCORER_TRANSE_L1;
+    if (g->dtype == MHR_DTYPE_BF16) {
+        if (te) hipLaunchKernelGGL((edge_weight_kernel<true, true>), dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
+        else hipLaunchKernelGGL((edge_weight_kernel<true, false>), dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
+    } else {
+        if (te) hipLaunchKernelGGL((edge_weight_kernel<false, true>), dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
+        else hipLaunchKernelGGL((edge_weight_kernel<false, false>), dim3(blocks), dim3(256), 0, st, A, ne, u, r, v, w32, e32, whi, wlo);
+    }
     MHR_HIP_TRY(hipGetLastError());
     return MHR_OK;
 }

@@ -41,10 +41,12 @@ def workload(name):
     return _workload_cached(name)
 
 
-def gpu_graph(n, R, h, r, t, X, Y, dtype="f32"):
+def gpu_graph(n, R, h, r, t, X, Y, dtype="f32", scorer="distmult", gamma=1.0):
     import torch
     import paper_2406_07727_amd as mhr
     g = mhr.Graph(h, r, t, n, R)
+    if scorer != "distmult" or gamma != 1.0:
+        g.set_scorer(scorer, gamma)
     if dtype == "bf16":
         Xd = torch.from_numpy(np.array(X, copy=True).view(np.int16)).cuda()
         Yd = torch.from_numpy(np.array(Y, copy=True).view(np.int16)).cuda()
@@ -71,14 +73,16 @@ class OracleResult(NamedTuple):
     full: np.ndarray
 
 
-def run_oracle(n, R, h, r, t, X, Y, s, d, k, dtype="f32", extra=ORACLE_EXTRA, og=None):
+def run_oracle(n, R, h, r, t, X, Y, s, d, k, dtype="f32", extra=ORACLE_EXTRA, og=None, scorer="distmult",
+               gamma=1.0):
     """Runs the oracle with K + extra per query (the extra ranks let the
     comparison check a precision tie at the K-th place)."""
     if og is None:
         og = oracle.Graph(n, R, h, r, t)
     s = np.ascontiguousarray(s, np.uint32)
     kk = np.broadcast_to(np.asarray(k, dtype=np.uint32), (len(s),)).copy()
-    p, full, tot = og.topk(oracle.as_f32_table(X, dtype), oracle.as_f32_table(Y, dtype), s, d, kk + extra)
+    p, full, tot = og.topk(oracle.as_f32_table(X, dtype), oracle.as_f32_table(Y, dtype), s, d, kk + extra,
+                           scorer=scorer, gamma=gamma)
     cnt = np.minimum(kk.astype(np.uint64), tot).astype(np.uint32)
     return OracleResult(p, cnt, tot, full)
 
