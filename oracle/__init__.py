@@ -83,6 +83,8 @@ def _load():
         lib.og_topk.restype = ctypes.c_int
         lib.og_topk.argtypes = [vp, u32, vp, vp, u32, vp, vp, vp, u32, ctypes.c_int,
                                 vp, vp, vp]
+        lib.og_scan_topk.restype = ctypes.c_int
+        lib.og_scan_topk.argtypes = [u32, vp, vp, u32, vp, vp, vp, u32, u32, ctypes.c_double, vp, vp]
         lib.og_max_threads.restype = ctypes.c_int
         lib.og_fsum.restype = ctypes.c_double
         lib.og_fsum.argtypes = [vp, ctypes.c_int]
@@ -188,6 +190,42 @@ class Graph:
         if rc != 0:
             raise ValueError("oracle query failed (bad id, k out of range, or out of memory)")
         return out, cnt, tot
+
+
+def scan_topk(X, Y, head, rel, cand, K, gamma=1.0):
+    """Candidate scan of the paper's Turing-award pipeline (section 3.3):
+    for each query q, the TransE-L1 score gamma - |X[head[q]] + Y[rel[q]] -
+    X[c]|_1 (FP64) of every candidate c in `cand`, and the best min(K,
+    len(cand)) under (score descending, id ascending).  Returns (ids
+    [nq][K], scores [nq][K]); unused slots hold 0xFFFFFFFF and -inf."""
+    X = np.ascontiguousarray(X, np.float32)
+    Y = np.ascontiguousarray(Y, np.float32)
+    head = np.ascontiguousarray(head, np.uint32)
+    rel = np.ascontiguousarray(rel, np.uint32)
+    cand = np.ascontiguousarray(cand, np.uint32)
+    nq = len(head)
+    ids = np.empty((nq, K), np.uint32)
+    sc = np.empty((nq, K), np.float64)
+    if _load().og_scan_topk(X.shape[1], _ptr(X), _ptr(Y), nq, _ptr(head), _ptr(rel), _ptr(cand), len(cand),
+                            int(K), float(gamma), _ptr(ids), _ptr(sc)) != 0:
+        raise MemoryError("oracle scan: allocation failed")
+    return ids, sc
+
+
+def turing_pipeline(X, Y, persons, universities, award, field, r_award, r_works, r_affil, K, gamma=1.0):
+    """The three hops of the paper's pipeline (section 3.2, the simple
+    algorithm; section 3.3 for the scores):
+      1. score every person against (award + r_award) and keep the top K;
+      2. score those K against (field + r_works) and rank them by it;
+      3. for each of them, in that order, score every university against
+         (person + r_affil) and keep the top K.
+    Returns (hop1 ids/scores [K], hop2 ids/scores [K], hop3 ids/scores [K][K])."""
+    h1_id, h1_s = scan_topk(X, Y, [award], [r_award], persons, K, gamma)
+    top = h1_id[0][h1_id[0] != 0xFFFFFFFF]
+    h2_id, h2_s = scan_topk(X, Y, [field], [r_works], top, K, gamma)
+    ranked = h2_id[0][h2_id[0] != 0xFFFFFFFF]
+    h3_id, h3_s = scan_topk(X, Y, ranked, np.full(len(ranked), r_affil, np.uint32), universities, K, gamma)
+    return (h1_id[0], h1_s[0]), (h2_id[0], h2_s[0]), (h3_id, h3_s)
 
 
 def max_threads() -> int:

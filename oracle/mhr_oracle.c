@@ -366,3 +366,52 @@ int og_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Candidate scan (the paper's three-hop Turing-award pipeline,         */
+/* section 3.2 and the person / affiliation scoring of section 3.3)    */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double s; uint32_t id; } og_cand;
+
+/* Score descending, then candidate id ascending (a total order). */
+static int cmp_cand(const void *x, const void *y)
+{
+    const og_cand *p = (const og_cand *)x, *q = (const og_cand *)y;
+    if (p->s != q->s) return p->s > q->s ? -1 : 1;
+    if (p->id != q->id) return p->id < q->id ? -1 : 1;
+    return 0;
+}
+
+/* For each query q: the TransE-L1 score of every candidate c of the list,
+ * gamma - sum_i |(X[head[q],i] + Y[rel[q],i]) - X[c,i]| (candidate as the
+ * tail, FP64, ascending i), and the best min(K, ncand) candidates under
+ * (score descending, id ascending).  out_id / out_s hold nq * K entries.
+ * Returns 0, or -1 on allocation failure. */
+int og_scan_topk(uint32_t d, const float *X, const float *Y, uint32_t nq,
+                 const uint32_t *head, const uint32_t *rel, const uint32_t *cand,
+                 uint32_t ncand, uint32_t K, double gamma,
+                 uint32_t *out_id, double *out_s)
+{
+    int fail = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < (int64_t)nq; ++q) {
+        og_cand *all = (og_cand *)malloc((ncand ? ncand : 1) * sizeof(og_cand));
+        if (!all) { fail = 1; continue; }
+        og_scorer sc = {OG_TRANSE_L1, gamma};
+        for (uint32_t i = 0; i < ncand; ++i) {
+            all[i].id = cand[i];
+            all[i].s = og_edge_weight(sc, d, X, Y, head[q], rel[q], cand[i]);
+        }
+        qsort(all, ncand, sizeof(og_cand), cmp_cand);
+        uint32_t keep = ncand < K ? ncand : K;
+        for (uint32_t k = 0; k < K; ++k) {
+            out_id[(size_t)q * K + k] = k < keep ? all[k].id : 0xFFFFFFFFu;
+            out_s[(size_t)q * K + k] = k < keep ? all[k].s : -HUGE_VAL;
+        }
+        free(all);
+    }
+    return fail ? -1 : 0;
+}
