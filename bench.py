@@ -142,6 +142,45 @@ def gather_bytes(csr_out, csr_in, src, dst, d, elem):
     return total, matches
 
 
+def gather_byte_parts(csr_out, csr_in, src, dst, d, elem):
+    """The terms of gather_bytes separately: list rows (16 B per entry with
+    its row bounds), probe rows (8 B), scanned columns (4 B), middle-edge
+    masks of matches (4 B) and embedding rows."""
+    orp, ocol, _ = csr_out
+    irp, icol, _ = csr_in
+    odeg = np.diff(orp).astype(np.int64)
+    ideg = np.diff(irp).astype(np.int64)
+    out = {"list_rows": 0, "probe_rows": 0, "scan": 0, "match_masks": 0, "emb": 0}
+    for s, t in zip(src.tolist(), dst.tolist()):
+        bl = icol[irp[t]:irp[t + 1]]
+        al = ocol[orp[s]:orp[s + 1]]
+        fwd = int(odeg[al].sum()) < int(ideg[bl].sum())
+        if fwd:
+            lst, rp, col, probe = al, orp, ocol, icol[irp[t]:irp[t + 1]]
+        else:
+            lst, rp, col, probe = bl, irp, icol, ocol[orp[s]:orp[s + 1]]
+        L, P = len(lst), len(probe)
+        out["list_rows"] += 16 * L
+        out["probe_rows"] += 8 * P
+        if L == 0 or P == 0:
+            continue
+        starts, ends = rp[lst].astype(np.int64), rp[lst + 1].astype(np.int64)
+        lens = ends - starts
+        C = int(lens.sum())
+        if not C:
+            continue
+        idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(C)
+        scanned = col[idx]
+        pos = np.searchsorted(probe, scanned)
+        pos[pos >= P] = 0
+        hit = probe[pos] == scanned
+        rowid = np.repeat(np.arange(L), lens)
+        out["scan"] += 4 * C
+        out["match_masks"] += 4 * int(hit.sum())
+        out["emb"] += d * elem * (len(np.unique(scanned[hit])) + len(np.unique(rowid[hit])) + 2)
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -207,6 +246,84 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps}), flush=True)
 
 
+def run_turing(args):
+    """The paper's three-hop award pipeline as a candidate scan (sections
+    3.2-3.3): 539,603 persons, 89,689 universities, K = 50, d = 8, over a
+    91,230,610-entity synthetic table (the shape of WikiKG90Mv2 as the paper
+    ran it).  One step = one pipeline (npipe = 1), and a batched form of
+    independent pipelines in one call.  Exactness: the FP64 oracle's
+    pipeline is compared bit for bit."""
+    import torch
+    import kgsynth
+    import paper_2406_07727_amd as mhr
+    spec = kgsynth.TURING["turing"]
+    t0 = time.perf_counter()
+    X, Y, persons, univ, award, field, (ra, rw, rf) = kgsynth.turing_workload(spec)
+    log(f"turing inputs generated in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.set_device(0)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.from_numpy(Y).cuda()
+    ev = HipEvents()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    K = spec.k
+    scores_per_pipe = len(persons) + K + K * len(univ)
+    results = {}
+    for npipe in (1, args.turing_batch):
+        rng = np.random.Generator(np.random.PCG64(spec.seed + 7))
+        awards = np.concatenate([[award], rng.integers(0, spec.n, npipe - 1)]).astype(np.uint32)
+        fields = np.concatenate([[field], rng.integers(0, spec.n, npipe - 1)]).astype(np.uint32)
+        pl = mhr.ScanPipeline(Xd, Yd, persons, univ, K, npipe=npipe)
+        aw = torch.from_numpy(awards.view(np.int32)).cuda()
+        fi = torch.from_numpy(fields.view(np.int32)).cuda()
+        for _ in range(max(1, args.warmup)):
+            pl.run(aw, fi, ra, rw, rf)
+        torch.cuda.synchronize()
+        e0, e1 = ev.create(), ev.create()
+        assert ev.hip.hipEventRecord(e0, stream) == 0
+        for _ in range(args.steps):
+            pl.run(aw, fi, ra, rw, rf)
+        assert ev.hip.hipEventRecord(e1, stream) == 0
+        ms = ev.elapsed_ms(e0, e1) / args.steps
+        results[npipe] = {"ms_per_call": ms, "pipelines_per_s": npipe / (ms * 1e-3),
+                          "candidate_scores_per_s": npipe * scores_per_pipe / (ms * 1e-3)}
+        log(f"turing npipe={npipe}: {results[npipe]}")
+        if npipe == 1:
+            pl1 = pl
+    # distinct HBM bytes of one pipeline: each candidate's id and row once
+    # per hop (rows re-read by later queries of a hop are cache hits)
+    row = spec.d * 4
+    nbytes = len(persons) * (4 + row) + K * (4 + row) + len(univ) * (4 + row) + 3 * K * 12
+    ms1 = results[1]["ms_per_call"]
+    achieved = nbytes / (ms1 * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "scan_chunk_kernel (whole pipeline)",
+            "bytes_per_launch": int(nbytes), "kernel_ms": round(ms1, 4)}
+    parity = cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        (h1, s1), (h2, s2), (h3, s3) = oracle.turing_pipeline(X, Y, persons, univ, award, field, ra, rw, rf, K)
+        dt = time.perf_counter() - t1
+        same = (np.array_equal(pl1.hop1_id[0].cpu().numpy().view(np.uint32), h1) and
+                np.array_equal(pl1.hop1_score[0].cpu().numpy(), s1) and
+                np.array_equal(pl1.hop2_id[0].cpu().numpy().view(np.uint32), h2) and
+                np.array_equal(pl1.hop2_score[0].cpu().numpy(), s2) and
+                np.array_equal(pl1.hop3_id[0].cpu().numpy().view(np.uint32), h3) and
+                np.array_equal(pl1.hop3_score[0].cpu().numpy(), s3))
+        parity = {"checked": 1, "mismatches": 0 if same else 1, "flagged_ties": 0}
+        cpu = {"value": 1.0 / dt, "unit": "pipelines/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"one pipeline, FP64 scan with OpenMP over queries; {dt:.2f} s", "cpu_model": cpu_model()}
+    out = {"metric": "award-pipeline candidate scan (three hops, K=50, d=8): pipelines/s", "value":
+           results[1]["pipelines_per_s"], "unit": "pipelines/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"turing: {spec.n} entities, d={spec.d} f32, {len(persons)} persons, "
+                                  f"{len(univ)} universities, K={K}", "batched": {str(k): v for k, v in results.items()}},
+           "roofline": roof, "cpu_baseline": cpu, "parity": parity}
+    print(json.dumps(out), flush=True)
+
+
 def run_pruner(args, cfg, g, h, s, d):
     """The learned-pruner form: train the network on exact-search labels,
     then answer the held-out batch with the pruned search (and the exact
@@ -268,6 +385,10 @@ def main():
                     help="edge scorer (transe_l1: gamma = 1 minus the L1 distance, the paper's score)")
     ap.add_argument("--band-abs", type=float, default=0.0,
                     help="absolute rescoring band below the K-th score (0: the rigorous band alone)")
+    ap.add_argument("--turing-batch", type=int, default=64, help="turing: pipelines per batched call")
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="load the phase-clock build (libmhr_phase.so) and report the gather kernel's time and "
+                         "bytes per phase (timings include the clock reads; not a benchmark line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -279,6 +400,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+
+    if args.config == "turing":
+        run_turing(args)
+        return
+    if args.phase_clocks:
+        os.environ["MHR_LIBRARY"] = os.path.join(ROOT, "paper_2406_07727_amd", "libmhr_phase.so")
 
     import torch
     import kgsynth
@@ -379,6 +506,14 @@ def main():
         gather_ms = [ev.elapsed_ms(ctypes.c_void_p(e.gather_begin), ctypes.c_void_p(e.gather_end)) for e in evs]
         gather_avg = float(np.mean(gather_ms))
 
+    phases = None
+    if args.phase_clocks:
+        # the timed steps again, with the phase clocks reset before them
+        mhr.phase_ticks(reset=True)
+        for i in range(args.steps):
+            g.topk(sd, dd, kk, k_max=k_max, out=res, opts=qo)
+        ticks, rate = mhr.phase_ticks()
+        phases = {"ticks": ticks, "rate_hz": rate}
     p, cnt, tot, st = res.to_numpy()
     paths = int(tot.sum())
     exact_pass = int(np.sum((st & mhr.Q_EXACT_PASS) != 0))
@@ -400,6 +535,33 @@ def main():
                 "kernel": "gather_kernel", "bytes_per_launch": int(nbytes), "kernel_ms": round(gather_avg, 4)}
         log(f"gather algorithmic bytes {nbytes / 1e6:.1f} MB ({matches} matched middle pairs) "
             f"in {time.perf_counter() - t1:.1f} s")
+
+    if phases is not None:
+        # per phase: the average workgroup's wall time per launch, and the
+        # algorithmic bytes the phase moves (scanned columns for the probe
+        # phase; embedding rows and middle-edge masks for formation and scoring)
+        ticks, rate = phases["ticks"], phases["rate_hz"]
+        tot_ticks = sum(ticks.values())
+        # the persistent grid holds one workgroup per CU (the LDS of one fills a CU)
+        nblocks = torch.cuda.get_device_properties(0).multi_processor_count
+        per_launch_s = {k: v / rate / nblocks / args.steps for k, v in ticks.items()}
+        out_ph = {k: {"share": round(v / tot_ticks, 4), "ms_per_launch": round(1e3 * per_launch_s[k], 4)}
+                  for k, v in ticks.items()}
+        if roof is not None:
+            csr_out = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=False))
+            csr_in = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=True))
+            elem = 2 if cfg.emb.dtype == "bf16" else 4
+            parts = gather_byte_parts(csr_out, csr_in, s, d, cfg.emb.d, elem)
+            ph_bytes = {"probe": parts["scan"], "form": parts["match_masks"], "score": parts["emb"],
+                        "setup": parts["probe_rows"], "rows": parts["list_rows"]}
+            for k, b in ph_bytes.items():
+                out_ph[k]["bytes"] = int(b)
+                if per_launch_s[k] > 0:
+                    out_ph[k]["GB_s"] = round(b / per_launch_s[k] / 1e9, 1)
+        log(f"gather phases: {json.dumps(out_ph)}")
+        print(json.dumps({"phases": out_ph, "config": args.config, "steps": args.steps,
+                          "note": "phase-clock build; wall time of the average workgroup per launch"}), flush=True)
+        return
 
     cpu = parity = None
     if not args.no_cpu_baseline:

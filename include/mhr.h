@@ -449,6 +449,76 @@ mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const uint32_t *u,
                             const uint32_t *r, const uint32_t *v, float *w_f32,
                             float *err_f32, float *w_hi, float *w_lo, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Candidate scan: the workload of the paper's three-hop award pipeline
+ * (section 3.2, the simple algorithm's three scoring steps; section 3.3,
+ * the person, field and affiliation scoring with the TransE-L1 score).
+ * These calls take the embedding tables directly (no graph handle): the
+ * pipeline scores lists of candidate entities, not graph paths.
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes of mhr_scan_topk for nq queries over lists of ncand
+ * candidates with K = k. */
+mhr_status mhr_scan_workspace_size(uint32_t nq, uint32_t ncand, uint32_t k, size_t *bytes);
+
+/* For each query q, the TransE-L1 score of every candidate c of its list,
+ *     score = gamma - sum_i |(X[head[q], i] + Y[rel[q], i]) - X[c, i]|
+ * (c as the tail), evaluated in FP64 (head plus relation, minus the
+ * candidate, summed in ascending i), and the best min(k, list length)
+ * candidates under (score descending, id ascending).
+ *   entity, relation  device tables [num_entities][dim], [num_relations][dim]
+ *                     of dtype, 16-byte aligned; dim a multiple of 8 <= 512
+ *   head              device uint32[nq]
+ *   rel               device uint32[nq], or NULL: rel_default for every query
+ *   cand              device uint32 lists: query q's list is cand + q *
+ *                     cand_stride, ncand entries (cand_stride = 0: one list
+ *                     shared by all queries).  0xFFFFFFFF entries are absent
+ *                     and skipped; other ids >= num_entities are skipped and
+ *                     flagged.
+ *   k                 1..256
+ *   out_id, out_score device [nq][k]: best first; unused slots 0xFFFFFFFF / -inf
+ *   out_status        device uint32[nq] or NULL: MHR_Q_BAD_ID when head or rel
+ *                     is out of range (no result) or a candidate id was
+ * Asynchronous on `stream`; allocates nothing.  Errors: INVALID_ARGUMENT,
+ * WORKSPACE_TOO_SMALL, DEVICE. */
+mhr_status mhr_scan_topk(mhr_dtype dtype, uint32_t dim, const void *entity, const void *relation,
+                         uint32_t num_entities, uint32_t num_relations, uint32_t nq, const uint32_t *head,
+                         const uint32_t *rel, uint32_t rel_default, const uint32_t *cand, uint32_t ncand,
+                         uint32_t cand_stride, uint32_t k, float gamma, uint32_t *out_id, double *out_score,
+                         uint32_t *out_status, void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of mhr_scan_pipeline. */
+mhr_status mhr_scan_pipeline_workspace_size(uint32_t npipe, uint32_t npersons, uint32_t nuniv, uint32_t k,
+                                            size_t *bytes);
+
+/* npipe independent runs of the three-hop pipeline, all on `stream` with no
+ * host synchronisation (each hop's device output feeds the next):
+ *   hop 1  every person p of `persons` scored against award[j] + r_award;
+ *          the best k -> hop1_id/score[j][k];
+ *   hop 2  those k persons scored against field[j] + r_works and ranked by
+ *          it -> hop2_id/score[j][k];
+ *   hop 3  for each ranked person p (in rank order) every university of
+ *          `universities` scored against p + r_affil; the best k ->
+ *          hop3_id/score[j][rank][k].
+ * award, field: device uint32[npipe]; persons, universities: device lists.
+ * Errors as mhr_scan_topk. */
+mhr_status mhr_scan_pipeline(mhr_dtype dtype, uint32_t dim, const void *entity, const void *relation,
+                             uint32_t num_entities, uint32_t num_relations, uint32_t npipe, const uint32_t *award,
+                             const uint32_t *field, uint32_t r_award, uint32_t r_works, uint32_t r_affil,
+                             const uint32_t *persons, uint32_t npersons, const uint32_t *universities,
+                             uint32_t nuniv, uint32_t k, float gamma, uint32_t *hop1_id, double *hop1_score,
+                             uint32_t *hop2_id, double *hop2_score, uint32_t *hop3_id, double *hop3_score,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+/* Profiling aid: the gather kernel's per-phase wall-clock ticks, summed over
+ * its workgroups since the last reset (phases: tile fetch, setup, list rows,
+ * probe, sub-batch formation, scoring, log-sigmoids, bounds, enumeration,
+ * stage merges, tile end; n >= 11), and the clock rate (Hz).  Recorded only
+ * by the library's phase-clock build (paper_2406_07727_amd/build.py
+ * --phase-clocks); the regular build returns MHR_ERR_UNSUPPORTED.
+ * Synchronises the device. */
+mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *rate_hz, int reset);
+
 const char *mhr_status_string(mhr_status s);
 const char *mhr_last_error(void);
 

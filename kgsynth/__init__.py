@@ -24,7 +24,7 @@ __all__ = [
     "GraphSpec", "EmbSpec", "QuerySpec", "Workload", "CONFIGS",
     "uniform_graph", "chung_lu_weights", "chung_lu_graph", "make_graph",
     "embeddings", "queries", "f32_to_bf16_bits", "bf16_bits_to_f32",
-    "out_degree", "in_degree",
+    "out_degree", "in_degree", "TuringSpec", "TURING", "turing_workload",
 ]
 
 
@@ -345,3 +345,43 @@ def queries(head: np.ndarray, n: int, spec: QuerySpec):
     else:
         k = np.full(nq, spec.k, dtype=np.int64)
     return s.astype(np.uint32), t.astype(np.uint32), k.astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# the award-pipeline candidate scan (paper sections 3.2-3.3, section 4.1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class TuringSpec:
+    n: int               # entities
+    R: int               # relations
+    d: int               # embedding dimension
+    n_persons: int       # candidate persons (first hop)
+    n_univ: int          # candidate universities (third hop)
+    k: int
+    seed: int
+
+
+# The paper's workload shape: WikiKG90Mv2's 91,230,610 entities and 1,387
+# relations, embeddings trimmed to d = 8, 539,603 persons, 89,689 universities,
+# K = 50.  Synthetic tables stand in for the dataset.
+TURING = {
+    "turing": TuringSpec(91_230_610, 1387, 8, 539_603, 89_689, 50, seed=41),
+    "turing_small": TuringSpec(2_000_000, 64, 8, 60_000, 12_000, 50, seed=43),
+    "turing_tiny": TuringSpec(20_000, 8, 8, 3_000, 700, 16, seed=45),
+}
+
+
+def turing_workload(spec: TuringSpec):
+    """Entity and relation tables (N(0, 1/d), FP32), disjoint random person
+    and university id lists, the award and field entities and three distinct
+    relations (award winner, works in, affiliated with).  Returns
+    (X, Y, persons, universities, award, field, (r_award, r_works, r_affil))."""
+    X, Y = embeddings(spec.n, spec.R, EmbSpec(spec.d, "f32", seed=spec.seed))
+    rng = np.random.Generator(np.random.PCG64(spec.seed + 1))
+    ids = rng.choice(spec.n, spec.n_persons + spec.n_univ + 2, replace=False).astype(np.uint32)
+    persons = ids[:spec.n_persons]
+    univ = ids[spec.n_persons:spec.n_persons + spec.n_univ]
+    award, field = int(ids[-2]), int(ids[-1])
+    rels = rng.choice(spec.R, 3, replace=False)
+    return X, Y, persons, univ, award, field, tuple(int(x) for x in rels)

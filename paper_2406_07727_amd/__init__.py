@@ -17,7 +17,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmhr.so")
+# MHR_LIBRARY may name another build of the same library (the phase-clock
+# profiling build, libmhr_phase.so); by default the regular build is loaded.
+LIB_PATH = os.environ.get("MHR_LIBRARY") or os.path.join(_HERE, "libmhr.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2406_07727_amd.build` "
@@ -148,6 +150,19 @@ _lib.mhr_pruner_fallback.argtypes = [_u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, c
                                      _vp, _vp]
 _lib.mhr_scatter_results.restype = _i
 _lib.mhr_scatter_results.argtypes = [_u32, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_scan_workspace_size.restype = _i
+_lib.mhr_scan_workspace_size.argtypes = [_u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_scan_topk.restype = _i
+_lib.mhr_scan_topk.argtypes = [_i, _u32, _vp, _vp, _u32, _u32, _u32, _vp, _vp, _u32, _vp, _u32, _u32, _u32,
+                               ctypes.c_float, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_scan_pipeline_workspace_size.restype = _i
+_lib.mhr_scan_pipeline_workspace_size.argtypes = [_u32, _u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_scan_pipeline.restype = _i
+_lib.mhr_scan_pipeline.argtypes = [_i, _u32, _vp, _vp, _u32, _u32, _u32, _vp, _vp, _u32, _u32, _u32, _vp, _u32, _vp,
+                                   _u32, _u32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                   _vp]
+_lib.mhr_debug_phase_ticks.restype = _i
+_lib.mhr_debug_phase_ticks.argtypes = [_vp, _u32, ctypes.POINTER(ctypes.c_double), _i]
 _lib.mhr_status_string.restype = ctypes.c_char_p
 _lib.mhr_status_string.argtypes = [_i]
 _lib.mhr_last_error.restype = ctypes.c_char_p
@@ -557,6 +572,93 @@ class Pruner:
         return loss
 
 
+GATHER_PHASES = ("fetch", "setup", "rows", "probe", "form", "score", "logsig", "bounds", "enum", "merge", "end")
+
+
+def phase_ticks(reset: bool = False):
+    """The gather kernel's per-phase wall-clock ticks summed over workgroups
+    (phase-clock build only; see mhr_debug_phase_ticks) as {phase: ticks},
+    and the clock rate in Hz."""
+    buf = (ctypes.c_uint64 * 16)()
+    rate = ctypes.c_double()
+    _check(_lib.mhr_debug_phase_ticks(buf, 16, ctypes.byref(rate), 1 if reset else 0), "mhr_debug_phase_ticks")
+    return {p: int(buf[i]) for i, p in enumerate(GATHER_PHASES)}, float(rate.value)
+
+
+def _table(t, dtype):
+    torch = _torch()
+    if dtype is None:
+        dtype = "f32" if t.dtype == torch.float32 else "bf16"
+    return t.contiguous(), (DTYPE_F32 if dtype == "f32" else DTYPE_BF16)
+
+
+def scan_topk(entity, relation, head, cand, k: int, rel=None, rel_default: int = 0, gamma: float = 1.0,
+              cand_stride: int = 0, ncand: Optional[int] = None, dtype: Optional[str] = None, stream=None):
+    """TransE-L1 candidate scan (mhr_scan_topk): for each query q the best k
+    candidates of its list under gamma - |X[head[q]] + Y[rel[q]] - X[c]|_1
+    (FP64).  entity / relation: device tables (float32, or int16/bfloat16
+    bit patterns with dtype="bf16").  Returns (ids [nq, k] int32, scores
+    [nq, k] float64, status [nq] int32) device tensors."""
+    torch = _torch()
+    X, code = _table(entity, dtype)
+    Y, _ = _table(relation, dtype)
+    h = _dev_u32(head)
+    c = _dev_u32(cand)
+    r = _dev_u32(rel) if rel is not None else None
+    nq = h.numel()
+    nc = int(c.numel() if ncand is None else ncand)
+    need = ctypes.c_size_t()
+    _check(_lib.mhr_scan_workspace_size(nq, nc, int(k), ctypes.byref(need)), "mhr_scan_workspace_size")
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    sc = torch.empty((nq, k), dtype=torch.float64, device="cuda")
+    st = torch.empty(max(nq, 1), dtype=torch.int32, device="cuda")
+    _check(_lib.mhr_scan_topk(code, int(X.shape[1]), _ptr(X), _ptr(Y), int(X.shape[0]), int(Y.shape[0]), nq, _ptr(h),
+                              _ptr(r), int(rel_default), _ptr(c), nc, int(cand_stride), int(k), float(gamma),
+                              _ptr(ids), _ptr(sc), _ptr(st), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+           "mhr_scan_topk")
+    return ids, sc, st[:nq]
+
+
+class ScanPipeline:
+    """The three-hop award pipeline (mhr_scan_pipeline) with its buffers
+    allocated once for npipe runs over fixed person and university lists;
+    run() enqueues all three hops on the stream."""
+
+    def __init__(self, entity, relation, persons, universities, k: int, npipe: int = 1, gamma: float = 1.0,
+                 dtype: Optional[str] = None):
+        torch = _torch()
+        self.X, self.code = _table(entity, dtype)
+        self.Y, _ = _table(relation, dtype)
+        self.persons, self.univ = _dev_u32(persons), _dev_u32(universities)
+        self.k, self.npipe, self.gamma = int(k), int(npipe), float(gamma)
+        need = ctypes.c_size_t()
+        _check(_lib.mhr_scan_pipeline_workspace_size(self.npipe, self.persons.numel(), self.univ.numel(), self.k,
+                                                     ctypes.byref(need)), "mhr_scan_pipeline_workspace_size")
+        self.ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
+        P, K = self.npipe, self.k
+        self.hop1_id = torch.empty((P, K), dtype=torch.int32, device="cuda")
+        self.hop1_score = torch.empty((P, K), dtype=torch.float64, device="cuda")
+        self.hop2_id = torch.empty((P, K), dtype=torch.int32, device="cuda")
+        self.hop2_score = torch.empty((P, K), dtype=torch.float64, device="cuda")
+        self.hop3_id = torch.empty((P, K, K), dtype=torch.int32, device="cuda")
+        self.hop3_score = torch.empty((P, K, K), dtype=torch.float64, device="cuda")
+
+    def run(self, award, field, r_award: int, r_works: int, r_affil: int, stream=None):
+        a, f = _dev_u32(award), _dev_u32(field)
+        if a.numel() != self.npipe or f.numel() != self.npipe:
+            raise ValueError("award and field must hold npipe entities")
+        self._keep = (a, f)
+        _check(_lib.mhr_scan_pipeline(self.code, int(self.X.shape[1]), _ptr(self.X), _ptr(self.Y),
+                                      int(self.X.shape[0]), int(self.Y.shape[0]), self.npipe, _ptr(a), _ptr(f),
+                                      int(r_award), int(r_works), int(r_affil), _ptr(self.persons),
+                                      self.persons.numel(), _ptr(self.univ), self.univ.numel(), self.k, self.gamma,
+                                      _ptr(self.hop1_id), _ptr(self.hop1_score), _ptr(self.hop2_id),
+                                      _ptr(self.hop2_score), _ptr(self.hop3_id), _ptr(self.hop3_score),
+                                      _ptr(self.ws), self.ws.numel(), _stream_ptr(stream)), "mhr_scan_pipeline")
+        return self
+
+
 class Plan:
     """A batched query call captured once into a HIP graph and replayed with
     one launch.  The plan owns fixed device buffers for the queries
@@ -608,5 +710,5 @@ class Plan:
             pass
 
 
-__all__ = ["Graph", "Plan", "Pruner", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+__all__ = ["Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
            "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]

@@ -1050,9 +1050,50 @@ __device__ __forceinline__ float combine3(bool fwd, float fp, float fm, float fl
     return fwd ? (fl + fm) + fp : (fp + fm) + fl;
 }
 
+// Phase clocks (a build with MHR_PHASE_CLOCKS defined): thread 0 of each
+// gather workgroup reads the constant-rate wall clock at phase boundaries
+// (each right after a barrier, so the interval is the workgroup's time in
+// the phase that ended) and the totals over all workgroups are added to
+// g_phase_ticks at exit.  Other builds compile the marks away.
+enum GatherPhase {
+    kPhFetch = 0,    // taking a tile, and the previous tile's output
+    kPhSetup,        // probe table, anchors
+    kPhRows,         // list rows: edge values, sorting
+    kPhProbe,        // chunks: row search, column loads, probes, compaction
+    kPhForm,         // sub-batch formation (masks, rows, value offsets)
+    kPhScore,        // edge scoring (matrix cores, or vector units for TransE)
+    kPhLogsig,       // dense log-sigmoids
+    kPhBounds,       // per-match maxima, error bounds, work-item scan
+    kPhEnum,         // path enumeration and staging
+    kPhMerge,        // stage merges into the tile list
+    kPhEnd,          // final merge, tile list and header out
+    kNumPhases
+};
+#ifdef MHR_PHASE_CLOCKS
+__device__ unsigned long long g_phase_ticks[kNumPhases];
+#define MHR_PHASE(p)                                           \
+    do {                                                       \
+        if (tid == 0) {                                        \
+            const unsigned long long now_ = wall_clock64();    \
+            ph_acc[p] += now_ - ph_t;                          \
+            ph_t = now_;                                       \
+        }                                                      \
+    } while (0)
+#else
+#define MHR_PHASE(p) \
+    do {             \
+    } while (0)
+#endif
+
 // TE: the TransE-L1 scorer (VALU); otherwise DistMult (matrix cores).
 template <bool BF16, bool EXACT, int KC, bool TE>
 __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
+#ifdef MHR_PHASE_CLOCKS
+    __shared__ unsigned long long ph_acc[kNumPhases];
+    __shared__ unsigned long long ph_t;
+    if (threadIdx.x < kNumPhases) ph_acc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ph_t = wall_clock64();
+#endif
     extern __shared__ __align__(16) unsigned char smem[];
     const GatherLayout Lo = gather_layout(A.hash_log2, A.R, A.d, KC);
     uint32_t *hkeys = reinterpret_cast<uint32_t *>(smem + Lo.hkeys);
@@ -1135,6 +1176,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         __syncthreads();
         const uint32_t tile = sh->tile;
+        MHR_PHASE(kPhFetch);
         if (tile == kEmpty) break;
         const uint32_t q = sh->q, j = sh->j;
         const QueryPlan P = A.plans[q];
@@ -1191,6 +1233,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         uint64_t npaths = 0;
         float eps_local = 0.0f;
         __syncthreads();
+        MHR_PHASE(kPhSetup);
 
         // ---- row batches
         const uint32_t row_end = (te.y > 0) ? te.x + 1 : te.x;  // exclusive
@@ -1269,6 +1312,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             }
             __syncthreads();
             const uint32_t E = sh->E;
+            MHR_PHASE(kPhRows);
 
             // ---- chunks of scanned entries.  Matches queue up across chunks
             // until a full sub-batch is ready (all of them after the last
@@ -1405,6 +1449,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     }
                 }
                 __syncthreads();
+                MHR_PHASE(kPhProbe);
                 const uint32_t nmatch = sh->qcount;
 
                 // ---- sub-batches of at most kBlock matches (value slab permitting)
@@ -1441,6 +1486,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         if (tid + 1 == ncnt) sh->vn = vincl;   // the taken matches are a prefix
                     }
                     __syncthreads();
+                    MHR_PHASE(kPhForm);
                     // scoring on the matrix cores: a wave takes 16 matches at a time.
                     // Lane (row m = lane & 15, k-quarter kq = lane >> 4) holds the
                     // d/4 elements [kq*d/4, (kq+1)*d/4) of match m's vectors
@@ -1638,6 +1684,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         }
                     }
                     __syncthreads();
+                    MHR_PHASE(kPhScore);
                     // centred log-sigmoids of the sub-batch's dot products, dense
                     // over the block
                     if constexpr (!TE) {
@@ -1648,6 +1695,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         }
                     }
                     __syncthreads();
+                    MHR_PHASE(kPhLogsig);
 
                     // ---- path enumeration.  A work item is one (match, probe value,
                     // mid value) triple; items are spread over the block so that a
@@ -1728,6 +1776,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         const uint32_t iincl = block_incl_scan<uint32_t>(nitems, sh->red32, &ntot);
                         sub_item[tid] = iincl - nitems;
                         __syncthreads();
+                        MHR_PHASE(kPhBounds);
                         // Each thread walks the items tid, tid + kBlock, ...; its cursor
                         // (item, list position) survives the rounds, so a round ends
                         // only when the stage quota is used up or the items run out.
@@ -1741,7 +1790,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         while (nact > 0) {
                             // the free stage slots are shared by the threads still
                             // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
+                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) {
+                                MHR_PHASE(kPhEnum);
+                                merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
+                                MHR_PHASE(kPhMerge);
+                            }
                             uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
                             if (quota > kMaxQuota) quota = kMaxQuota;
                             const Cand thr = sh->thr;
@@ -1831,6 +1884,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     }
                     m0 += ncnt;
                     __syncthreads();
+                    MHR_PHASE(kPhEnum);
                 }
                 // the remaining matches (fewer than a sub-batch) move to the
                 // queue's front; the next chunk appends after them
@@ -1849,6 +1903,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 }
                 if (tid == 0) sh->qcount = rem;
                 __syncthreads();
+                MHR_PHASE(kPhProbe);
             }
             __syncthreads();  // rows[] and sh->E are rewritten by the next batch
         }
@@ -1857,6 +1912,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         if (sh->stage_n > 0) merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
         float em = block_max<>(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
+        MHR_PHASE(kPhEnd);
         Cand *out = A.cands + static_cast<uint64_t>(tile) * KC;
         for (uint32_t i = tid; i < static_cast<uint32_t>(KC); i += kBlock) out[i] = list[i];
         if (tid == 0) {
@@ -1869,6 +1925,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             A.hdr[tile] = h;
         }
     }
+#ifdef MHR_PHASE_CLOCKS
+    __syncthreads();
+    if (threadIdx.x < kNumPhases) atomicAdd(&g_phase_ticks[threadIdx.x], ph_acc[threadIdx.x]);
+#endif
 }
 // ---------------------------------------------------------------------------
 // merge
@@ -2562,4 +2622,38 @@ extern "C" mhr_status mhr_topk_paths_noalloc(const mhr_graph *g, const mhr_query
     if (!ws) return MHR_ERR_DEVICE;
     return topk_impl(g, o, nq, src, dst, k, kmax, out, out_count, out_total, out_status, ws,
                      MHR_NOALLOC_SCRATCH_BYTES, stream, nullptr, nullptr, nullptr);
+}
+
+// Phase clocks of the gather kernel (see GatherPhase): copies the summed
+// per-workgroup wall-clock ticks of every phase since the last reset to out
+// (host, n entries), the clock's rate in Hz to *rate_hz, and resets them if
+// reset != 0.  Synchronises the device.  Only a build with MHR_PHASE_CLOCKS
+// records them; other builds return MHR_ERR_UNSUPPORTED.
+extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *rate_hz, int reset) {
+#ifdef MHR_PHASE_CLOCKS
+    MHR_ARG_CHECK(out != nullptr && n >= static_cast<uint32_t>(kNumPhases), "mhr_debug_phase_ticks: bad output");
+    MHR_HIP_TRY(hipDeviceSynchronize());
+    unsigned long long h[kNumPhases];
+    MHR_HIP_TRY(hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase_ticks), sizeof(h)));
+    for (int i = 0; i < kNumPhases; ++i) out[i] = h[i];
+    if (rate_hz) {
+        int dev = 0, khz = 0;
+        MHR_HIP_TRY(hipGetDevice(&dev));
+        MHR_HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        *rate_hz = 1e3 * static_cast<double>(khz);
+    }
+    if (reset) {
+        const unsigned long long z[kNumPhases] = {};
+        MHR_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), z, sizeof(z)));
+        MHR_HIP_TRY(hipDeviceSynchronize());
+    }
+    return MHR_OK;
+#else
+    (void)out;
+    (void)n;
+    (void)rate_hz;
+    (void)reset;
+    set_error("this build records no phase clocks (build with MHR_PHASE_CLOCKS)");
+    return MHR_ERR_UNSUPPORTED;
+#endif
 }
