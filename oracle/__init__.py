@@ -41,6 +41,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mhr_oracle.c")
 _LIB = os.path.join(_HERE, "libmhr_oracle.so")
 
+MAX_HOPS = 8
+BEAM_DTYPE = np.dtype([("s", np.float64), ("len", np.uint32), ("v", np.uint32, (MAX_HOPS,)),
+                       ("r", np.uint32, (MAX_HOPS,))], align=True)
+
 PATH_DTYPE = np.dtype([("s", np.float64), ("a", np.uint32), ("b", np.uint32),
                        ("r1", np.uint32), ("r2", np.uint32), ("r3", np.uint32)],
                       align=True)
@@ -83,6 +87,8 @@ def _load():
         lib.og_topk.restype = ctypes.c_int
         lib.og_topk.argtypes = [vp, u32, vp, vp, u32, vp, vp, vp, u32, ctypes.c_int,
                                 vp, vp, vp]
+        lib.og_beam.restype = ctypes.c_int
+        lib.og_beam.argtypes = [vp, ctypes.c_int, ctypes.c_double, u32, vp, vp, u32, vp, vp, u32, u32, vp, vp, vp]
         lib.og_scan_topk.restype = ctypes.c_int
         lib.og_scan_topk.argtypes = [u32, vp, vp, u32, vp, vp, vp, u32, u32, ctypes.c_double, vp, vp]
         lib.og_max_threads.restype = ctypes.c_int
@@ -151,6 +157,26 @@ class Graph:
         r = np.empty(self.m, np.uint32)
         _load().og_graph_export(self._g, _ptr(rp), _ptr(t), _ptr(r))
         return rp, t, r
+
+    def beam(self, X, Y, src, dst, H, K, scorer: str = "distmult", gamma: float = 1.0):
+        """The generic multi-hop search of section 5 (level-by-level
+        expansion, cycles excluded, paths to the target recorded as found,
+        the best K children of each parent passed on): per query the best K
+        recorded paths of at most H edges.  Returns (paths [nq][K] of
+        BEAM_DTYPE, count [nq], recorded [nq])."""
+        X = np.ascontiguousarray(X, np.float32)
+        Y = np.ascontiguousarray(Y, np.float32)
+        src = np.ascontiguousarray(src, np.uint32)
+        dst = np.ascontiguousarray(dst, np.uint32)
+        nq = len(src)
+        out = np.zeros((nq, K), BEAM_DTYPE)
+        cnt = np.zeros(nq, np.uint32)
+        rec = np.zeros(nq, np.uint64)
+        rc = _load().og_beam(self._g, _scorer(scorer), float(gamma), X.shape[1], _ptr(X), _ptr(Y), nq, _ptr(src),
+                             _ptr(dst), int(H), int(K), _ptr(out), _ptr(cnt), _ptr(rec))
+        if rc != 0:
+            raise ValueError("oracle beam search failed (bad argument or out of memory)")
+        return out, cnt, rec
 
     def edge_weights(self, X, Y, u, r, v, scorer: str = "distmult", gamma: float = 1.0):
         """(x, w) of arbitrary edges: the scorer's raw value (DistMult score

@@ -415,3 +415,122 @@ int og_scan_topk(uint32_t d, const float *X, const float *Y, uint32_t nq,
     }
     return fail ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Generic multi-hop search (section 5: the level-by-level expansion   */
+/* with a per-parent top-K, paths to the target recorded as found)     */
+/* ------------------------------------------------------------------ */
+
+#define OG_MAX_HOPS 8
+
+typedef struct {
+    double s;
+    uint32_t len;                   /* edges */
+    uint32_t v[OG_MAX_HOPS];        /* v[0..len): the vertices after the source */
+    uint32_t r[OG_MAX_HOPS];
+} og_bpath;
+
+/* Score descending, then the vertex sequence lexicographically (a proper
+ * prefix first), then the relation sequence. */
+static int cmp_bpath(const og_bpath *p, const og_bpath *q)
+{
+    if (p->s != q->s) return p->s > q->s ? -1 : 1;
+    uint32_t n = p->len < q->len ? p->len : q->len;
+    for (uint32_t i = 0; i < n; ++i)
+        if (p->v[i] != q->v[i]) return p->v[i] < q->v[i] ? -1 : 1;
+    if (p->len != q->len) return p->len < q->len ? -1 : 1;
+    for (uint32_t i = 0; i < p->len; ++i)
+        if (p->r[i] != q->r[i]) return p->r[i] < q->r[i] ? -1 : 1;
+    return 0;
+}
+
+static int cmp_bpath_q(const void *x, const void *y)
+{
+    return cmp_bpath((const og_bpath *)x, (const og_bpath *)y);
+}
+
+typedef struct { og_bpath *p; uint64_t n, cap; int oom; } og_bvec;
+
+static void bvec_push(og_bvec *v, const og_bpath *x)
+{
+    if (v->oom) return;
+    if (v->n == v->cap) {
+        uint64_t nc = v->cap ? v->cap * 2 : 64;
+        og_bpath *np = (og_bpath *)realloc(v->p, nc * sizeof(og_bpath));
+        if (!np) { v->oom = 1; return; }
+        v->p = np; v->cap = nc;
+    }
+    v->p[v->n++] = *x;
+}
+
+/* One query of the generic search.  A path starts as the source alone with
+ * score 0.  At each of the H levels every current path is extended by every
+ * out-edge (horizon, r, nb) of its last vertex whose head nb is not on the
+ * path yet; the extension's score is the path's score plus w(horizon, r, nb)
+ * (scores add along the path).  An extension that reaches the target is
+ * recorded as a result and not extended further; of the others, each parent
+ * passes its best K (under the order above) to the next level.  The result
+ * is the best K recorded paths.  Returns the number recorded, or UINT64_MAX
+ * on allocation failure. */
+static uint64_t og_beam_query(const og_graph *g, og_scorer sc, uint32_t d, const float *X, const float *Y,
+                              uint32_t s, uint32_t t, uint32_t H, uint32_t K, og_bpath *out, uint32_t *count)
+{
+    og_bvec curr = {0}, next = {0}, res = {0}, kids = {0};
+    og_bpath root;
+    memset(&root, 0, sizeof(root));
+    bvec_push(&curr, &root);
+    for (uint32_t level = 0; level < H; ++level) {
+        next.n = 0;
+        for (uint64_t pi = 0; pi < curr.n; ++pi) {
+            const og_bpath *par = &curr.p[pi];
+            uint32_t h = par->len ? par->v[par->len - 1] : s;
+            kids.n = 0;
+            for (uint64_t e = g->rowptr[h]; e < g->rowptr[h + 1]; ++e) {
+                uint32_t nb = g->tail[e], r = g->rel[e];
+                int on_path = nb == s;
+                for (uint32_t i = 0; i < par->len; ++i) on_path |= par->v[i] == nb;
+                if (on_path) continue;
+                og_bpath x = *par;
+                x.v[x.len] = nb;
+                x.r[x.len] = r;
+                x.len += 1;
+                x.s = par->s + og_edge_weight(sc, d, X, Y, h, r, nb);
+                if (nb == t) bvec_push(&res, &x);
+                else bvec_push(&kids, &x);
+            }
+            if (kids.n) qsort(kids.p, kids.n, sizeof(og_bpath), cmp_bpath_q);
+            for (uint64_t i = 0; i < kids.n && i < K; ++i) bvec_push(&next, &kids.p[i]);
+        }
+        og_bvec tmp = curr; curr = next; next = tmp;
+    }
+    uint64_t total = res.n;
+    int oom = curr.oom | next.oom | res.oom | kids.oom;
+    if (!oom && res.n) qsort(res.p, res.n, sizeof(og_bpath), cmp_bpath_q);
+    uint32_t keep = (uint32_t)(res.n < K ? res.n : K);
+    if (!oom && keep) memcpy(out, res.p, keep * sizeof(og_bpath));
+    *count = oom ? 0 : keep;
+    free(curr.p); free(next.p); free(res.p); free(kids.p);
+    return oom ? UINT64_MAX : total;
+}
+
+/* Batch of queries (OpenMP over queries).  H in 1..OG_MAX_HOPS.  out holds
+ * nq * K paths.  Returns 0, or -1 on a bad argument or allocation failure. */
+int og_beam(const og_graph *g, int scorer, double gamma, uint32_t d, const float *X, const float *Y,
+            uint32_t nq, const uint32_t *src, const uint32_t *dst, uint32_t H, uint32_t K,
+            og_bpath *out, uint32_t *out_count, uint64_t *out_recorded)
+{
+    if (H < 1 || H > OG_MAX_HOPS || K < 1) return -1;
+    for (uint32_t q = 0; q < nq; ++q)
+        if (src[q] >= g->n || dst[q] >= g->n) return -1;
+    og_scorer sc = {scorer, gamma};
+    int fail = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < (int64_t)nq; ++q) {
+        uint64_t tot = og_beam_query(g, sc, d, X, Y, src[q], dst[q], H, K, out + (size_t)q * K, &out_count[q]);
+        if (tot == UINT64_MAX) fail = 1;
+        out_recorded[q] = tot;
+    }
+    return fail ? -1 : 0;
+}

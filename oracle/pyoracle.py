@@ -62,3 +62,36 @@ def topk_paths(edges, X, Y, s, t, K, keep_first=None, keep_last=None, scorer="di
                 paths.append((math.fsum((w1, w2, w3)), a, b, r1, r2, r3))
     paths.sort(key=lambda p: (-p[0], p[1], p[2], p[3], p[4], p[5]))
     return paths[:K], len(paths)
+
+
+def beam_paths(edges, X, Y, s, t, H, K, scorer="distmult", gamma=1.0):
+    """The generic multi-hop search of section 5 in plain Python: level by
+    level, every current path grows by each out-edge whose head is not on
+    it; extensions reaching t are recorded, the others keep the best K per
+    parent (score descending, then the vertex sequence, then the relation
+    sequence).  Returns (best K recorded paths as (S, vertices, relations),
+    number recorded)."""
+    out = defaultdict(list)
+    for (h, r, v) in sorted(set((int(h), int(r), int(v)) for (h, r, v) in edges)):
+        out[h].append((v, r))
+
+    def key(p):
+        return (-p[0], list(p[1]), list(p[2]))
+
+    curr = [(0.0, (), ())]
+    results = []
+    for _ in range(H):
+        nxt = []
+        for score, vs, rs in curr:
+            h = vs[-1] if vs else s
+            kids = []
+            for (nb, r) in out[h]:
+                if nb == s or nb in vs:
+                    continue
+                x = (score + edge_weight(X, Y, h, r, nb, scorer, gamma), vs + (nb,), rs + (r,))
+                (results if nb == t else kids).append(x)
+            kids.sort(key=key)
+            nxt.extend(kids[:K])
+        curr = nxt
+    results.sort(key=key)
+    return results[:K], len(results)
