@@ -287,6 +287,17 @@ def bf16_bits_to_f32(h: np.ndarray) -> np.ndarray:
     return (h.astype(np.uint32) << 16).view(np.float32)
 
 
+def grid_values(rng, shape, levels: int, exp: int, density: float = 1.0) -> np.ndarray:
+    """Integers drawn uniformly from [-levels, levels] times 2^exp (zeroed
+    with probability 1 - density), as float64: values exactly representable
+    in bfloat16 for levels <= 256, so that sums of their products stay on a
+    known power-of-two grid."""
+    v = rng.integers(-levels, levels + 1, shape).astype(np.float64)
+    if density < 1.0:
+        v *= rng.random(shape) < density
+    return np.ldexp(v, exp)
+
+
 def embeddings(n: int, R: int, spec: EmbSpec, chunk_rows: int = 1 << 16):
     """Entity table X[n][d] and relation table Y[R][d], entries drawn from a
     normal law with variance 1/d in float64 and rounded to the storage type.

@@ -164,3 +164,180 @@ def keep_top_fraction(scores, permille):
     m = keep_count(n, permille)
     thr = np.sort(scores)[::-1][m - 1]
     return np.nonzero(scores >= thr)[0]
+
+
+# ---------------------------------------------------------------------------
+# Element-wise error bounds for a computation that follows the formulas above
+# with bfloat16-rounded operands and FP32 accumulation in any order (as the
+# GPU kernels do).  Each quantity travels with a bound e on |x_gpu - x|,
+# where x is the FP64 value of forward / backward with bf16=True:
+#   product C = A B (inner length k), |A' - A| <= eA, |B' - B| <= eB:
+#     |C' - C| <= |A| eB + eA |B| + eA eB + gamma_k (|A| + eA)(|B| + eB)
+#     (gamma_k = k u / (1 - k u), u = 2^-24, bounds any summation order)
+#   bfloat16 rounding to nearest of x' vs of x: rounding is monotone, so
+#     rnd(x') lies between rnd(x - e) and rnd(x + e)
+#   relu is 1-Lipschitz; a 0/1 mask (x > 0) is certain only where |x| > e,
+#   elsewhere the masked value may be kept or dropped.
+#   exact sums: where both operands are known exactly and every term
+#     A_ij B_jk (and the added bias) is a multiple of one power of two q
+#     with sum |terms| < 2^24 q, every partial sum in any order is a
+#     multiple of q below 2^24 q in magnitude, hence an FP32 number: the
+#     product is computed without rounding and its bound is zero.
+# ---------------------------------------------------------------------------
+
+U32 = 2.0 ** -24
+
+
+def gamma(k):
+    return k * U32 / (1.0 - k * U32)
+
+
+def quantum(x):
+    """Largest power of two dividing each element of x (float64 holding
+    FP32 values); +inf for zeros."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)
+    M = np.abs(m * 2.0 ** 53).astype(np.int64)
+    low = (M & -M).astype(np.float64)
+    with np.errstate(divide="ignore"):
+        q = np.ldexp(low, e - 53)
+    return np.where(x == 0, np.inf, q)
+
+
+def _exact_mask(A, eA, B, eB, S, bias=None):
+    """True where the product element (i, k) is provably exact: row i of A
+    and column k of B (and the bias) are exact and S_ik < 2^24 q_ik, S the
+    sum of the terms' magnitudes and q_ik the smallest quantum among the
+    terms, bounded below by qA_i qB_k (q the smallest quantum of the row /
+    column) and the bias's own quantum."""
+    qa = quantum(A).min(axis=1)
+    qb = quantum(B).min(axis=0)
+    exact_rows = ~np.any(eA != 0, axis=1)
+    exact_cols = ~np.any(eB != 0, axis=0)
+    with np.errstate(invalid="ignore", over="ignore"):
+        q = np.outer(qa, qb)
+        if bias is not None:
+            q = np.minimum(q, quantum(bias)[None, :])
+        ok = (S < 2.0 ** 24 * q) | (S == 0)
+    return ok & exact_rows[:, None] & exact_cols[None, :]
+
+
+def _prod_err(A, eA, B, eB, k, bias=None):
+    """Bound on |C' - C| for C = A B (+ bias per column, exact), k terms
+    per element in any order (one more with a bias)."""
+    aA, aB = np.abs(A), np.abs(B)
+    S = aA @ aB
+    err = aA @ eB + eA @ aB + eA @ eB
+    if bias is not None:
+        bias = np.asarray(bias, dtype=np.float64).reshape(-1)
+        err = err + gamma(k) * ((aA + eA) @ (aB + eB) + np.abs(bias)[None, :])
+        S = S + np.abs(bias)[None, :]
+    else:
+        err = err + gamma(k) * ((aA + eA) @ (aB + eB))
+    return np.where(_exact_mask(A, eA, B, eB, S, bias), 0.0, err)
+
+
+def _rnd_err(x, e):
+    """Bound on |rnd(x') - rnd(x)| for |x' - x| <= e: rounding to nearest is
+    monotone, so rnd(x') lies between rnd(x - e) and rnd(x + e) (zero when
+    no rounding boundary falls within the interval)."""
+    r = round_bf16(x)
+    return np.maximum(round_bf16(x + e) - r, r - round_bf16(x - e))
+
+
+def forward_bounds(theta, F, d, H):
+    """(z, bound on |z_gpu - z|, cache with per-quantity bounds) for the
+    bfloat16-operand forward pass; FP32 parameters as held on the device
+    (theta exactly representable in FP32)."""
+    z, c = forward(theta, F, d, H, bf16=True)
+    W1, b1, W2, b2, w3, b3 = unpack(theta, d, H)
+    zero = lambda a: np.zeros_like(a)
+    # the features and weights are rounded from exact inputs: no error
+    e_z1 = _prod_err(c["F"], zero(c["F"]), c["W1"].T, zero(c["W1"].T), 4 * d + 1, bias=b1)
+    e_h1 = _rnd_err(np.maximum(c["z1"], 0.0), e_z1)
+    e_z2 = _prod_err(c["h1"], e_h1, c["W2"].T, zero(c["W2"].T), H + 1, bias=b2)
+    e_h2 = _rnd_err(np.maximum(c["z2"], 0.0), e_z2)
+    e_z = _prod_err(c["h2"], e_h2, c["w3"][:, None], zero(c["w3"][:, None]), H + 1, bias=b3)[:, 0]
+    c.update(e_z1=e_z1, e_h1=e_h1, e_z2=e_z2, e_h2=e_h2)
+    return z, e_z, c
+
+
+def backward_bounds(theta, cache, z, e_z, y, w_pos, d, H):
+    """(gradient, element-wise bound) for the bfloat16-operand backward
+    pass from the logits' bounds e_z (BCE with sigmoid: dL/dz is 1/4-
+    Lipschitz in z per sample, scaled by the weight and 1/N, plus the FP32
+    evaluation's few roundings)."""
+    N = len(z)
+    g = backward(theta, cache, bce_grad(z, y, w_pos), d, H, bf16=True)
+    dz = bce_grad(z, y, w_pos)
+    wmax = np.where(np.asarray(y) > 0, w_pos, 1.0)
+    e_dz = 0.25 * wmax * e_z / N + 8 * U32 * np.abs(dz) + 1e-45
+    h1, h2, z1, z2 = cache["h1"], cache["h2"], cache["z1"], cache["z2"]
+    e_h1, e_h2, e_z1, e_z2 = cache["e_h1"], cache["e_h2"], cache["e_z1"], cache["e_z2"]
+    w3, W2, F = cache["w3"], cache["W2"], cache["F"]
+    # output layer: g_w3 = h2^T dz, g_b3 = sum dz
+    e_gw3 = _prod_err(h2.T, e_h2.T, dz[:, None], e_dz[:, None], N + 1)[:, 0]
+    e_gb3 = np.array([e_dz.sum() + gamma(N) * np.abs(dz).sum()])
+    # dz2 = bf16(dz w3^T * [z2 > 0])
+    pre2 = np.outer(dz, w3)
+    e_pre2 = np.outer(e_dz, np.abs(w3)) + gamma(1) * np.abs(pre2)
+    m2 = z2 > 0
+    unsure2 = (e_z2 > 0) & (np.abs(z2) <= e_z2)   # an exact z2 decides its mask
+    dz2 = round_bf16(pre2 * m2)
+    e_dz2 = np.where(unsure2, np.abs(pre2) + e_pre2, _rnd_err(pre2 * m2, e_pre2 * m2))
+    e_gW2 = _prod_err(dz2.T, e_dz2.T, h1, e_h1, N + 1)
+    e_gb2 = e_dz2.sum(0) + gamma(N) * np.abs(dz2).sum(0)
+    # dz1 = bf16((dz2 W2) * [z1 > 0])
+    pre1 = dz2 @ W2
+    e_pre1 = _prod_err(dz2, e_dz2, W2, np.zeros_like(W2), H + 1)
+    m1 = z1 > 0
+    unsure1 = (e_z1 > 0) & (np.abs(z1) <= e_z1)
+    dz1 = round_bf16(pre1 * m1)
+    e_dz1 = np.where(unsure1, np.abs(pre1) + e_pre1, _rnd_err(pre1 * m1, e_pre1 * m1))
+    e_gW1 = _prod_err(dz1.T, e_dz1.T, F, np.zeros_like(F), N + 1)
+    e_gb1 = e_dz1.sum(0) + gamma(N) * np.abs(dz1).sum(0)
+    return g, pack(e_gW1, e_gb1, e_gW2, e_gb2, e_gw3, e_gb3)
+
+
+def adam_interval(theta, g, e_g, m, v, step, lr, beta1, beta2, eps):
+    """Element-wise intervals (lo, hi) for the parameters, first and second
+    moments after one Adam step evaluated in FP32 from exact FP32 state
+    (theta, m, v, step) and constants, whose gradient lies within e_g of g.
+
+    Every quantity is bounded by interval arithmetic: the moments are
+    monotone in g (the second through g^2), and the step r = m_hat /
+    (sqrt(v_hat) + eps) is increasing in m_hat and, for a fixed sign of
+    m_hat, decreasing in |.| with v_hat.  FP32 evaluation is allowed a
+    relative error of 4u per moment update, 8u per bias correction term
+    1 - beta^t (pow within 4 ulp, then one subtraction, relative to the
+    difference), 4u for the square root and eps, 4u for the step's
+    products and quotient and u for the final subtraction (u = 2^-24)."""
+    u = U32
+    g = np.asarray(g, dtype=np.float64)
+    glo, ghi = g - e_g, g + e_g
+    m1lo = beta1 * m + (1 - beta1) * glo
+    m1hi = beta1 * m + (1 - beta1) * ghi
+    am = 4 * u * (np.abs(beta1 * m) + (1 - beta1) * np.maximum(np.abs(glo), np.abs(ghi)))
+    m1lo, m1hi = m1lo - am, m1hi + am
+    g2hi = np.maximum(glo * glo, ghi * ghi)
+    g2lo = np.where((glo <= 0) & (ghi >= 0), 0.0, np.minimum(glo * glo, ghi * ghi))
+    v1lo = beta2 * v + (1 - beta2) * g2lo
+    v1hi = beta2 * v + (1 - beta2) * g2hi
+    av = 4 * u * (np.abs(beta2 * v) + (1 - beta2) * g2hi)
+    v1lo, v1hi = np.maximum(v1lo - av, 0.0), v1hi + av
+    p1, p2 = beta1 ** step, beta2 ** step
+    bc1, bc2 = 1 - p1, 1 - p2
+    r1 = (8 * u * p1 + u) / bc1 + u      # relative error of the FP32 bias corrections
+    r2 = (8 * u * p2 + u) / bc2 + u
+    mh = np.stack([m1lo / (bc1 * (1 + r1)), m1lo / (bc1 * (1 - r1)),
+                   m1hi / (bc1 * (1 + r1)), m1hi / (bc1 * (1 - r1))])
+    mhlo, mhhi = mh.min(0), mh.max(0)
+    dlo = np.sqrt(v1lo / (bc2 * (1 + r2))) * (1 - 4 * u) + eps * (1 - u)
+    dhi = np.sqrt(v1hi / (bc2 * (1 - r2))) * (1 + 4 * u) + eps * (1 + u)
+    rr = np.stack([mhlo / dlo, mhlo / dhi, mhhi / dlo, mhhi / dhi])
+    rlo, rhi = rr.min(0), rr.max(0)
+    rlo = rlo - 4 * u * np.abs(rlo)
+    rhi = rhi + 4 * u * np.abs(rhi)
+    tlo, thi = theta - lr * rhi, theta - lr * rlo
+    at = u * np.maximum(np.abs(tlo), np.abs(thi))
+    return (tlo - at, thi + at), (m1lo, m1hi), (v1lo, v1hi)
