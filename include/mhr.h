@@ -57,7 +57,10 @@ typedef enum mhr_status {
     MHR_ERR_DEVICE = 5,
     MHR_ERR_NO_EMBEDDINGS = 6,
     MHR_ERR_BAD_EDGE = 7,
-    MHR_ERR_INTERNAL = 8          /* an internal consistency check failed */
+    MHR_ERR_INTERNAL = 8,         /* an internal consistency check failed */
+    MHR_ERR_IO = 9,               /* a file could not be read or written */
+    MHR_ERR_CORRUPT = 10,         /* a file failed its format or checksum checks */
+    MHR_ERR_NOT_FOUND = 11        /* no matching record (tuning cache) */
 } mhr_status;
 
 typedef enum mhr_dtype {
@@ -302,6 +305,24 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
                         void *workspace, size_t ws_bytes, void *stream, uint32_t reps,
                         mhr_query_opts *tuned, float *best_ms);
 
+/* Tuning cache: the autotuner's chosen settings (tile_edges, hash_log2,
+ * grid_blocks) and time per call, keyed by the device architecture name,
+ * the graph's vertices, relations and distinct pairs, the embedding
+ * dimension and dtype, the scorer, the batch size nq and k_max.  The file is
+ * a sequence of 96-byte records, each with its own CRC-32; save replaces the
+ * record of the same key (or appends one) and rewrites the file atomically,
+ * refusing to touch a damaged file (CORRUPT).  load fills *tuned (other
+ * fields zero) and *ms (may be NULL), or returns NOT_FOUND.  Errors:
+ * INVALID_ARGUMENT, IO, CORRUPT, NOT_FOUND, DEVICE. */
+mhr_status mhr_tuning_save(const char *path, const mhr_graph *g, uint32_t nq, uint32_t k_max,
+                           const mhr_query_opts *tuned, float ms);
+mhr_status mhr_tuning_load(const char *path, const mhr_graph *g, uint32_t nq, uint32_t k_max,
+                           mhr_query_opts *tuned, float *ms);
+
+/* Checks a tuning cache on the host alone and counts its records.  Errors:
+ * IO, CORRUPT. */
+mhr_status mhr_tuning_file_records(const char *path, uint32_t *count);
+
 /* ---------------------------------------------------------------------------
  * Learned frontier pruner.
  *
@@ -327,6 +348,28 @@ mhr_status mhr_autotune(const mhr_graph *g, const mhr_query_opts *base, uint32_t
 typedef struct mhr_pruner mhr_pruner;
 
 #define MHR_PRUNER_HOP2 0x80000000u   /* second-hop flag in a sample's or candidate's query word */
+
+/* Checkpoint of a pruner: parameters, Adam moments and step count, to
+ * resume training or reuse a trained network.  Little-endian file: a 40-byte
+ * header ("MHRPRUN1", format version, dim, hidden, step, parameter count,
+ * CRC-32 of the payload, CRC-32 of the header) and the payload (FP32
+ * parameters, first moments, second moments).  save synchronises `stream`
+ * and writes the file atomically (temporary name, then rename).  load
+ * checks the magic, version, sizes and both checksums before anything is
+ * copied, requires the pruner's dim and hidden, restores the step count and
+ * synchronises.  Errors: INVALID_ARGUMENT, IO, CORRUPT, UNSUPPORTED (another
+ * format version), DEVICE. */
+mhr_status mhr_pruner_save(const mhr_pruner *p, const char *path, void *stream);
+mhr_status mhr_pruner_load(mhr_pruner *p, const char *path, void *stream);
+
+/* Checks a pruner checkpoint on the host alone (no device needed) and
+ * reports its dimensions and step count (each output may be NULL).
+ * Errors: IO, CORRUPT, UNSUPPORTED. */
+mhr_status mhr_pruner_file_info(const char *path, uint32_t *dim, uint32_t *hidden, uint32_t *step);
+
+/* CRC-32 (IEEE 802.3 polynomial, reflected 0xEDB88320, the zlib / PNG
+ * checksum) of n bytes, continuing from crc (0 to start). */
+uint32_t mhr_crc32(uint32_t crc, const void *data, size_t n);
 
 /* Number of parameters for embedding dimension dim and hidden width hidden. */
 size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden);
@@ -365,6 +408,37 @@ mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, uint32_t n, 
                                  const uint32_t *r, const float *label, float pos_weight, float lr,
                                  float beta1, float beta2, float eps, int update, float *loss,
                                  void *ws, size_t ws_bytes, void *stream);
+
+/* A whole training run on nq training queries (src, dst: device uint32[nq]),
+ * the sequence of the calls above:
+ *   per epoch, the queries in a shuffled order (SplitMix64-driven
+ *   Fisher-Yates from seed), in batches of batch_queries; per batch the
+ *   exact top-k labels the candidates (mhr_topk_paths, mhr_pruner_count /
+ *   enumerate / label), every positive and about neg_per_hop negatives per
+ *   hop and query are sampled (mhr_pruner_sample), and the network takes
+ *   Adam steps of step_samples samples each with a positive weight of
+ *   negatives / positives (mhr_pruner_train_step).
+ * The loss of each step is written to losses[0 .. min(steps, max_losses))
+ * (host), the step count to *nsteps (host).  Allocates its device buffers
+ * (hipMalloc) and frees them before returning; synchronises `stream` once or
+ * twice per batch to size them.  Zero option fields take the defaults in
+ * the comments; reserved fields must be zero.  Errors: those of the calls
+ * above, INVALID_ARGUMENT, DEVICE. */
+typedef struct mhr_train_opts {
+    uint32_t k;              /* K of the labelling search (1 .. MHR_MAX_K), e.g. 32 */
+    uint32_t batch_queries;  /* 0 = 4096 */
+    uint32_t step_samples;   /* 0 = 65536 */
+    uint32_t epochs;         /* 0 = 1 */
+    uint32_t neg_per_hop;    /* 0 = 64 */
+    float lr, beta1, beta2, eps;   /* 0 = 1e-3, 0.9, 0.999, 1e-8 */
+    uint32_t pad;
+    uint64_t seed;
+    uint32_t reserved[8];
+} mhr_train_opts;
+
+mhr_status mhr_pruner_train(mhr_pruner *p, const mhr_graph *g, const mhr_train_opts *opts, uint32_t nq,
+                            const uint32_t *src, const uint32_t *dst, float *losses, uint32_t max_losses,
+                            uint32_t *nsteps, void *stream);
 
 /* Candidate bookkeeping for nq queries (device arrays).  entry_off and
  * cand_off receive [nq + 1] exclusive offsets: entries are the keep-flag
@@ -432,6 +506,17 @@ mhr_status mhr_pruner_fallback(uint32_t nq, const uint32_t *src, const uint32_t 
                                const float *mass, float tau, uint32_t *fb_src, uint32_t *fb_dst,
                                uint32_t *fb_k, uint32_t *fb_idx, uint32_t *nfb, void *stream);
 
+/* The weight of each candidate's own edge under the graph's scorer, in FP32
+ * as the search's fast pass evaluates it: s -r-> v for a first-hop
+ * candidate of query q, v -r-> t for a second-hop one (query words with
+ * MHR_PRUNER_HOP2, as mhr_pruner_enumerate writes them).  This is the
+ * ranking a per-level score beam keeps (the paper's generic search bounds
+ * each level by the best partial scores, section 5): the pruner's
+ * no-network baseline.  Device arrays of ncand entries. */
+mhr_status mhr_pruner_candidate_weights(const mhr_graph *g, uint64_t ncand, const uint32_t *src,
+                                        const uint32_t *dst, const uint32_t *cand_q, const uint32_t *cand_v,
+                                        const uint32_t *cand_r, float *w, void *stream);
+
 /* Copies result row i of a compact batch (paths[i][0..kmax), count, total,
  * status) to row idx[i] of a full batch, for i < n (host count). */
 mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint32_t kmax, const mhr_path *src_paths,
@@ -448,6 +533,43 @@ mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint32_t kmax, c
 mhr_status mhr_edge_weights(const mhr_graph *g, uint64_t ne, const uint32_t *u,
                             const uint32_t *r, const uint32_t *v, float *w_f32,
                             float *err_f32, float *w_hi, float *w_lo, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Generic multi-hop search (section 5, the generic algorithm and its path
+ * expansion): a beam search of up to `hops` edges, the per-parent top-K of
+ * the paper's level-by-level frontier.  Unlike mhr_topk_paths it is not
+ * exact over all paths: it keeps K children per path and level.
+ * ------------------------------------------------------------------------- */
+#define MHR_BEAM_MAX_HOPS 4
+
+/* One recorded path s -r[0]-> v[0] -r[1]-> ... -> v[len-1] = t (40 bytes);
+ * unused slots hold len 0, vertices 0xFFFFFFFF and score -inf. */
+typedef struct mhr_beam_path {
+    double score;                     /* the edge weights summed along the path, FP64 */
+    uint32_t len;                     /* edges, 1 .. hops */
+    uint32_t v[MHR_BEAM_MAX_HOPS];
+    uint16_t r[MHR_BEAM_MAX_HOPS];
+} mhr_beam_path;
+
+/* Workspace bytes of mhr_beam_search (it grows as nq * k^(hops-1)). */
+mhr_status mhr_beam_workspace_size(const mhr_graph *g, uint32_t nq, uint32_t hops, uint32_t k, size_t *bytes);
+
+/* For each query (src[q], dst[q]): start from the path holding s alone; at
+ * each of `hops` levels every current path grows by each typed out-edge
+ * (h, r, nb) of its last vertex h whose head nb is not on the path yet, its
+ * score plus w(h, r, nb) (the graph's scorer, FP64); an extension reaching t
+ * is recorded and not grown further; of the others each parent passes its
+ * best k (score descending, then nb, then r ascending) to the next level.
+ * out[q][0 .. out_count[q]) holds the best k recorded paths (score
+ * descending, then the vertex sequence lexicographically with a proper
+ * prefix first, then the relation sequence); out_recorded[q] (may be NULL)
+ * the number recorded.  hops 1..MHR_BEAM_MAX_HOPS, k 1..64, k^(hops-1) <=
+ * 2^20.  Asynchronous on `stream` (one launch per level); allocates
+ * nothing.  Errors: INVALID_ARGUMENT, NO_EMBEDDINGS, WORKSPACE_TOO_SMALL,
+ * DEVICE. */
+mhr_status mhr_beam_search(const mhr_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                           uint32_t hops, uint32_t k, mhr_beam_path *out, uint32_t *out_count,
+                           uint64_t *out_recorded, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Candidate scan: the workload of the paper's three-hop award pipeline

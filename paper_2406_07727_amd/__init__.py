@@ -34,6 +34,7 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 MHR_OK = 0
+ERR_IO, ERR_CORRUPT, ERR_NOT_FOUND = 9, 10, 11
 MHR_MAX_K = 224
 NOALLOC_SCRATCH_BYTES = 64 << 20
 Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS, Q_OVERFLOW = 1, 2, 4, 8
@@ -45,6 +46,10 @@ PATH_DTYPE = np.dtype([("a", np.uint32), ("b", np.uint32), ("r1", np.uint16), ("
                        ("r3", np.uint16), ("flags", np.uint16), ("score", np.float32),
                        ("err_bound", np.float32)])
 assert PATH_DTYPE.itemsize == 24
+BEAM_MAX_HOPS = 4
+BEAM_DTYPE = np.dtype([("score", np.float64), ("len", np.uint32), ("v", np.uint32, (BEAM_MAX_HOPS,)),
+                       ("r", np.uint16, (BEAM_MAX_HOPS,)), ("pad", np.uint32)])
+assert BEAM_DTYPE.itemsize == 40
 
 
 class _GraphDesc(ctypes.Structure):
@@ -66,6 +71,14 @@ class PhaseEvents(ctypes.Structure):
     """hipEvent_t handles recorded around the phases of one query call."""
     _fields_ = [("begin", ctypes.c_void_p), ("gather_begin", ctypes.c_void_p),
                 ("gather_end", ctypes.c_void_p), ("end", ctypes.c_void_p)]
+
+
+class TrainOpts(ctypes.Structure):
+    """mhr_train_opts (zero fields take the library's defaults)."""
+    _fields_ = [("k", ctypes.c_uint32), ("batch_queries", ctypes.c_uint32), ("step_samples", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("neg_per_hop", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("pad", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 8)]
 
 
 class QueryOpts(ctypes.Structure):
@@ -131,6 +144,11 @@ _lib.mhr_pruner_train_step.restype = _i
 _lib.mhr_pruner_train_step.argtypes = [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_float, _i, _vp, _vp, ctypes.c_size_t,
                                        _vp]
+_lib.mhr_pruner_train.restype = _i
+_lib.mhr_pruner_train.argtypes = [_vp, _vp, ctypes.POINTER(TrainOpts), _u32, _vp, _vp, _vp, _u32,
+                                  ctypes.POINTER(_u32), _vp]
+_lib.mhr_pruner_candidate_weights.restype = _i
+_lib.mhr_pruner_candidate_weights.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_pruner_count.restype = _i
 _lib.mhr_pruner_count.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp]
 _lib.mhr_pruner_enumerate.restype = _i
@@ -150,6 +168,10 @@ _lib.mhr_pruner_fallback.argtypes = [_u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, c
                                      _vp, _vp]
 _lib.mhr_scatter_results.restype = _i
 _lib.mhr_scatter_results.argtypes = [_u32, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mhr_beam_workspace_size.restype = _i
+_lib.mhr_beam_workspace_size.argtypes = [_vp, _u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_beam_search.restype = _i
+_lib.mhr_beam_search.argtypes = [_vp, _u32, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.mhr_scan_workspace_size.restype = _i
 _lib.mhr_scan_workspace_size.argtypes = [_u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.mhr_scan_topk.restype = _i
@@ -161,6 +183,21 @@ _lib.mhr_scan_pipeline.restype = _i
 _lib.mhr_scan_pipeline.argtypes = [_i, _u32, _vp, _vp, _u32, _u32, _u32, _vp, _vp, _u32, _u32, _u32, _vp, _u32, _vp,
                                    _u32, _u32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                    _vp]
+_cp = ctypes.c_char_p
+_lib.mhr_crc32.restype = ctypes.c_uint32
+_lib.mhr_crc32.argtypes = [ctypes.c_uint32, _vp, ctypes.c_size_t]
+_lib.mhr_pruner_file_info.restype = _i
+_lib.mhr_pruner_file_info.argtypes = [_cp, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
+_lib.mhr_pruner_save.restype = _i
+_lib.mhr_pruner_save.argtypes = [_vp, _cp, _vp]
+_lib.mhr_pruner_load.restype = _i
+_lib.mhr_pruner_load.argtypes = [_vp, _cp, _vp]
+_lib.mhr_tuning_file_records.restype = _i
+_lib.mhr_tuning_file_records.argtypes = [_cp, ctypes.POINTER(_u32)]
+_lib.mhr_tuning_save.restype = _i
+_lib.mhr_tuning_save.argtypes = [_cp, _vp, _u32, _u32, ctypes.POINTER(QueryOpts), ctypes.c_float]
+_lib.mhr_tuning_load.restype = _i
+_lib.mhr_tuning_load.argtypes = [_cp, _vp, _u32, _u32, ctypes.POINTER(QueryOpts), ctypes.POINTER(ctypes.c_float)]
 _lib.mhr_debug_phase_ticks.restype = _i
 _lib.mhr_debug_phase_ticks.argtypes = [_vp, _u32, ctypes.POINTER(ctypes.c_double), _i]
 _lib.mhr_status_string.restype = ctypes.c_char_p
@@ -414,10 +451,47 @@ class Graph:
                                  ctypes.byref(ms)), "mhr_autotune")
         return tuned, float(ms.value)
 
+    def save_tuning(self, path: str, nq: int, k_max: int, tuned: QueryOpts, ms: float):
+        """Records tuned settings for this device, graph, nq and k_max in the
+        tuning cache at path (mhr_tuning_save)."""
+        _check(_lib.mhr_tuning_save(os.fsencode(path), self._h, int(nq), int(k_max), ctypes.byref(tuned),
+                                    float(ms)), "mhr_tuning_save")
+
+    def load_tuning(self, path: str, nq: int, k_max: int):
+        """(QueryOpts, ms) from the tuning cache, or None when it holds no
+        record for this device, graph, nq and k_max."""
+        o = QueryOpts()
+        ms = ctypes.c_float()
+        st = _lib.mhr_tuning_load(os.fsencode(path), self._h, int(nq), int(k_max), ctypes.byref(o), ctypes.byref(ms))
+        if st == ERR_NOT_FOUND:
+            return None
+        _check(st, "mhr_tuning_load")
+        return o, float(ms.value)
+
     def plan(self, src, dst, k=None, k_max: Optional[int] = None, opts: Optional[QueryOpts] = None,
              stream=None) -> "Plan":
         """Captures one batched query call into a HIP graph (see Plan)."""
         return Plan(self, src, dst, k, k_max, opts, stream)
+
+    def beam(self, src, dst, hops: int, k: int, stream=None):
+        """The generic multi-hop search (mhr_beam_search): per query the best
+        k recorded paths of at most `hops` edges.  Returns (paths [nq, k]
+        uint8 records of BEAM_DTYPE, count [nq], recorded [nq]) device
+        tensors; beam_to_numpy converts them."""
+        torch = _torch()
+        s, d = _dev_u32(src), _dev_u32(dst)
+        nq = s.numel()
+        need = ctypes.c_size_t()
+        _check(_lib.mhr_beam_workspace_size(self._h, nq, int(hops), int(k), ctypes.byref(need)),
+               "mhr_beam_workspace_size")
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
+        out = torch.empty((nq, k, BEAM_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+        cnt = torch.empty(max(nq, 1), dtype=torch.int32, device="cuda")
+        rec = torch.empty(max(nq, 1), dtype=torch.int64, device="cuda")
+        _check(_lib.mhr_beam_search(self._h, nq, _ptr(s), _ptr(d), int(hops), int(k), _ptr(out), _ptr(cnt), _ptr(rec),
+                                    _ptr(ws), ws.numel(), _stream_ptr(stream)), "mhr_beam_search")
+        self._beam_keep = (s, d, ws)
+        return out, cnt[:nq], rec[:nq]
 
     def edge_weights(self, u, r, v, stream=None):
         """FP32 log-sigmoid DistMult weights with their error bounds, and the
@@ -536,6 +610,23 @@ class Pruner:
         _check(_lib.mhr_pruner_get_params(self._h, None, _ptr(t), _stream_ptr(stream)), "mhr_pruner_get_params")
         return t
 
+    def train(self, graph: "Graph", src, dst, opts: TrainOpts, max_steps: int = 1 << 20, stream=None):
+        """A whole training run (mhr_pruner_train); returns the loss per step."""
+        s, d = _dev_u32(src), _dev_u32(dst)
+        losses = (ctypes.c_float * max(1, max_steps))()
+        n = _u32()
+        _check(_lib.mhr_pruner_train(self._h, graph._h, ctypes.byref(opts), s.numel(), _ptr(s), _ptr(d), losses,
+                                     int(max_steps), ctypes.byref(n), _stream_ptr(stream)), "mhr_pruner_train")
+        return [float(losses[i]) for i in range(min(int(n.value), max_steps))]
+
+    def save(self, path: str, stream=None):
+        """Checkpoint: parameters, Adam moments and step (mhr_pruner_save)."""
+        _check(_lib.mhr_pruner_save(self._h, os.fsencode(path), _stream_ptr(stream)), "mhr_pruner_save")
+
+    def load(self, path: str, stream=None):
+        """Restores a checkpoint written by save (mhr_pruner_load)."""
+        _check(_lib.mhr_pruner_load(self._h, os.fsencode(path), _stream_ptr(stream)), "mhr_pruner_load")
+
     def _workspace(self, n):
         torch = _torch()
         need = ctypes.c_size_t()
@@ -570,6 +661,36 @@ class Pruner:
                                           1 if update else 0, _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)),
                "mhr_pruner_train_step")
         return loss
+
+
+def beam_to_numpy(out, cnt, rec):
+    """Host copies of mhr_beam_search's results: (paths [nq][k] of
+    BEAM_DTYPE, count, recorded)."""
+    nq, k = out.shape[0], out.shape[1]
+    p = out.cpu().numpy().view(BEAM_DTYPE).reshape(nq, k)
+    return p, cnt.cpu().numpy().view(np.uint32), rec.cpu().numpy().view(np.uint64)
+
+
+def crc32(data: bytes, crc: int = 0) -> int:
+    """The library's CRC-32 (the checksum its files carry)."""
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    return int(_lib.mhr_crc32(int(crc), buf, len(data)))
+
+
+def pruner_file_info(path: str):
+    """(dim, hidden, step) of a pruner checkpoint, checked on the host
+    (raises MhrError for a damaged or foreign file)."""
+    d, h, s = _u32(), _u32(), _u32()
+    _check(_lib.mhr_pruner_file_info(os.fsencode(path), ctypes.byref(d), ctypes.byref(h), ctypes.byref(s)),
+           "mhr_pruner_file_info")
+    return int(d.value), int(h.value), int(s.value)
+
+
+def tuning_file_records(path: str) -> int:
+    """Number of records of a tuning cache, checked on the host."""
+    n = _u32()
+    _check(_lib.mhr_tuning_file_records(os.fsencode(path), ctypes.byref(n)), "mhr_tuning_file_records")
+    return int(n.value)
 
 
 GATHER_PHASES = ("fetch", "setup", "rows", "probe", "form", "score", "logsig", "bounds", "enum", "merge", "end")
@@ -710,5 +831,5 @@ class Plan:
             pass
 
 
-__all__ = ["Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+__all__ = ["BEAM_DTYPE", "beam_to_numpy", "TrainOpts", "Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "crc32", "pruner_file_info", "tuning_file_records", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
            "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]

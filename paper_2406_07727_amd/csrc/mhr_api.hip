@@ -25,6 +25,9 @@ extern "C" const char *mhr_status_string(mhr_status s) {
         case MHR_ERR_NO_EMBEDDINGS: return "embeddings not set";
         case MHR_ERR_BAD_EDGE: return "edge id out of range";
         case MHR_ERR_INTERNAL: return "internal consistency check failed";
+        case MHR_ERR_IO: return "file input/output error";
+        case MHR_ERR_CORRUPT: return "corrupt or unrecognised file";
+        case MHR_ERR_NOT_FOUND: return "not found";
     }
     return "unknown status";
 }

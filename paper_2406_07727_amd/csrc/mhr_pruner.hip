@@ -18,15 +18,13 @@
 
 #include "mhr.h"
 #include "mhr_device.h"
-#include "mhr_internal.h"
+#include <algorithm>
+#include <vector>
 
-struct mhr_pruner {
-    uint32_t d = 0, H = 0;
-    size_t np = 0;                      // parameter count
-    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
-    uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;   // bfloat16 copies
-    uint32_t step = 0;
-};
+#include "mhr_internal.h"
+#include "mhr_pruner_internal.h"
+
+
 
 namespace mhr {
 namespace {
@@ -109,11 +107,13 @@ __device__ __forceinline__ void mat_row8(const Mat &M, uint32_t row, uint32_t co
 // [z * kchunk, (z + 1) * kchunk) of [0, K).
 //   opA(m, k) = TA ? A(k, m) : A(m, k)      opB(k, n) = TB ? B(n, k) : B(k, n)
 // Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA tiles of 16 x 16),
-// 32 k per step staged in LDS with k contiguous.  atomic: add into C (split
-// K; C zeroed beforehand), else store.
+// 32 k per step staged in LDS with k contiguous.  part != nullptr (split K):
+// the block stores its chunk's sum in part[z][M][N] and a second kernel adds
+// the chunks in order, so the result does not depend on block timing; else
+// the block stores C.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Mat A, Mat B, float *C, uint32_t ldc, uint32_t M,
-                                                            uint32_t N, uint32_t K, uint32_t kchunk, int atomic) {
+                                                            uint32_t N, uint32_t K, uint32_t kchunk, float *part) {
     __shared__ __align__(16) uint16_t As[BM][BKP];
     __shared__ __align__(16) uint16_t Bs[BN][BKP];
     const uint32_t m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -175,13 +175,28 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Mat A, Mat B, float 
                 const uint32_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
                 const uint32_t n = n0 + wn + 16 * j + (lane & 15);
                 if (m < M && n < N) {
-                    float *c = C + static_cast<size_t>(m) * ldc + n;
-                    if (atomic) atomicAdd(c, acc[i][j][e]); else *c = acc[i][j][e];
+                    if (part) part[(static_cast<size_t>(blockIdx.z) * M + m) * N + n] = acc[i][j][e];
+                    else C[static_cast<size_t>(m) * ldc + n] = acc[i][j][e];
                 }
             }
 }
 
 // ---- elementwise and reduction kernels -------------------------------------
+//
+// Every reduction over samples sums per-block partials in a fixed order (no
+// floating-point atomics), so a training step is a deterministic function of
+// its inputs and a resumed run repeats the uninterrupted one bit for bit.
+
+// C[m][n] = sum over z = 0, 1, ... of part[z][m][n]
+__global__ void splitk_reduce_kernel(const float *part, uint32_t splits, uint32_t M, uint32_t N, float *C,
+                                     uint32_t ldc) {
+    const size_t MN = size_t(M) * N;
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < MN; i += size_t(gridDim.x) * blockDim.x) {
+        float acc = 0.0f;
+        for (uint32_t z = 0; z < splits; ++z) acc += part[z * MN + i];
+        C[(i / N) * ldc + i % N] = acc;
+    }
+}
 
 __global__ void fill_kernel(float *p, size_t n, float v) {
     for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
@@ -225,8 +240,9 @@ __global__ void output_kernel(const uint16_t *h2, const uint16_t *w3b, const flo
     if (lane == 0) z[row] = acc + b3[0];
 }
 
-// dz_i = (w y (p - 1) + (1 - y) p) / n and the mean loss (added into *loss)
-__global__ void bce_kernel(const float *z, const float *y, uint32_t n, float w_pos, float *dz, float *loss) {
+// dz_i = (w y (p - 1) + (1 - y) p) / n, and this block's share of the mean
+// loss in lpart[block]
+__global__ void bce_kernel(const float *z, const float *y, uint32_t n, float w_pos, float *dz, float *lpart) {
     __shared__ float red[kBlock / kWave];
     float part = 0.0f;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -246,26 +262,46 @@ __global__ void bce_kernel(const float *z, const float *y, uint32_t n, float w_p
     if (threadIdx.x == 0) {
         float s = 0.0f;
         for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) s += red[w];
-        if (loss) atomicAdd(loss, s / static_cast<float>(n));
+        lpart[blockIdx.x] = s / static_cast<float>(n);
     }
 }
 
-// out[j] += sum_i scale_i * M[i][j] (scale = nullptr: 1) over a chunk of rows
-__global__ void colsum_kernel(const uint16_t *Mv, const float *scale, float *out, uint32_t n, uint32_t H,
+// part[y][j] = sum_i scale_i * M[i][j] (scale = nullptr: 1) over the rows of
+// chunk y
+__global__ void colsum_kernel(const uint16_t *Mv, const float *scale, float *part, uint32_t n, uint32_t H,
                               uint32_t rows_per_block) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= H) return;
     const uint32_t r0 = blockIdx.y * rows_per_block, r1 = min(n, r0 + rows_per_block);
     float acc = 0.0f;
     for (uint32_t i = r0; i < r1; ++i) acc += (scale ? scale[i] : 1.0f) * from_bf16(Mv[static_cast<size_t>(i) * H + j]);
-    atomicAdd(&out[j], acc);
+    part[static_cast<size_t>(blockIdx.y) * H + j] = acc;
 }
 
+// out[j] = sum over y = 0, 1, ... of part[y][j]
+__global__ void colsum_reduce_kernel(const float *part, uint32_t chunks, uint32_t H, float *out) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= H) return;
+    float acc = 0.0f;
+    for (uint32_t y = 0; y < chunks; ++y) acc += part[static_cast<size_t>(y) * H + j];
+    out[j] = acc;
+}
+
+// *out = sum of x[0 .. n), one block: per-thread strided sums, then a fixed
+// tree over the block
 __global__ void sum_kernel(const float *x, uint32_t n, float *out) {
+    __shared__ float red[kBlock / kWave];
     float part = 0.0f;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) part += x[i];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) part += x[i];
     for (int o = kWave / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, part);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int w = 0; w < static_cast<int>(blockDim.x / kWave); ++w) s += red[w];
+        *out = s;
+    }
 }
 
 // dz2 = bfloat16(dz_i w3_j [h2_ij > 0]), in place over h2
@@ -329,19 +365,31 @@ Mat features(const mhr_graph *g, const uint32_t *s, const uint32_t *t, const uin
     return F;
 }
 
-template <bool TA, bool TB>
-hipError_t gemm(const Mat &A, const Mat &B, float *C, uint32_t ldc, uint32_t M, uint32_t N, uint32_t K,
-                uint32_t splits, hipStream_t st) {
-    if (M == 0 || N == 0) return hipSuccess;
+// K chunk (a multiple of BK) and chunk count for a requested split count
+struct Split {
+    uint32_t kchunk, splits;
+};
+Split split_k(uint32_t K, uint32_t splits) {
     if (splits < 1) splits = 1;
     uint32_t kchunk = (K + splits - 1) / splits;
     kchunk = (kchunk + BK - 1) / BK * BK;
     if (kchunk == 0) kchunk = BK;
     splits = (K + kchunk - 1) / kchunk;
-    if (splits == 0) splits = 1;
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, splits);
-    hipLaunchKernelGGL((gemm_kernel<TA, TB>), grid, dim3(kGemmThreads), 0, st, A, B, C, ldc, M, N, K, kchunk,
-                       splits > 1 ? 1 : 0);
+    return {kchunk, splits < 1 ? 1u : splits};
+}
+
+// part: split-K staging of at least splits * M * N floats (unused for one
+// split)
+template <bool TA, bool TB>
+hipError_t gemm(const Mat &A, const Mat &B, float *C, uint32_t ldc, uint32_t M, uint32_t N, uint32_t K,
+                uint32_t splits, float *part, hipStream_t st) {
+    if (M == 0 || N == 0) return hipSuccess;
+    const Split sp = split_k(K, splits);
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, sp.splits);
+    float *pp = sp.splits > 1 ? part : nullptr;
+    hipLaunchKernelGGL((gemm_kernel<TA, TB>), grid, dim3(kGemmThreads), 0, st, A, B, C, ldc, M, N, K, sp.kchunk, pp);
+    if (pp) hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(size_t(M) * N)), dim3(256), 0, st, pp, sp.splits,
+                               M, N, C, ldc);
     return hipGetLastError();
 }
 
@@ -354,10 +402,18 @@ uint32_t splits_for(uint32_t M, uint32_t N, uint32_t K) {
     return s < 1 ? 1 : s;
 }
 
+// floats of split-K staging for an M x N weight gradient over K samples
+size_t split_floats(uint32_t M, uint32_t N, uint32_t K) {
+    const Split sp = split_k(K, splits_for(M, N, K));
+    return sp.splits > 1 ? size_t(sp.splits) * M * N : 0;
+}
+
+constexpr uint32_t kColRows = 256;   // rows per column-sum chunk
+
 struct PWs {
-    size_t Z, h1, h2, z, dz, s, t, total;
+    size_t Z, h1, h2, z, dz, s, t, part, cpart, lpart, total;
 };
-PWs pws_layout(uint32_t n, uint32_t H) {
+PWs pws_layout(uint32_t n, uint32_t d, uint32_t H) {
     PWs L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) & ~size_t(255); return r; };
@@ -368,6 +424,9 @@ PWs pws_layout(uint32_t n, uint32_t H) {
     L.dz = take(size_t(n) * 4);
     L.s = take(size_t(n) * 4);
     L.t = take(size_t(n) * 4);
+    L.part = take(std::max(split_floats(H, H, n), split_floats(H, 4 * d, n)) * 4);
+    L.cpart = take(size_t((n + kColRows - 1) / kColRows) * H * 4);
+    L.lpart = take(size_t(grid_for(n, kBlock)) * 4);
     L.total = o;
     return L;
 }
@@ -385,7 +444,7 @@ hipError_t refresh_bf16(mhr_pruner *p, hipStream_t st) {
 // forward pass over n samples; leaves Z1 / h1 / h2 / z in the workspace
 mhr_status forward_impl(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uint32_t *q, const uint32_t *src,
                         const uint32_t *dst, const uint32_t *v, const uint32_t *r, char *ws, hipStream_t st) {
-    const PWs W = pws_layout(n, p->H);
+    const PWs W = pws_layout(n, p->d, p->H);
     const PLayout L = play(p->d, p->H);
     const uint32_t H = p->H, d = p->d;
     float *Z = reinterpret_cast<float *>(ws + W.Z);
@@ -393,10 +452,10 @@ mhr_status forward_impl(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uin
     uint32_t *s = reinterpret_cast<uint32_t *>(ws + W.s), *t = reinterpret_cast<uint32_t *>(ws + W.t);
     hipLaunchKernelGGL(expand_query_kernel, dim3(grid_for(n)), dim3(256), 0, st, q, src, dst, s, t, n);
     const Mat F = features(g, s, t, v, r);
-    MHR_HIP_TRY((gemm<false, true>(F, plain(p->W1b, 4 * d), Z, H, n, H, 4 * d, 1, st)));
+    MHR_HIP_TRY((gemm<false, true>(F, plain(p->W1b, 4 * d), Z, H, n, H, 4 * d, 1, nullptr, st)));
     hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b1, h1,
                        size_t(n) * H, H);
-    MHR_HIP_TRY((gemm<false, true>(plain(h1, H), plain(p->W2b, H), Z, H, n, H, H, 1, st)));
+    MHR_HIP_TRY((gemm<false, true>(plain(h1, H), plain(p->W2b, H), Z, H, n, H, H, 1, nullptr, st)));
     hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b2, h2,
                        size_t(n) * H, H);
     hipLaunchKernelGGL(output_kernel, dim3((n + 3) / 4), dim3(256), 0, st, h2, p->w3b, p->theta + L.b3,
@@ -783,6 +842,9 @@ __global__ void scatter_kernel(uint32_t n, const uint32_t *idx, uint32_t kmax, c
 }
 
 }  // namespace
+
+hipError_t pruner_refresh_bf16(mhr_pruner *p, hipStream_t st) { return refresh_bf16(p, st); }
+
 }  // namespace mhr
 
 using namespace mhr;
@@ -859,7 +921,7 @@ extern "C" mhr_status mhr_pruner_get_params(const mhr_pruner *p, float *params, 
 
 extern "C" mhr_status mhr_pruner_workspace_size(const mhr_pruner *p, uint32_t n, size_t *bytes) {
     MHR_ARG_CHECK(p && bytes, "mhr_pruner_workspace_size: null argument");
-    *bytes = pws_layout(n, p->H).total;
+    *bytes = pws_layout(n, p->d, p->H).total;
     return MHR_OK;
 }
 
@@ -870,8 +932,8 @@ static mhr_status check_model(const mhr_pruner *p, const mhr_graph *g, uint32_t 
         return MHR_ERR_NO_EMBEDDINGS;
     }
     MHR_ARG_CHECK(g->dim == p->d, "pruner: the graph's embedding dimension differs from the pruner's");
-    if (ws_bytes < pws_layout(n, p->H).total) {
-        set_error("pruner workspace too small: need " + std::to_string(pws_layout(n, p->H).total) + " bytes");
+    if (ws_bytes < pws_layout(n, p->d, p->H).total) {
+        set_error("pruner workspace too small: need " + std::to_string(pws_layout(n, p->d, p->H).total) + " bytes");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
     }
     return MHR_OK;
@@ -888,7 +950,7 @@ extern "C" mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint
     char *w = static_cast<char *>(ws);
     rc = forward_impl(p, g, n, q, src, dst, v, r, w, st);
     if (rc != MHR_OK) return rc;
-    MHR_HIP_TRY(hipMemcpyAsync(logits, w + pws_layout(n, p->H).z, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+    MHR_HIP_TRY(hipMemcpyAsync(logits, w + pws_layout(n, p->d, p->H).z, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
     return MHR_OK;
 }
 
@@ -906,7 +968,7 @@ extern "C" mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, u
     char *w = static_cast<char *>(ws);
     rc = forward_impl(p, g, n, q, src, dst, v, r, w, st);
     if (rc != MHR_OK) return rc;
-    const PWs W = pws_layout(n, p->H);
+    const PWs W = pws_layout(n, p->d, p->H);
     const PLayout L = play(p->d, p->H);
     const uint32_t H = p->H, d = p->d;
     float *Z = reinterpret_cast<float *>(w + W.Z);
@@ -914,26 +976,33 @@ extern "C" mhr_status mhr_pruner_train_step(mhr_pruner *p, const mhr_graph *g, u
     float *z = reinterpret_cast<float *>(w + W.z), *dz = reinterpret_cast<float *>(w + W.dz);
     uint32_t *s = reinterpret_cast<uint32_t *>(w + W.s), *t = reinterpret_cast<uint32_t *>(w + W.t);
     const size_t nh = size_t(n) * H;
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(p->np)), dim3(256), 0, st, p->grad, p->np, 0.0f);
-    if (loss) hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, loss, size_t(1), 0.0f);
-    hipLaunchKernelGGL(bce_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, z, label, n, pos_weight, dz, loss);
+    float *part = reinterpret_cast<float *>(w + W.part), *cpart = reinterpret_cast<float *>(w + W.cpart);
+    float *lpart = reinterpret_cast<float *>(w + W.lpart);
+    const uint32_t nblk = grid_for(n, kBlock), chunks = (n + kColRows - 1) / kColRows;
+    const dim3 cgrid((H + 255) / 256, chunks);
+    hipLaunchKernelGGL(bce_kernel, dim3(nblk), dim3(kBlock), 0, st, z, label, n, pos_weight, dz, lpart);
+    if (loss) hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kBlock), 0, st, lpart, nblk, loss);
     // output layer
-    const uint32_t rows_blk = 256;
-    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h2, dz,
-                       p->grad + L.w3, n, H, rows_blk);
-    hipLaunchKernelGGL(sum_kernel, dim3(grid_for(n)), dim3(256), 0, st, dz, n, p->grad + L.b3);
+    hipLaunchKernelGGL(colsum_kernel, cgrid, dim3(256), 0, st, h2, dz, cpart, n, H, kColRows);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((H + 255) / 256), dim3(256), 0, st, cpart, chunks, H,
+                       p->grad + L.w3);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kBlock), 0, st, dz, n, p->grad + L.b3);
     // second layer: dz2 over h2, then dW2 = dz2^T h1, db2, dH1 = dz2 W2
     hipLaunchKernelGGL(dz2_kernel, dim3(grid_for(nh)), dim3(256), 0, st, dz, p->w3b, h2, nh, H);
-    MHR_HIP_TRY((gemm<true, false>(plain(h2, H), plain(h1, H), p->grad + L.W2, H, H, H, n, splits_for(H, H, n), st)));
-    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h2,
-                       nullptr, p->grad + L.b2, n, H, rows_blk);
-    MHR_HIP_TRY((gemm<false, false>(plain(h2, H), plain(p->W2b, H), Z, H, n, H, H, 1, st)));
+    MHR_HIP_TRY((gemm<true, false>(plain(h2, H), plain(h1, H), p->grad + L.W2, H, H, H, n, splits_for(H, H, n), part,
+                                   st)));
+    hipLaunchKernelGGL(colsum_kernel, cgrid, dim3(256), 0, st, h2, nullptr, cpart, n, H, kColRows);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((H + 255) / 256), dim3(256), 0, st, cpart, chunks, H,
+                       p->grad + L.b2);
+    MHR_HIP_TRY((gemm<false, false>(plain(h2, H), plain(p->W2b, H), Z, H, n, H, H, 1, nullptr, st)));
     // first layer: dz1 over h1, then dW1 = dz1^T F, db1
     hipLaunchKernelGGL(dz1_kernel, dim3(grid_for(nh)), dim3(256), 0, st, Z, h1, nh);
     const Mat F = features(g, s, t, v, r);
-    MHR_HIP_TRY((gemm<true, false>(plain(h1, H), F, p->grad + L.W1, 4 * d, H, 4 * d, n, splits_for(H, 4 * d, n), st)));
-    hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256, (n + rows_blk - 1) / rows_blk), dim3(256), 0, st, h1,
-                       nullptr, p->grad + L.b1, n, H, rows_blk);
+    MHR_HIP_TRY((gemm<true, false>(plain(h1, H), F, p->grad + L.W1, 4 * d, H, 4 * d, n, splits_for(H, 4 * d, n),
+                                   part, st)));
+    hipLaunchKernelGGL(colsum_kernel, cgrid, dim3(256), 0, st, h1, nullptr, cpart, n, H, kColRows);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((H + 255) / 256), dim3(256), 0, st, cpart, chunks, H,
+                       p->grad + L.b1);
     if (update) {
         p->step += 1;
         const float bc1 = 1.0f - powf(beta1, static_cast<float>(p->step));
@@ -1072,5 +1141,193 @@ extern "C" mhr_status mhr_scatter_results(uint32_t n, const uint32_t *idx, uint3
     hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(64), 0, static_cast<hipStream_t>(stream), n, idx, kmax, src_paths,
                        src_count, src_total, src_status, paths, count, total, status);
     MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Whole training run (the sequence a caller would otherwise drive): batches
+// of queries in a shuffled order, each labelled by the exact search, sampled
+// and trained on in steps.
+// ---------------------------------------------------------------------------
+namespace mhr {
+namespace {
+
+__global__ void gather_u32_kernel(const uint32_t *src, const uint32_t *idx, uint32_t n, uint32_t *out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = src[idx[i]];
+}
+
+inline uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Device buffers owned by one training run (freed on every exit).
+struct TrainBuffers {
+    std::vector<void *> owned;
+    ~TrainBuffers() {
+        for (void *p : owned) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t get(T *&p, size_t count) {
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(T));
+        if (e == hipSuccess) owned.push_back(q);
+        p = static_cast<T *>(q);
+        return e;
+    }
+};
+
+}  // namespace
+}  // namespace mhr
+
+extern "C" mhr_status mhr_pruner_train(mhr_pruner *p, const mhr_graph *g, const mhr_train_opts *opts, uint32_t nq,
+                                       const uint32_t *src, const uint32_t *dst, float *losses, uint32_t max_losses,
+                                       uint32_t *nsteps, void *stream) {
+    MHR_ARG_CHECK(p && g && opts && nsteps, "mhr_pruner_train: null argument");
+    MHR_ARG_CHECK(nq == 0 || (src && dst), "mhr_pruner_train: null query arrays");
+    MHR_ARG_CHECK(max_losses == 0 || losses, "mhr_pruner_train: null loss array");
+    for (uint32_t v : opts->reserved) MHR_ARG_CHECK(v == 0, "mhr_pruner_train: reserved fields must be zero");
+    if (!g->X) {
+        set_error("embeddings not set");
+        return MHR_ERR_NO_EMBEDDINGS;
+    }
+    MHR_ARG_CHECK(g->dim == p->d, "mhr_pruner_train: the graph's embedding dimension differs from the pruner's");
+    const uint32_t K = opts->k;
+    MHR_ARG_CHECK(K >= 1 && K <= MHR_MAX_K, "mhr_pruner_train: k must be in [1, MHR_MAX_K]");
+    const uint32_t B = opts->batch_queries ? opts->batch_queries : 4096u;
+    const uint32_t S = opts->step_samples ? opts->step_samples : 65536u;
+    const uint32_t E = opts->epochs ? opts->epochs : 1u;
+    const uint32_t neg = opts->neg_per_hop ? opts->neg_per_hop : 64u;
+    const float lr = opts->lr > 0.0f ? opts->lr : 1e-3f;
+    const float b1 = opts->beta1 > 0.0f ? opts->beta1 : 0.9f, b2 = opts->beta2 > 0.0f ? opts->beta2 : 0.999f;
+    const float eps = opts->eps > 0.0f ? opts->eps : 1e-8f;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    *nsteps = 0;
+    if (nq == 0) return MHR_OK;
+
+    TrainBuffers tb;
+    const uint32_t nb_max = std::min(B, nq);
+    uint32_t *perm_d, *bsrc, *bdst, *cnt;
+    mhr_path *paths;
+    uint64_t *eo, *co, *cs, *nsamp;
+    float *loss_d, *possum;
+    MHR_HIP_TRY(tb.get(perm_d, nb_max));
+    MHR_HIP_TRY(tb.get(bsrc, nb_max));
+    MHR_HIP_TRY(tb.get(bdst, nb_max));
+    MHR_HIP_TRY(tb.get(cnt, nb_max));
+    MHR_HIP_TRY(tb.get(paths, size_t(nb_max) * K));
+    MHR_HIP_TRY(tb.get(eo, size_t(nb_max) + 1));
+    MHR_HIP_TRY(tb.get(co, size_t(nb_max) + 1));
+    MHR_HIP_TRY(tb.get(cs, nb_max));
+    MHR_HIP_TRY(tb.get(nsamp, 1));
+    MHR_HIP_TRY(tb.get(possum, 1));
+    mhr_query_opts qo{};
+    qo.k = K;
+    size_t ws_bytes = 0;
+    mhr_status rc = mhr_workspace_size(g, &qo, nb_max, K, &ws_bytes);
+    if (rc != MHR_OK) return rc;
+    unsigned char *ws;
+    MHR_HIP_TRY(tb.get(ws, ws_bytes));
+    size_t pws_bytes = 0;
+    rc = mhr_pruner_workspace_size(p, S, &pws_bytes);
+    if (rc != MHR_OK) return rc;
+    unsigned char *pws;
+    MHR_HIP_TRY(tb.get(pws, pws_bytes));
+    // candidate and sample buffers grow with the largest batch seen
+    uint64_t cap_c = 0, cap_e = 0;
+    uint32_t *cq = nullptr, *cv = nullptr, *cr = nullptr, *sq = nullptr, *sv = nullptr, *sr = nullptr;
+    uint64_t *ce = nullptr;
+    uint8_t *pos = nullptr;
+    float *sl = nullptr;
+    unsigned char *sws = nullptr;
+    size_t sws_cap = 0;
+    uint32_t loss_cap = 0;
+    loss_d = nullptr;
+
+    std::vector<uint32_t> perm(nq);
+    uint64_t rng = opts->seed ^ 0x6D68725F74726169ull;
+    uint32_t steps = 0;
+    uint64_t batch_no = 0;
+    for (uint32_t ep = 0; ep < E; ++ep) {
+        for (uint32_t i = 0; i < nq; ++i) perm[i] = i;
+        for (uint32_t i = nq - 1; i > 0; --i) {   // Fisher-Yates with SplitMix64
+            const uint32_t j = static_cast<uint32_t>(splitmix64(rng) % (static_cast<uint64_t>(i) + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        for (uint32_t b0 = 0; b0 < nq; b0 += B, ++batch_no) {
+            const uint32_t nb = std::min(B, nq - b0);
+            MHR_HIP_TRY(hipMemcpyAsync(perm_d, perm.data() + b0, size_t(nb) * 4, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(gather_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, src, perm_d, nb, bsrc);
+            hipLaunchKernelGGL(gather_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, dst, perm_d, nb, bdst);
+            // labels: the exact top-K
+            rc = mhr_topk_paths(g, &qo, nb, bsrc, bdst, nullptr, K, paths, cnt, nullptr, nullptr, ws, ws_bytes, st);
+            if (rc != MHR_OK) return rc;
+            rc = mhr_pruner_count(g, nb, bsrc, bdst, eo, co, st);
+            if (rc != MHR_OK) return rc;
+            uint64_t tot[2];
+            MHR_HIP_TRY(hipMemcpyAsync(&tot[0], eo + nb, 8, hipMemcpyDeviceToHost, st));
+            MHR_HIP_TRY(hipMemcpyAsync(&tot[1], co + nb, 8, hipMemcpyDeviceToHost, st));
+            MHR_HIP_TRY(hipStreamSynchronize(st));
+            const uint64_t nent = tot[0], ncand = tot[1];
+            if (ncand == 0) continue;
+            if (ncand > cap_c) {
+                cap_c = ncand + ncand / 4;
+                MHR_HIP_TRY(tb.get(cq, cap_c));
+                MHR_HIP_TRY(tb.get(cv, cap_c));
+                MHR_HIP_TRY(tb.get(cr, cap_c));
+                MHR_HIP_TRY(tb.get(ce, cap_c));
+                MHR_HIP_TRY(tb.get(sq, cap_c));
+                MHR_HIP_TRY(tb.get(sv, cap_c));
+                MHR_HIP_TRY(tb.get(sr, cap_c));
+                MHR_HIP_TRY(tb.get(sl, cap_c));
+            }
+            if (nent > cap_e) {
+                cap_e = nent + nent / 4;
+                MHR_HIP_TRY(tb.get(pos, cap_e));
+            }
+            const size_t swsb = mhr_pruner_sample_workspace(nb, ncand);
+            if (swsb > sws_cap) {
+                sws_cap = swsb;
+                MHR_HIP_TRY(tb.get(sws, sws_cap));
+            }
+            rc = mhr_pruner_enumerate(g, nb, bsrc, bdst, eo, co, cs, cq, cv, cr, ce, st);
+            if (rc != MHR_OK) return rc;
+            rc = mhr_pruner_label(g, nb, bsrc, bdst, eo, paths, cnt, K, pos, st);
+            if (rc != MHR_OK) return rc;
+            rc = mhr_pruner_sample(nb, co, cs, ncand, cq, cv, cr, ce, pos, neg, opts->seed * 1000003ull + batch_no, sq, sv,
+                                   sr, sl, nsamp, sws, sws_cap, st);
+            if (rc != MHR_OK) return rc;
+            uint64_t m = 0;
+            MHR_HIP_TRY(hipMemcpyAsync(&m, nsamp, 8, hipMemcpyDeviceToHost, st));
+            MHR_HIP_TRY(hipStreamSynchronize(st));
+            if (m == 0) continue;
+            hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, possum, size_t(1), 0.0f);
+            hipLaunchKernelGGL(sum_kernel, dim3(grid_for(m)), dim3(256), 0, st, sl, static_cast<uint32_t>(m), possum);
+            float npos = 0.0f;
+            MHR_HIP_TRY(hipMemcpyAsync(&npos, possum, 4, hipMemcpyDeviceToHost, st));
+            MHR_HIP_TRY(hipStreamSynchronize(st));
+            const float wpos = (static_cast<float>(m) - npos) / std::max(npos, 1.0f);
+            const uint32_t nst = static_cast<uint32_t>((m + S - 1) / S);
+            if (nst > loss_cap) {
+                loss_cap = nst;
+                MHR_HIP_TRY(tb.get(loss_d, loss_cap));
+            }
+            for (uint32_t k = 0; k < nst; ++k) {
+                const uint64_t a = uint64_t(k) * S;
+                const uint32_t len = static_cast<uint32_t>(std::min<uint64_t>(S, m - a));
+                rc = mhr_pruner_train_step(p, g, len, sq + a, bsrc, bdst, sv + a, sr + a, sl + a, wpos, lr, b1, b2, eps,
+                                           1, loss_d + k, pws, pws_bytes, st);
+                if (rc != MHR_OK) return rc;
+            }
+            const uint32_t room = steps < max_losses ? std::min(nst, max_losses - steps) : 0u;
+            if (room) MHR_HIP_TRY(hipMemcpyAsync(losses + steps, loss_d, size_t(room) * 4, hipMemcpyDeviceToHost, st));
+            MHR_HIP_TRY(hipStreamSynchronize(st));
+            steps += nst;
+        }
+    }
+    *nsteps = steps;
     return MHR_OK;
 }

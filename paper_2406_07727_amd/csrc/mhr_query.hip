@@ -2292,6 +2292,38 @@ __global__ void edge_weight_kernel(GArgs A, uint64_t ne, const uint32_t *u, cons
     if (e32) e32[i] = err;
 }
 
+// The fast-pass FP32 weight of one edge (DistMult: the FMA dot product and
+// the centred log-sigmoid less ln 2; TransE-L1: gamma minus the distance).
+template <bool BF16, bool TE>
+__device__ inline float edge_w32(const GArgs &A, uint32_t uu, uint32_t rr, uint32_t vv) {
+    const size_t d = A.d;
+    if (TE) {
+        float l1 = 0.0f;
+        for (uint32_t k = 0; k < A.d; ++k)
+            l1 += fabsf((load1<BF16>(A.X, uu * d + k) + load1<BF16>(A.Y, rr * d + k)) - load1<BF16>(A.X, vv * d + k));
+        return A.gamma - l1;
+    }
+    float x = 0.0f;
+    for (uint32_t k = 0; k < A.d; ++k)
+        x = __builtin_fmaf(load1<BF16>(A.X, uu * d + k) * load1<BF16>(A.Y, rr * d + k), load1<BF16>(A.X, vv * d + k), x);
+    float fe;
+    return centred_logsigmoid_e(x, fe) - kLn2f;
+}
+
+// The weight of each pruner candidate's own edge: s -r-> v for a first-hop
+// candidate of query q, v -r-> t for a second-hop one (the ranking a
+// per-level score beam would use).
+template <bool BF16, bool TE>
+__global__ void candidate_weight_kernel(GArgs A, uint64_t n, const uint32_t *src, const uint32_t *dst,
+                                        const uint32_t *cq, const uint32_t *cv, const uint32_t *cr, float *w) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t qw = cq[i], q = qw & 0x7FFFFFFFu;
+    const bool hop2 = (qw & 0x80000000u) != 0;
+    const uint32_t u = hop2 ? cv[i] : src[q], v = hop2 ? dst[q] : cv[i];
+    w[i] = edge_w32<BF16, TE>(A, u, cr[i], v);
+}
+
 GArgs make_args(const mhr_graph *g) {
     GArgs A{};
     A.out_rp = g->out.row_ptr; A.out_col = g->out.col; A.out_mask = g->out.rmask;
@@ -2656,4 +2688,29 @@ extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *r
     set_error("this build records no phase clocks (build with MHR_PHASE_CLOCKS)");
     return MHR_ERR_UNSUPPORTED;
 #endif
+}
+
+extern "C" mhr_status mhr_pruner_candidate_weights(const mhr_graph *g, uint64_t ncand, const uint32_t *src,
+                                                   const uint32_t *dst, const uint32_t *cand_q, const uint32_t *cand_v,
+                                                   const uint32_t *cand_r, float *w, void *stream) {
+    MHR_ARG_CHECK(g != nullptr, "mhr_pruner_candidate_weights: null graph");
+    if (!g->X) {
+        set_error("embeddings not set");
+        return MHR_ERR_NO_EMBEDDINGS;
+    }
+    if (ncand == 0) return MHR_OK;
+    MHR_ARG_CHECK(src && dst && cand_q && cand_v && cand_r && w, "mhr_pruner_candidate_weights: null pointer");
+    GArgs A = make_args(g);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid(static_cast<uint32_t>((ncand + 255) / 256));
+    const bool te = g->scorer == MHR_SCORER_TRANSE_L1;
+    if (g->dtype == MHR_DTYPE_BF16) {
+        if (te) hipLaunchKernelGGL((candidate_weight_kernel<true, true>), grid, dim3(256), 0, st, A, ncand, src, dst, cand_q, cand_v, cand_r, w);
+        else hipLaunchKernelGGL((candidate_weight_kernel<true, false>), grid, dim3(256), 0, st, A, ncand, src, dst, cand_q, cand_v, cand_r, w);
+    } else {
+        if (te) hipLaunchKernelGGL((candidate_weight_kernel<false, true>), grid, dim3(256), 0, st, A, ncand, src, dst, cand_q, cand_v, cand_r, w);
+        else hipLaunchKernelGGL((candidate_weight_kernel<false, false>), grid, dim3(256), 0, st, A, ncand, src, dst, cand_q, cand_v, cand_r, w);
+    }
+    MHR_HIP_TRY(hipGetLastError());
+    return MHR_OK;
 }

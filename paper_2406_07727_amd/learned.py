@@ -17,9 +17,9 @@ Inference.
    confidence test: fewer than K paths found, or a kept share of the
    predicted mass below ``tau`` at either hop.
 
-Every step of both runs in the library's kernels.  This module only sequences
-them, sizes buffers from the counts the kernels report, and keeps the loss
-history.
+Every step of both runs in the library's kernels.  Training is one library
+call (mhr_pruner_train); for inference this module sequences the calls and
+sizes buffers from the counts the kernels report.
 """
 
 from __future__ import annotations
@@ -29,7 +29,8 @@ import time
 
 import numpy as np
 
-from . import (Graph, Pruner, TopK, _check, _dev_u32, _lib, _ptr, _stream_ptr, _torch, candidates, select)
+from . import (Graph, Pruner, TopK, TrainOpts, _check, _dev_u32, _lib, _ptr, _stream_ptr, _torch, candidates,
+               select)
 
 
 def init_params(dim: int, hidden: int, seed: int) -> np.ndarray:
@@ -79,31 +80,15 @@ class LearnedPruner:
 
     def fit(self, src, dst, K: int = 32, batch_queries: int = 4096, step_samples: int = 65536, epochs: int = 1,
             lr: float = 1e-3, neg_per_hop: int = 64, seed: int = 1, log=None):
-        """Trains on the queries (host arrays); returns the loss per step."""
-        src = np.asarray(src, dtype=np.uint32)
-        dst = np.asarray(dst, dtype=np.uint32)
-        rng = np.random.Generator(np.random.PCG64(seed))
-        losses = []
-        batch = 0
-        for ep in range(epochs):
-            order = rng.permutation(len(src))
-            for b0 in range(0, len(src), batch_queries):
-                idx = order[b0:b0 + batch_queries]
-                sq, sv, sr, sl, s, d = self.samples(src[idx], dst[idx], K, neg_per_hop, seed * 1000003 + batch)
-                batch += 1
-                m = sq.numel()
-                if m == 0:
-                    continue
-                npos = float(sl.sum().item())
-                w_pos = (m - npos) / max(npos, 1.0)
-                for st in range(0, m, step_samples):
-                    e = min(m, st + step_samples)
-                    losses.append(self.net.train_step(self.graph, sq[st:e], s, d, sv[st:e], sr[st:e], sl[st:e],
-                                                      pos_weight=w_pos, lr=lr))
-                if log:
-                    log(f"epoch {ep} batch {batch}: {m} samples ({npos:.0f} positive), "
-                        f"loss {float(losses[-1].item()):.4f}")
-        return [float(x.item()) for x in losses]
+        """Trains on the queries (host or device arrays) with the library's
+        whole-run call (mhr_pruner_train); returns the loss per step."""
+        o = TrainOpts()
+        o.k, o.batch_queries, o.step_samples, o.epochs = int(K), int(batch_queries), int(step_samples), int(epochs)
+        o.neg_per_hop, o.lr, o.seed = int(neg_per_hop), float(lr), int(seed)
+        losses = self.net.train(self.graph, src, dst, o)
+        if log and losses:
+            log(f"trained {len(losses)} steps: loss {np.mean(losses[:3]):.4f} -> {np.mean(losses[-10:]):.4f}")
+        return losses
 
     # ---- inference ----------------------------------------------------------
     def logits(self, c, chunk: int = 1 << 20):
@@ -151,12 +136,11 @@ class LearnedPruner:
             rng = np.random.Generator(np.random.PCG64(seed))
             return torch.from_numpy(rng.random(c.n).astype(np.float32)).cuda()
         if kind == "beam":
-            q = (c.q & 0x7FFFFFFF).long()
-            hop2 = torch.arange(c.n, device="cuda") >= c.cand_split[q]
-            u = torch.where(hop2, c.v, c.src[q])
-            v = torch.where(hop2, c.dst[q], c.v)
-            w, _, _, _ = self.graph.edge_weights(u, c.r, v)
-            return w
+            w = torch.empty(max(c.n, 1), dtype=torch.float32, device="cuda")
+            _check(_lib.mhr_pruner_candidate_weights(self.graph._h, c.n, _ptr(c.src), _ptr(c.dst), _ptr(c.q),
+                                                     _ptr(c.v), _ptr(c.r), _ptr(w), _stream_ptr()),
+                   "mhr_pruner_candidate_weights")
+            return w[:c.n]
         raise ValueError(kind)
 
 

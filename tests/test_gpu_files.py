@@ -1,0 +1,93 @@
+"""Checkpoint and tuning-cache files on the GPU: a pruner saved after some
+Adam steps and loaded into a fresh handle resumes training identically (the
+same parameters after further steps); a damaged checkpoint is refused before
+anything is copied; tuned settings saved for a graph and batch come back
+for that key only."""
+
+import numpy as np
+import pytest
+
+from tests.parity import gpu_graph, run_gpu, say, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2406_07727_amd  # noqa: F401
+
+
+def test_pruner_checkpoint_resume(tmp_path):
+    import torch
+    import paper_2406_07727_amd as mhr
+    from paper_2406_07727_amd.learned import init_params
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    say("case pruner checkpoint resume")
+    g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y)
+    dim, H = cfg.emb.d, 32
+    rng = np.random.Generator(np.random.PCG64(4))
+    n = 600
+    q = rng.integers(0, len(s), n).astype(np.uint32)
+    v = rng.integers(0, cfg.graph.n, n).astype(np.uint32)
+    rr = rng.integers(0, cfg.graph.R, n).astype(np.uint32)
+    y = (rng.random(n) < 0.3).astype(np.float32)
+    a = mhr.Pruner(dim, H)
+    a.set_params(init_params(dim, H, 9))
+    for _ in range(3):
+        a.train_step(g, q, s, d, v, rr, y, pos_weight=2.0, lr=1e-2)
+    torch.cuda.synchronize()
+    path = str(tmp_path / "pruner.ckpt")
+    a.save(path)
+    assert mhr.pruner_file_info(path) == (dim, H, 3)
+    b = mhr.Pruner(dim, H)
+    b.load(path)
+    assert np.array_equal(a.params().cpu().numpy(), b.params().cpu().numpy())
+    for _ in range(2):
+        a.train_step(g, q, s, d, v, rr, y, pos_weight=2.0, lr=1e-2)
+        b.train_step(g, q, s, d, v, rr, y, pos_weight=2.0, lr=1e-2)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.params().cpu().numpy(), b.params().cpu().numpy())
+    # a damaged file is refused and leaves the handle unchanged
+    data = bytearray(open(path, "rb").read())
+    data[len(data) // 2] ^= 0x40
+    open(path, "wb").write(bytes(data))
+    before = b.params().cpu().numpy()
+    with pytest.raises(mhr.MhrError) as e:
+        b.load(path)
+    assert e.value.status == mhr.ERR_CORRUPT
+    assert np.array_equal(before, b.params().cpu().numpy())
+    # dimensions must match
+    a.save(path)
+    c = mhr.Pruner(dim, 48)
+    with pytest.raises(mhr.MhrError):
+        c.load(path)
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    import paper_2406_07727_amd as mhr
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload("hub_tiny")
+    say("case tuning cache")
+    g = gpu_graph(cfg.graph.n, cfg.graph.R, h, r, t, X, Y)
+    tuned, ms = g.autotune(s, d, 16, reps=1)
+    path = str(tmp_path / "tune.bin")
+    g.save_tuning(path, len(s), 16, tuned, ms)
+    g.save_tuning(path, len(s), 32, mhr.QueryOpts(0, 8192, 0, 10), 9.0)
+    assert mhr.tuning_file_records(path) == 2
+    o, ms2 = g.load_tuning(path, len(s), 16)
+    assert (o.tile_edges, o.hash_log2, o.grid_blocks) == (tuned.tile_edges, tuned.hash_log2, tuned.grid_blocks)
+    assert ms2 == pytest.approx(ms)
+    o32, _ = g.load_tuning(path, len(s), 32)
+    assert (o32.tile_edges, o32.hash_log2) == (8192, 10)
+    assert g.load_tuning(path, len(s) + 1, 16) is None
+    # saving the same key again replaces the record
+    g.save_tuning(path, len(s), 16, mhr.QueryOpts(0, 16384, 0, 11), 2.0)
+    assert mhr.tuning_file_records(path) == 2
+    assert g.load_tuning(path, len(s), 16)[0].tile_edges == 16384
+    # the loaded settings give the default settings' results
+    ref = run_gpu(g, s, d, 16)
+    got = run_gpu(g, s, d, 16, opts=o)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
