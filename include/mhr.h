@@ -83,7 +83,8 @@ typedef enum mhr_scorer {
 #define MHR_Q_BAD_K       2u   /* k == 0 or k > k_max: count 0 */
 #define MHR_Q_EXACT_PASS  4u   /* informational: the FP32 candidate band overflowed and
                                   the exhaustive compensated pass produced the result */
-#define MHR_Q_OVERFLOW    8u   /* an internal capacity was exceeded: result incomplete */
+/* No capacity can truncate a result: a query whose candidates overflow the
+ * tile lists is answered by the exhaustive pass (MHR_Q_EXACT_PASS). */
 
 /* Per-path flags. */
 #define MHR_PATH_RESCORED       1u  /* score evaluated in compensated FP32 (float-float) */
@@ -127,7 +128,8 @@ typedef struct mhr_graph_stats {
     uint32_t heavy_rows_out, heavy_rows_in;  /* rows with a probe directory */
 } mhr_graph_stats;
 
-/* Builds the graph on the device (one-time ingest): forward CSR (rows =
+/* Builds the graph G of the problem (section 3.1: the multi-relational
+ * graph searched for paths) on the device (one-time ingest): forward CSR (rows =
  * heads, entries = distinct tails ascending) and reverse CSR (rows = tails,
  * entries = distinct heads ascending), each entry carrying the bitmask of
  * relations joining the pair; plus bucket directories of long rows.  The
@@ -137,7 +139,9 @@ typedef struct mhr_graph_stats {
  * of range), OUT_OF_MEMORY, DEVICE. */
 mhr_status mhr_graph_create(const mhr_graph_desc *desc, void *stream, mhr_graph **out);
 
-/* Attaches embeddings: entity[num_vertices][dim] and relation[num_relations][dim],
+/* Attaches the embeddings that define the edge weights (section 3.1: the
+ * weight of an edge is computed from its head, relation and tail vectors):
+ * entity[num_vertices][dim] and relation[num_relations][dim],
  * row-major device arrays of `dtype`, BORROWED (they must stay valid and
  * unchanged while the graph is queried), 16-byte aligned.  dim: power of two
  * in [8, 512].  Enqueues nothing (`stream` is unused). */
@@ -184,7 +188,10 @@ typedef struct mhr_query_opts {
 mhr_status mhr_workspace_size(const mhr_graph *g, const mhr_query_opts *opts, uint32_t nq,
                               uint32_t k_max, size_t *bytes);
 
-/* Exact top-K three-hop paths for nq queries (src[q], dst[q], k[q]).
+/* Exact top-K three-hop paths for nq queries (src[q], dst[q], k[q]): the K
+ * highest-scoring paths s -> a -> b -> t of section 3.1, a path's score the
+ * sum of its three edge weights (the generic search of section 5 with three
+ * levels and no frontier bound).
  *   src, dst   device uint32[nq]
  *   k          device uint32[nq], or NULL to use opts->k for every query
  *   k_max      1..MHR_MAX_K; every k[q] must be <= k_max (else MHR_Q_BAD_K)
@@ -241,7 +248,8 @@ mhr_status mhr_topk_paths_profiled(const mhr_graph *g, const mhr_query_opts *opt
                                    const mhr_phase_events *ev);
 
 /* Pruned search: mhr_topk_paths restricted by keep flags, as a frontier
- * pruner decides them (the learned pruner below, or any other rule).
+ * pruner decides them (the learned pruner below, or any other rule; section
+ * 5 bounds each level's frontier, here the first and last levels).
  *   keep      device uint8 flags; for query q, keep[keep_off[q] + i] is the
  *             flag of entry i of s's out-row (i < deg+(s), forward CSR order)
  *             and keep[keep_off[q] + deg+(s) + j] that of entry j of t's
@@ -288,7 +296,8 @@ mhr_status mhr_plan_launch(mhr_plan *plan, void *stream);
 
 mhr_status mhr_plan_destroy(mhr_plan *plan);
 
-/* Autotuner.  Times mhr_topk_paths on the given batch for candidate values of
+/* Autotuner (an engineering addition; the paper tunes nothing).  Times
+ * mhr_topk_paths on the given batch for candidate values of
  * tile_edges and hash_log2 (the other fields of *base are kept), `reps` timed
  * runs each after one untimed run, and writes the fastest setting to *tuned
  * and its mean time per call (ms) to *best_ms (may be NULL).  Tuning never

@@ -37,7 +37,7 @@ MHR_OK = 0
 ERR_IO, ERR_CORRUPT, ERR_NOT_FOUND = 9, 10, 11
 MHR_MAX_K = 224
 NOALLOC_SCRATCH_BYTES = 64 << 20
-Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS, Q_OVERFLOW = 1, 2, 4, 8
+Q_BAD_ID, Q_BAD_K, Q_EXACT_PASS = 1, 2, 4
 PATH_RESCORED, PATH_PRECISION_TIE = 1, 2
 DTYPE_F32, DTYPE_BF16 = 0, 1
 SCORERS = {"distmult": 0, "transe_l1": 1}
@@ -832,4 +832,4 @@ class Plan:
 
 
 __all__ = ["BEAM_DTYPE", "beam_to_numpy", "TrainOpts", "Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "crc32", "pruner_file_info", "tuning_file_records", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
-           "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "Q_OVERFLOW", "PATH_RESCORED", "PATH_PRECISION_TIE"]
+           "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "PATH_RESCORED", "PATH_PRECISION_TIE"]
