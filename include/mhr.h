@@ -333,6 +333,93 @@ mhr_status mhr_tuning_load(const char *path, const mhr_graph *g, uint32_t nq, ui
 mhr_status mhr_tuning_file_records(const char *path, uint32_t *count);
 
 /* ---------------------------------------------------------------------------
+ * Wide-relation graphs (up to 65,535 relations).
+ *
+ * The paper's experiments search a knowledge graph of 91.23M entities, 1,387
+ * relations and 601.06M triples with 8-dimensional TransE embeddings
+ * (section 4.1).  mhr_graph keeps one 32-bit relation mask per vertex pair,
+ * which caps it at 32 relations.  A wide graph stores every distinct triple
+ * as its own CSR entry (neighbour id and 16-bit relation; rows sorted by
+ * (neighbour, relation), so the relations of one pair are consecutive) and
+ * scores edges with TransE-L1 (section 3.3) in FP64:
+ *     w(u, r, v) = gamma - sum_i |(X[u,i] + Y[r,i]) - X[v,i]|,
+ * every operation in FP64 in ascending i, and a path's score is
+ * S = w1 + w2 + w3 rounded once (the correctly rounded sum).  Scores are
+ * therefore exact functions of the inputs; paths are ranked by S
+ * descending, then a, b, r1, r2, r3 ascending (the problem of section 3.1).
+ * ------------------------------------------------------------------------- */
+#define MHR_WIDE_MAX_RELATIONS 65535u
+#define MHR_WIDE_MAX_K 256u
+
+typedef struct mhr_wide_graph mhr_wide_graph;
+
+/* Builds a wide graph from the triples in desc (num_relations in
+ * 1..65535, num_edges < 2^32; head/rel/tail device arrays read during the
+ * call only).  Identical triples are merged.  The handle owns the device
+ * memory it allocates: per direction (n + 1) * 4 + 6 bytes per distinct
+ * triple.  Synchronises `stream`.  Errors: INVALID_ARGUMENT, BAD_EDGE,
+ * OUT_OF_MEMORY, DEVICE. */
+mhr_status mhr_wide_graph_create(const mhr_graph_desc *desc, void *stream, mhr_wide_graph **out);
+mhr_status mhr_wide_graph_destroy(mhr_wide_graph *g);
+
+/* Attaches the TransE embeddings (section 3.3): entity[num_vertices][dim]
+ * and relation[num_relations][dim] row-major device arrays of dtype
+ * (FP32 or bfloat16 bits), BORROWED; dim in 1..1024; gamma finite (1.0 in
+ * the paper).  Enqueues nothing.  Errors: INVALID_ARGUMENT. */
+mhr_status mhr_wide_graph_set_embeddings(mhr_wide_graph *g, mhr_dtype dtype, uint32_t dim, const void *entity,
+                                         const void *relation, double gamma);
+
+typedef struct mhr_wide_stats {
+    uint32_t num_vertices, num_relations;
+    uint64_t num_triples;        /* distinct (h, r, t) */
+    uint32_t max_out_degree, max_in_degree;   /* in entries (triples) */
+    uint32_t dim, dtype;
+    uint64_t device_bytes;
+} mhr_wide_stats;
+
+mhr_status mhr_wide_graph_get_stats(const mhr_wide_graph *g, mhr_wide_stats *out);
+
+/* Copies one CSR into caller device buffers: row_ptr[num_vertices + 1],
+ * col[num_triples], rel[num_triples] (uint16).  reverse = 0: rows are heads;
+ * 1: rows are tails. */
+mhr_status mhr_wide_graph_export_csr(const mhr_wide_graph *g, int reverse, uint32_t *row_ptr, uint32_t *col,
+                                     uint16_t *rel, void *stream);
+
+/* One ranked path s -r1-> a -r2-> b -r3-> t (24 bytes).  Unused slots of an
+ * output row hold a = b = 0xFFFFFFFF, score = -inf. */
+typedef struct mhr_wide_path {
+    double score;   /* S, exact as defined above */
+    uint32_t a, b;
+    uint16_t r1, r2, r3, reserved;
+} mhr_wide_path;
+
+/* Device workspace bytes for mhr_wide_topk_paths on this batch (the same
+ * src, dst, k and k_max).  The size depends on the queries' frontiers, so
+ * the call plans the batch on the device and synchronises `stream`.
+ * Errors: as mhr_wide_topk_paths. */
+mhr_status mhr_wide_workspace_size(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                                   const uint32_t *k, uint32_t k_max, size_t *bytes, void *stream);
+
+/* Exact top-K three-hop paths for nq queries (the problem of section 3.1 on
+ * a wide graph).
+ *   src, dst   device uint32[nq]
+ *   k          device uint32[nq], or NULL for k_max on every query
+ *   k_max      1..MHR_WIDE_MAX_K
+ *   out        device mhr_wide_path[nq][k_max], best first
+ *   out_count  device uint32[nq]: min(k[q], |P(s,t)|)
+ *   out_total  device uint64[nq] or NULL: |P(s,t)|
+ *   out_status device uint32[nq] or NULL: MHR_Q_BAD_ID, MHR_Q_BAD_K
+ *   workspace  device buffer of ws_bytes >= mhr_wide_workspace_size(...)
+ * The call plans the batch, synchronises `stream` once to read the plan's
+ * totals, then enqueues the search and returns.  Allocates nothing.
+ * Errors: INVALID_ARGUMENT, NO_EMBEDDINGS, WORKSPACE_TOO_SMALL (nothing of
+ * the search enqueued), UNSUPPORTED, DEVICE. */
+mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
+                               const uint32_t *k, uint32_t k_max, mhr_wide_path *out, uint32_t *out_count,
+                               uint64_t *out_total, uint32_t *out_status, void *workspace, size_t ws_bytes,
+                               void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned frontier pruner.
  *
  * The generic search of section 5 bounds each level's frontier by a per-

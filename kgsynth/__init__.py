@@ -396,3 +396,99 @@ def turing_workload(spec: TuringSpec):
     award, field = int(ids[-2]), int(ids[-1])
     rels = rng.choice(spec.R, 3, replace=False)
     return X, Y, persons, univ, award, field, tuple(int(x) for x in rels)
+
+
+# ---------------------------------------------------------------------------
+# wide-relation knowledge graphs (the scale of the paper's WikiKG90Mv2
+# experiments: 91,230,610 entities, 1,387 relations, 601,062,811 triples,
+# 8-dimensional embeddings; section 4.1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class WideSpec:
+    n: int
+    R: int
+    m: int                  # triples drawn (duplicates are merged at ingest)
+    seed: int
+    out_gamma: float = 2.5  # power-law exponent of the out-degree distribution
+    in_gamma: float = 2.2   # and of the in-degree distribution (hubs are targets)
+    rel_power: float = 4.0  # relation rank = floor(R * u^rel_power): a few relations dominate
+    d: int = 8
+    dtype: str = "f32"
+
+
+WIDE = {
+    # the paper's graph size
+    "paper_kg": WideSpec(91_230_610, 1_387, 601_062_811, seed=2406),
+    # one sixteenth of it, same shape
+    "paper_kg_16th": WideSpec(5_701_913, 1_387, 37_566_425, seed=2407),
+    # small graphs for parity tests: many relations per pair, hubs past one tile
+    "wide_tiny": WideSpec(60, 40, 1_500, seed=11, out_gamma=3.0, in_gamma=3.0, rel_power=1.5),
+    "wide_small": WideSpec(20_000, 1_387, 300_000, seed=12),
+    "wide_hub": WideSpec(6_000, 300, 500_000, seed=13, out_gamma=2.1, in_gamma=2.0),
+    "wide_small_bf16": WideSpec(20_000, 1_387, 300_000, seed=14, dtype="bf16"),
+}
+
+
+def _scatter_ids(rank: np.ndarray, n: int, mult: int, add: int) -> np.ndarray:
+    """A fixed bijection of [0, n) (x -> (mult x + add) mod n with mult
+    coprime to n), so that the highest-weight ranks land on unrelated ids."""
+    while math.gcd(mult, n) != 1:
+        mult += 2
+    return ((rank.astype(np.uint64) * np.uint64(mult) + np.uint64(add)) % np.uint64(n)).astype(np.uint32)
+
+
+def powerlaw_ranks(u: np.ndarray, n: int, gamma: float) -> np.ndarray:
+    """Vertex ranks drawn with probability density proportional to
+    (x + 1)^(-1 / (gamma - 1)) on [0, n) (the expected-degree sequence of a
+    Chung-Lu graph whose degrees follow a power law of exponent gamma), by
+    inverting the continuous distribution function at the uniforms u."""
+    beta = 1.0 / (gamma - 1.0)
+    e = 1.0 - beta
+    if abs(e) < 1e-9:   # density 1 / (x + 1): the distribution function is logarithmic
+        x = (n + 1.0) ** u - 1.0
+    else:
+        lo, hi = 1.0, (n + 1.0) ** e
+        x = (lo + u * (hi - lo)) ** (1.0 / e) - 1.0
+    return np.minimum(x.astype(np.int64), n - 1)
+
+
+def wide_graph(spec: WideSpec, chunk: int = 1 << 24):
+    """(head, rel, tail) uint32 arrays of spec.m triples, drawn in chunks
+    from one generator: heads and tails from power laws over scattered ids,
+    relations by rank."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    head = np.empty(spec.m, np.uint32)
+    rel = np.empty(spec.m, np.uint32)
+    tail = np.empty(spec.m, np.uint32)
+    for c0 in range(0, spec.m, chunk):
+        c1 = min(spec.m, c0 + chunk)
+        u = rng.random((3, c1 - c0))
+        head[c0:c1] = _scatter_ids(powerlaw_ranks(u[0], spec.n, spec.out_gamma), spec.n, 2654435761, 12345)
+        tail[c0:c1] = _scatter_ids(powerlaw_ranks(u[1], spec.n, spec.in_gamma), spec.n, 40503 * 65537, 777)
+        rel[c0:c1] = np.minimum((spec.R * u[2] ** spec.rel_power).astype(np.int64), spec.R - 1)
+    return head, rel, tail
+
+
+def wide_embeddings(spec: WideSpec, chunk_rows: int = 1 << 22):
+    """X [n][d], Y [R][d]: normal entries of variance 1/d, float32 (or
+    bfloat16 bit patterns)."""
+    return embeddings(spec.n, spec.R, EmbSpec(spec.d, spec.dtype, seed=spec.seed + 1), chunk_rows)
+
+
+def wide_queries(head: np.ndarray, tail: np.ndarray, nq: int, seed: int):
+    """Query pairs (s, t): the head of one uniformly drawn triple and the
+    tail of another (sources and targets in proportion to their degrees)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    i = rng.integers(0, len(head), nq)
+    j = rng.integers(0, len(tail), nq)
+    return head[i].astype(np.uint32), tail[j].astype(np.uint32)
+
+
+def wide_subgraph(head, rel, tail, s: int, t: int):
+    """The triples any three-hop path s -> a -> b -> t can use: the out-edges
+    of s, the out-edges of its out-neighbours and the in-edges of t."""
+    first = head == s
+    mids = np.unique(tail[first])
+    keep = first | np.isin(head, mids) | (tail == t)
+    return head[keep], rel[keep], tail[keep]

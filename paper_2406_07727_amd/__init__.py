@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass
-from typing import Optional
+from typing import NamedTuple, Optional
 
 import numpy as np
 
@@ -172,6 +172,20 @@ _lib.mhr_beam_workspace_size.restype = _i
 _lib.mhr_beam_workspace_size.argtypes = [_vp, _u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.mhr_beam_search.restype = _i
 _lib.mhr_beam_search.argtypes = [_vp, _u32, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_wide_graph_create.restype = _i
+_lib.mhr_wide_graph_create.argtypes = [ctypes.POINTER(_GraphDesc), _vp, ctypes.POINTER(_vp)]
+_lib.mhr_wide_graph_destroy.restype = _i
+_lib.mhr_wide_graph_destroy.argtypes = [_vp]
+_lib.mhr_wide_graph_set_embeddings.restype = _i
+_lib.mhr_wide_graph_set_embeddings.argtypes = [_vp, _i, _u32, _vp, _vp, ctypes.c_double]
+_lib.mhr_wide_graph_get_stats.restype = _i
+_lib.mhr_wide_graph_get_stats.argtypes = [_vp, _vp]
+_lib.mhr_wide_graph_export_csr.restype = _i
+_lib.mhr_wide_graph_export_csr.argtypes = [_vp, _i, _vp, _vp, _vp, _vp]
+_lib.mhr_wide_workspace_size.restype = _i
+_lib.mhr_wide_workspace_size.argtypes = [_vp, _u32, _vp, _vp, _vp, _u32, ctypes.POINTER(ctypes.c_size_t), _vp]
+_lib.mhr_wide_topk_paths.restype = _i
+_lib.mhr_wide_topk_paths.argtypes = [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.mhr_scan_workspace_size.restype = _i
 _lib.mhr_scan_workspace_size.argtypes = [_u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.mhr_scan_topk.restype = _i
@@ -663,6 +677,121 @@ class Pruner:
         return loss
 
 
+WIDE_MAX_K = 256
+WIDE_PATH_DTYPE = np.dtype([("score", np.float64), ("a", np.uint32), ("b", np.uint32), ("r1", np.uint16),
+                            ("r2", np.uint16), ("r3", np.uint16), ("reserved", np.uint16)])
+assert WIDE_PATH_DTYPE.itemsize == 24
+
+
+class _WideStats(ctypes.Structure):
+    _fields_ = [("num_vertices", _u32), ("num_relations", _u32), ("num_triples", ctypes.c_uint64),
+                ("max_out_degree", _u32), ("max_in_degree", _u32), ("dim", _u32), ("dtype", _u32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class WideResult(NamedTuple):
+    paths: object    # device uint8 [nq][k_max * 24] (mhr_wide_path records)
+    count: object
+    total: object
+    status: object
+
+    def to_numpy(self):
+        """(paths [nq][k_max] of WIDE_PATH_DTYPE, count, total, status)."""
+        nq = self.count.numel()
+        p = self.paths.cpu().numpy().view(WIDE_PATH_DTYPE).reshape(nq, -1)
+        return (p, self.count.cpu().numpy().view(np.uint32), self.total.cpu().numpy().view(np.uint64),
+                self.status.cpu().numpy().view(np.uint32))
+
+
+class WideGraph:
+    """A knowledge graph with up to 65,535 relations (one CSR entry per
+    distinct triple), searched with TransE-L1 scores in FP64
+    (include/mhr.h, wide-relation graphs)."""
+
+    def __init__(self, head, rel, tail, num_vertices: int, num_relations: int, stream=None):
+        torch = _torch()
+        h, r, t = _dev_u32(head), _dev_u32(rel), _dev_u32(tail)
+        if not (h.numel() == r.numel() == t.numel()):
+            raise ValueError("head, rel and tail must have the same length")
+        desc = _GraphDesc(int(num_vertices), int(num_relations), int(h.numel()),
+                          h.data_ptr(), r.data_ptr(), t.data_ptr())
+        handle = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(_lib.mhr_wide_graph_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(handle)),
+               "mhr_wide_graph_create")
+        self._h = handle
+        self.n = int(num_vertices)
+        self.R = int(num_relations)
+        self._emb = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.mhr_wide_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_embeddings(self, entity, relation, gamma: float = 1.0, dtype: Optional[str] = None):
+        torch = _torch()
+        if dtype is None:
+            dtype = "f32" if entity.dtype == torch.float32 else "bf16"
+        X, Y = entity.contiguous(), relation.contiguous()
+        if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1] or X.shape[0] != self.n or Y.shape[0] != self.R:
+            raise ValueError("embedding tables must be [n][d] and [R][d] matching the graph")
+        _check(_lib.mhr_wide_graph_set_embeddings(self._h, DTYPE_F32 if dtype == "f32" else DTYPE_BF16,
+                                                  int(X.shape[1]), X.data_ptr(), Y.data_ptr(), float(gamma)),
+               "mhr_wide_graph_set_embeddings")
+        self._emb = (X, Y)
+        self.dim = int(X.shape[1])
+
+    def stats(self) -> dict:
+        st = _WideStats()
+        _check(_lib.mhr_wide_graph_get_stats(self._h, ctypes.byref(st)), "mhr_wide_graph_get_stats")
+        return {f: getattr(st, f) for f, _ in _WideStats._fields_}
+
+    def export_csr(self, reverse: bool = False, stream=None):
+        torch = _torch()
+        st = self.stats()
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(st["num_triples"], 1), dtype=torch.int32, device="cuda")
+        rel = torch.empty(max(st["num_triples"], 1), dtype=torch.int16, device="cuda")
+        _check(_lib.mhr_wide_graph_export_csr(self._h, 1 if reverse else 0, rp.data_ptr(), col.data_ptr(),
+                                              rel.data_ptr(), _stream_ptr(stream)), "mhr_wide_graph_export_csr")
+        return rp, col[:st["num_triples"]], rel[:st["num_triples"]]
+
+    def workspace_size(self, src, dst, k_max: int, k=None, stream=None) -> int:
+        s, d = _dev_u32(src), _dev_u32(dst)
+        kk = _dev_u32(k) if k is not None else None
+        b = ctypes.c_size_t()
+        _check(_lib.mhr_wide_workspace_size(self._h, s.numel(), _ptr(s), _ptr(d), _ptr(kk), int(k_max),
+                                            ctypes.byref(b), _stream_ptr(stream)), "mhr_wide_workspace_size")
+        return int(b.value)
+
+    def topk(self, src, dst, k_max: int, k=None, workspace=None, stream=None) -> WideResult:
+        """Exact top-K paths of each query (src[q], dst[q]); k: per-query K
+        (None: k_max for all).  workspace: a device uint8 tensor of at least
+        workspace_size() bytes, or None to allocate one."""
+        torch = _torch()
+        s, d = _dev_u32(src), _dev_u32(dst)
+        kk = _dev_u32(k) if k is not None else None
+        nq = s.numel()
+        if workspace is None:
+            workspace = torch.empty(max(self.workspace_size(s, d, k_max, kk, stream), 1), dtype=torch.uint8,
+                                    device="cuda")
+        paths = torch.empty((nq, int(k_max) * 24), dtype=torch.uint8, device="cuda")
+        count = torch.empty(nq, dtype=torch.int32, device="cuda")
+        total = torch.empty(nq, dtype=torch.int64, device="cuda")
+        status = torch.empty(nq, dtype=torch.int32, device="cuda")
+        _check(_lib.mhr_wide_topk_paths(self._h, nq, _ptr(s), _ptr(d), _ptr(kk), int(k_max), _ptr(paths),
+                                        _ptr(count), _ptr(total), _ptr(status), _ptr(workspace), workspace.numel(),
+                                        _stream_ptr(stream)), "mhr_wide_topk_paths")
+        return WideResult(paths, count, total, status)
+
+
 def beam_to_numpy(out, cnt, rec):
     """Host copies of mhr_beam_search's results: (paths [nq][k] of
     BEAM_DTYPE, count, recorded)."""
@@ -831,5 +960,5 @@ class Plan:
             pass
 
 
-__all__ = ["BEAM_DTYPE", "beam_to_numpy", "TrainOpts", "Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "crc32", "pruner_file_info", "tuning_file_records", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
+__all__ = ["WideGraph", "WideResult", "WIDE_PATH_DTYPE", "WIDE_MAX_K", "BEAM_DTYPE", "beam_to_numpy", "TrainOpts", "Graph", "Plan", "Pruner", "scan_topk", "ScanPipeline", "crc32", "pruner_file_info", "tuning_file_records", "Candidates", "candidates", "select", "TopK", "QueryOpts", "PhaseEvents", "MhrError", "PATH_DTYPE", "LIB_PATH", "MHR_MAX_K",
            "Q_BAD_ID", "Q_BAD_K", "Q_EXACT_PASS", "PATH_RESCORED", "PATH_PRECISION_TIE"]

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmhr.so")
 PHASE_LIB = os.path.join(HERE, "libmhr_phase.so")
-SOURCES = ["mhr_api.hip", "mhr_graph.hip", "mhr_query.hip", "mhr_plan.hip", "mhr_pruner.hip", "mhr_scan.hip", "mhr_files.hip", "mhr_beam.hip"]
+SOURCES = ["mhr_api.hip", "mhr_graph.hip", "mhr_query.hip", "mhr_plan.hip", "mhr_pruner.hip", "mhr_scan.hip", "mhr_files.hip", "mhr_beam.hip", "mhr_wide.hip"]
 ARCH = os.environ.get("MHR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

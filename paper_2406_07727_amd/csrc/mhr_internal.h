@@ -54,6 +54,12 @@ struct Csr {
 
 constexpr uint32_t kDirMinDegree = 512;
 
+// Exclusive scan of n uint32 on the device (out may equal in); the grand
+// total goes to *d_total when it is not null.  scratch holds
+// n / 2048 + 1 uint32.
+mhr_status device_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *d_total,
+                                 uint32_t *scratch, hipStream_t st);
+
 }  // namespace mhr
 
 struct mhr_graph {

@@ -1,0 +1,199 @@
+"""GPU parity of the wide-relation path (include/mhr.h, wide-relation
+graphs: more than 32 relations, TransE-L1 in FP64) against the oracle.
+Scores are exact functions of the inputs on both sides, so paths, scores,
+counts and totals must agree bit for bit."""
+
+import numpy as np
+import pytest
+
+import kgsynth
+import oracle
+from tests.parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2406_07727_amd  # noqa: F401
+
+
+def _wide(name):
+    sp = kgsynth.WIDE[name]
+    h, r, t = kgsynth.wide_graph(sp)
+    X, Y = kgsynth.wide_embeddings(sp)
+    return sp, (h, r, t), (X, Y)
+
+
+def _gpu_graph(sp, h, r, t, X, Y, gamma=1.0):
+    import torch
+    import paper_2406_07727_amd as mhr
+    g = mhr.WideGraph(h, r, t, sp.n, sp.R)
+    if sp.dtype == "bf16":
+        Xt = torch.from_numpy(X.view(np.int16)).cuda()
+        Yt = torch.from_numpy(Y.view(np.int16)).cuda()
+    else:
+        Xt = torch.from_numpy(X).cuda()
+        Yt = torch.from_numpy(Y).cuda()
+    g.set_embeddings(Xt, Yt, gamma=gamma, dtype=sp.dtype)
+    return g
+
+
+def _f32(sp, T):
+    return oracle.as_f32_table(T, sp.dtype)
+
+
+def _compare(res, orc, k):
+    """Bit-exact agreement of counts, totals and every returned path."""
+    p, c, tot, st = res
+    op, oc, ot = orc
+    nq = len(c)
+    kk = np.broadcast_to(np.asarray(k), (nq,))
+    for q in range(nq):
+        assert int(st[q]) == 0, q
+        assert int(tot[q]) == int(ot[q]), (q, int(tot[q]), int(ot[q]))
+        assert int(c[q]) == int(oc[q]) == min(int(kk[q]), int(ot[q])), q
+        n = int(c[q])
+        g = p[q][:n]
+        o = op[q][:n]
+        assert np.array_equal(g["score"], o["s"]), q
+        for f in ("a", "b", "r1", "r2", "r3"):
+            assert np.array_equal(g[f].astype(np.uint32), o[f]), (q, f)
+        rest = p[q][n:]
+        assert np.all(rest["a"] == 0xFFFFFFFF) and np.all(np.isneginf(rest["score"]))
+    return int(np.sum(c)), int(np.sum(tot))
+
+
+def test_wide_tiny_all_pairs():
+    sp, (h, r, t), (X, Y) = _wide("wide_tiny")
+    say("case wide tiny all pairs")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    src = np.repeat(np.arange(sp.n, dtype=np.uint32), sp.n)
+    dst = np.tile(np.arange(sp.n, dtype=np.uint32), sp.n)
+    K = 16
+    res = g.topk(src, dst, K).to_numpy()
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(X, Y, src, dst, K, scorer="transe_l1")
+    nret, ntot = _compare(res, orc, K)
+    say(f"wide tiny: {len(src)} queries, {nret} paths returned of {ntot}")
+    assert ntot > 1000 and int(r.max()) >= 32
+
+
+@pytest.mark.parametrize("K", [1, 8, 32, 256])
+def test_wide_small_k(K):
+    sp, (h, r, t), (X, Y) = _wide("wide_small")
+    say(f"case wide small K={K}")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    src, dst = kgsynth.wide_queries(h, t, 160, seed=21)
+    res = g.topk(src, dst, K).to_numpy()
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(X, Y, src, dst, K, scorer="transe_l1")
+    _, ntot = _compare(res, orc, K)
+    assert ntot > 0
+
+
+def test_wide_mixed_k_and_gamma():
+    sp, (h, r, t), (X, Y) = _wide("wide_small")
+    say("case wide mixed k, gamma 2.5")
+    g = _gpu_graph(sp, h, r, t, X, Y, gamma=2.5)
+    src, dst = kgsynth.wide_queries(h, t, 200, seed=22)
+    k = np.random.Generator(np.random.PCG64(5)).integers(1, 65, len(src)).astype(np.uint32)
+    res = g.topk(src, dst, 64, k=k).to_numpy()
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(X, Y, src, dst, k, scorer="transe_l1", gamma=2.5)
+    _compare(res, orc, k)
+
+
+def test_wide_bf16_tables():
+    sp, (h, r, t), (X, Y) = _wide("wide_small_bf16")
+    say("case wide bf16")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    src, dst = kgsynth.wide_queries(h, t, 128, seed=23)
+    res = g.topk(src, dst, 32).to_numpy()
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(_f32(sp, X), _f32(sp, Y), src, dst, 32, scorer="transe_l1")
+    _compare(res, orc, 32)
+
+
+def test_wide_hubs_many_tiles_and_long_probe_rows():
+    """Hub sources and targets: scans of many tiles per query and probe
+    rows longer than the LDS copy (searched in global memory)."""
+    sp, (h, r, t), (X, Y) = _wide("wide_hub")
+    say("case wide hubs")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    st = g.stats()
+    assert st["max_in_degree"] > 4096 and st["max_out_degree"] > 4096
+    od = np.bincount(h, minlength=sp.n)
+    idg = np.bincount(t, minlength=sp.n)
+    hubs_out = np.argsort(-od)[:4].astype(np.uint32)
+    hubs_in = np.argsort(-idg)[:4].astype(np.uint32)
+    s1, d1 = kgsynth.wide_queries(h, t, 40, seed=24)
+    src = np.concatenate([s1, hubs_out, hubs_out, np.repeat(hubs_out[:2], 2)]).astype(np.uint32)
+    dst = np.concatenate([d1, hubs_in, d1[:4], np.tile(hubs_in[:2], 2)]).astype(np.uint32)
+    res = g.topk(src, dst, 32).to_numpy()
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(X, Y, src, dst, 32, scorer="transe_l1")
+    _, ntot = _compare(res, orc, 32)
+    say(f"wide hubs: {ntot} paths over {len(src)} queries")
+    assert ntot > 1_000_000
+
+
+def test_wide_bad_queries_and_empty_results():
+    import paper_2406_07727_amd as mhr
+    sp, (h, r, t), (X, Y) = _wide("wide_tiny")
+    say("case wide bad queries")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    src = np.array([sp.n, 0, 1, 2, 3], np.uint32)
+    dst = np.array([0, sp.n + 7, 2, 3, 3], np.uint32)
+    k = np.array([4, 4, 0, 9, 4], np.uint32)
+    p, c, tot, st = g.topk(src, dst, 8, k=k).to_numpy()
+    assert list(st) == [mhr.Q_BAD_ID, mhr.Q_BAD_ID, mhr.Q_BAD_K, mhr.Q_BAD_K, 0]
+    assert list(c[:4]) == [0, 0, 0, 0] and list(tot[:4]) == [0, 0, 0, 0]
+    orc = oracle.Graph(sp.n, sp.R, h, r, t).topk(X, Y, src[4:], dst[4:], k[4:], scorer="transe_l1")
+    _compare((p[4:], c[4:], tot[4:], st[4:]), orc, k[4:])
+    with pytest.raises(mhr.MhrError):
+        g.topk(src, dst, mhr.WIDE_MAX_K + 1)
+
+
+def test_wide_graph_without_edges():
+    import torch
+    import paper_2406_07727_amd as mhr
+    say("case wide empty graph")
+    e = np.zeros(0, np.uint32)
+    g = mhr.WideGraph(e, e, e, 10, 50)
+    g.set_embeddings(torch.zeros(10, 8, device="cuda"), torch.zeros(50, 8, device="cuda"))
+    p, c, tot, st = g.topk(np.arange(10, dtype=np.uint32), np.arange(10, dtype=np.uint32)[::-1].copy(), 4).to_numpy()
+    assert not c.any() and not tot.any() and not st.any()
+
+
+def test_wide_csr_matches_numpy_construction():
+    sp, (h, r, t), (X, Y) = _wide("wide_small")
+    say("case wide csr")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    trip = np.unique(np.stack([h, r, t], 1).astype(np.int64), axis=0)
+    assert g.stats()["num_triples"] == len(trip)
+    for reverse in (False, True):
+        rp, col, rel = (x.cpu().numpy() for x in g.export_csr(reverse))
+        u = trip[:, 2] if reverse else trip[:, 0]
+        v = trip[:, 0] if reverse else trip[:, 2]
+        order = np.lexsort((trip[:, 1], v, u))
+        assert np.array_equal(rp.view(np.uint32).astype(np.int64), np.concatenate([[0], np.cumsum(np.bincount(u, minlength=sp.n))]))
+        assert np.array_equal(col.view(np.uint32), v[order].astype(np.uint32))
+        assert np.array_equal(rel.view(np.uint16), trip[order, 1].astype(np.uint16))
+
+
+@pytest.mark.timeout(600)
+def test_wide_sixteenth_of_paper_scale_sample():
+    """A graph of one sixteenth of the paper's size (5.7M entities, 1,387
+    relations, 37.6M triples, d = 8): sampled queries against the oracle on
+    each query's subgraph (the triples its paths can use)."""
+    sp, (h, r, t), (X, Y) = _wide("paper_kg_16th")
+    say("case wide 1/16 paper scale")
+    g = _gpu_graph(sp, h, r, t, X, Y)
+    src, dst = kgsynth.wide_queries(h, t, 256, seed=25)
+    res = g.topk(src, dst, 32).to_numpy()
+    checked = 0
+    for q in range(0, len(src), 16):
+        sh, sr, st = kgsynth.wide_subgraph(h, r, t, int(src[q]), int(dst[q]))
+        orc = oracle.Graph(sp.n, sp.R, sh, sr, st).topk(X, Y, src[q:q + 1], dst[q:q + 1], 32, scorer="transe_l1")
+        _compare(tuple(x[q:q + 1] for x in res), orc, 32)
+        checked += 1
+    say(f"wide 1/16 scale: {checked} sampled queries equal the oracle; {int(res[2].sum())} paths in the batch")
