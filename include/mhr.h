@@ -393,6 +393,18 @@ typedef struct mhr_wide_path {
     uint16_t r1, r2, r3, reserved;
 } mhr_wide_path;
 
+/* Work of one query (diagnostics and the benchmark's byte counts). */
+typedef struct mhr_wide_work {
+    uint64_t scanned;    /* adjacency entries scanned in the middle hop */
+    uint64_t matches;    /* of those, entries whose neighbour lies in the probe row */
+    uint64_t paths;      /* |P(s,t)| */
+    uint64_t frontier;   /* |out(s)| + |in(t)| entries (weighted once each) */
+    uint64_t distinct;   /* distinct list-side vertices whose rows were scanned */
+    uint64_t probe_len;  /* entries of the probe row */
+    uint64_t tiles;      /* work tiles of the query */
+    uint64_t forward;    /* 1: scanned out-rows of out(s); 0: in-rows of in(t) */
+} mhr_wide_work;
+
 /* Device workspace bytes for mhr_wide_topk_paths on this batch (the same
  * src, dst, k and k_max).  The size depends on the queries' frontiers, so
  * the call plans the batch on the device and synchronises `stream`.
@@ -409,15 +421,19 @@ mhr_status mhr_wide_workspace_size(const mhr_wide_graph *g, uint32_t nq, const u
  *   out_count  device uint32[nq]: min(k[q], |P(s,t)|)
  *   out_total  device uint64[nq] or NULL: |P(s,t)|
  *   out_status device uint32[nq] or NULL: MHR_Q_BAD_ID, MHR_Q_BAD_K
+ *   out_work   device mhr_wide_work[nq] or NULL
  *   workspace  device buffer of ws_bytes >= mhr_wide_workspace_size(...)
+ *   ev         phase events or NULL: begin before planning, gather_begin and
+ *              gather_end around the tile kernel (after the frontier
+ *              kernel), end after the merge
  * The call plans the batch, synchronises `stream` once to read the plan's
  * totals, then enqueues the search and returns.  Allocates nothing.
  * Errors: INVALID_ARGUMENT, NO_EMBEDDINGS, WORKSPACE_TOO_SMALL (nothing of
  * the search enqueued), UNSUPPORTED, DEVICE. */
 mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                                const uint32_t *k, uint32_t k_max, mhr_wide_path *out, uint32_t *out_count,
-                               uint64_t *out_total, uint32_t *out_status, void *workspace, size_t ws_bytes,
-                               void *stream);
+                               uint64_t *out_total, uint32_t *out_status, mhr_wide_work *out_work,
+                               void *workspace, size_t ws_bytes, void *stream, const mhr_phase_events *ev);
 
 /* ---------------------------------------------------------------------------
  * Learned frontier pruner.

@@ -185,7 +185,8 @@ _lib.mhr_wide_graph_export_csr.argtypes = [_vp, _i, _vp, _vp, _vp, _vp]
 _lib.mhr_wide_workspace_size.restype = _i
 _lib.mhr_wide_workspace_size.argtypes = [_vp, _u32, _vp, _vp, _vp, _u32, ctypes.POINTER(ctypes.c_size_t), _vp]
 _lib.mhr_wide_topk_paths.restype = _i
-_lib.mhr_wide_topk_paths.argtypes = [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.mhr_wide_topk_paths.argtypes = [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                                     _vp]
 _lib.mhr_scan_workspace_size.restype = _i
 _lib.mhr_scan_workspace_size.argtypes = [_u32, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.mhr_scan_topk.restype = _i
@@ -689,11 +690,19 @@ class _WideStats(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+WIDE_WORK_FIELDS = ("scanned", "matches", "paths", "frontier", "distinct", "probe_len", "tiles", "forward")
+
+
 class WideResult(NamedTuple):
     paths: object    # device uint8 [nq][k_max * 24] (mhr_wide_path records)
     count: object
     total: object
     status: object
+    work: object     # device int64 [nq][8] (mhr_wide_work records)
+
+    def work_numpy(self) -> dict:
+        w = self.work.cpu().numpy().view(np.uint64)
+        return {f: w[:, i] for i, f in enumerate(WIDE_WORK_FIELDS)}
 
     def to_numpy(self):
         """(paths [nq][k_max] of WIDE_PATH_DTYPE, count, total, status)."""
@@ -771,7 +780,7 @@ class WideGraph:
                                             ctypes.byref(b), _stream_ptr(stream)), "mhr_wide_workspace_size")
         return int(b.value)
 
-    def topk(self, src, dst, k_max: int, k=None, workspace=None, stream=None) -> WideResult:
+    def topk(self, src, dst, k_max: int, k=None, workspace=None, stream=None, events=None) -> WideResult:
         """Exact top-K paths of each query (src[q], dst[q]); k: per-query K
         (None: k_max for all).  workspace: a device uint8 tensor of at least
         workspace_size() bytes, or None to allocate one."""
@@ -786,10 +795,12 @@ class WideGraph:
         count = torch.empty(nq, dtype=torch.int32, device="cuda")
         total = torch.empty(nq, dtype=torch.int64, device="cuda")
         status = torch.empty(nq, dtype=torch.int32, device="cuda")
+        work = torch.empty((nq, len(WIDE_WORK_FIELDS)), dtype=torch.int64, device="cuda")
+        ev = ctypes.byref(events) if events is not None else None
         _check(_lib.mhr_wide_topk_paths(self._h, nq, _ptr(s), _ptr(d), _ptr(kk), int(k_max), _ptr(paths),
-                                        _ptr(count), _ptr(total), _ptr(status), _ptr(workspace), workspace.numel(),
-                                        _stream_ptr(stream)), "mhr_wide_topk_paths")
-        return WideResult(paths, count, total, status)
+                                        _ptr(count), _ptr(total), _ptr(status), _ptr(work), _ptr(workspace),
+                                        workspace.numel(), _stream_ptr(stream), ev), "mhr_wide_topk_paths")
+        return WideResult(paths, count, total, status, work)
 
 
 def beam_to_numpy(out, cnt, rec):

@@ -23,12 +23,12 @@
 //             (sum of the scanned rows' lengths over distinct frontier
 //             vertices), the cheaper direction, its tile count
 //   offsets   exclusive scans over the batch (one workgroup)
-//   front     per query: the weights of every out(s) and in(t) entry, and
-//             the table of distinct list-side vertices with their scan-row
-//             prefix sums
+//   table     per query: the distinct list-side vertices with their
+//             scan-row prefix sums, and the tile map
 //   gather    persistent workgroups take tiles of scan entries, look each
-//             scanned neighbour up in the probe row (LDS copy or global
-//             binary search), score the paths through every match and keep
+//             scanned neighbour up in the probe row (an LDS copy when it is
+//             short, else the neighbour's own row), score the paths through
+//             every match (edge weights computed where used) and keep
 //             the tile's best K in LDS (staging buffer plus bitonic merges,
 //             pruned by the query's best known K-th score)
 //   merge     one wave per query: K-way merge of the tiles' sorted lists
@@ -393,7 +393,7 @@ __device__ __forceinline__ bool wbetter(const WCand &x, const WCand &y) {
 constexpr int kWBlock = 256;
 constexpr uint32_t kWTile = 16384;      // scan entries per tile
 constexpr uint32_t kWSub = 512;         // scan entries per staged sub-chunk
-constexpr uint32_t kWProbeLds = 4096;   // probe rows up to this length are copied to LDS
+constexpr uint32_t kWProbeLds = 2048;   // probe rows up to this length may be copied to LDS
 constexpr uint32_t kWPathsMin = 512;    // candidate buffer (list + staging) is max(512, 2K) rounded up to 2^j
 
 struct WPlan {
@@ -405,11 +405,11 @@ struct WPlan {
     uint32_t nd;                    // distinct list vertices with a nonempty scan row
     uint32_t ntiles, tile_base;
     uint64_t cost;                  // scan entries
-    uint64_t front_off, tab_off;
+    uint64_t tab_off;
 };
 
 struct WTotals {
-    unsigned long long front, nd, tiles, ctr;
+    unsigned long long nd, tiles, ctr;
 };
 
 struct WRow {
@@ -427,7 +427,7 @@ struct WArgs {
     WTotals *tot;
     uint64_t *gthr;     // per query: order key of the best known K-th score
     uint64_t *qtotal;   // per query: paths counted
-    double *front;
+    uint64_t *qmatch;   // per query: scanned entries found in the probe row
     WRow *tab;
     uint32_t *tile_q, *tile_n, *head;
     WCand *slots;       // [tile][k_max]
@@ -466,6 +466,36 @@ __device__ inline T wblock_excl(T v, T *red, T *total) {
     return base + x - v;
 }
 
+constexpr uint32_t kWSeg = 16;                 // row entries per thread per planning step
+constexpr uint32_t kWChunk = kWBlock * kWSeg;  // row entries per planning step
+
+// Over the entries [i0, min(i0 + kWSeg, end)) of the row [beg, end): the
+// scan lengths (rows of the same CSR) of the distinct vertices starting a
+// run there, and how many of those are nonempty.
+// All loads of the segment are issued together (ids first, then the row
+// bounds of the run starts), so a thread waits for memory twice per segment.
+__device__ __forceinline__ void seg_cost(const uint32_t *col, const uint32_t *rp, uint32_t beg, uint32_t end,
+                                         uint32_t i0, unsigned long long &cost, unsigned long long &nd) {
+    if (i0 >= end) return;
+    uint32_t xs[kWSeg + 1];
+    xs[0] = i0 > beg ? col[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) xs[j + 1] = (i0 + j < end) ? col[i0 + j] : 0xFFFFFFFFu;
+    uint32_t lo[kWSeg], hi[kWSeg];
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) {
+        const bool first = i0 + j < end && xs[j + 1] != xs[j];
+        lo[j] = first ? rp[xs[j + 1]] : 0u;
+        hi[j] = first ? rp[xs[j + 1] + 1] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) {
+        const uint32_t dg = hi[j] - lo[j];
+        cost += dg;
+        nd += dg ? 1 : 0;
+    }
+}
+
 __global__ __launch_bounds__(kWBlock) void wide_plan_kernel(WArgs A, const uint32_t *src, const uint32_t *dst,
                                                             const uint32_t *kq) {
     __shared__ unsigned long long red[kWBlock / kWave];
@@ -484,33 +514,31 @@ __global__ __launch_bounds__(kWBlock) void wide_plan_kernel(WArgs A, const uint3
         os1 = A.out_rp[s + 1];
         it0 = A.in_rp[t];
         it1 = A.in_rp[t + 1];
-        if (os1 > os0 && it1 > it0) {
-            for (uint32_t i = os0 + threadIdx.x; i < os1; i += kWBlock) {
-                const uint32_t a = A.out_col[i];
-                if (i == os0 || A.out_col[i - 1] != a) {
-                    const uint32_t dg = A.out_rp[a + 1] - A.out_rp[a];
-                    cf += dg;
-                    nf += dg ? 1 : 0;
-                }
-            }
-            for (uint32_t i = it0 + threadIdx.x; i < it1; i += kWBlock) {
-                const uint32_t b = A.in_col[i];
-                if (i == it0 || A.in_col[i - 1] != b) {
-                    const uint32_t dg = A.in_rp[b + 1] - A.in_rp[b];
-                    cb += dg;
-                    nb += dg ? 1 : 0;
-                }
-            }
+    }
+    // Both rows are summed in lockstep chunks; once one side is complete and
+    // the other's partial sum has reached it, the other cannot be cheaper and
+    // is not read further (a hub row of millions of entries is then left
+    // after its first chunks).
+    bool fdone = true, bdone = true;
+    if (P.status == 0 && os1 > os0 && it1 > it0) {
+        fdone = bdone = false;
+        for (uint32_t c = 0;; c += kWChunk) {
+            unsigned long long pf = 0, pb = 0, qf = 0, qb = 0;
+            if (!fdone) seg_cost(A.out_col, A.out_rp, os0, os1, os0 + c + threadIdx.x * kWSeg, pf, qf);
+            if (!bdone) seg_cost(A.in_col, A.in_rp, it0, it1, it0 + c + threadIdx.x * kWSeg, pb, qb);
+            cf += wblock_sum(pf, red);
+            cb += wblock_sum(pb, red);
+            nf += wblock_sum(qf, red);
+            nb += wblock_sum(qb, red);
+            fdone = fdone || os0 + c + kWChunk >= os1;
+            bdone = bdone || it0 + c + kWChunk >= it1;
+            if ((fdone && bdone) || (fdone && cb >= cf) || (bdone && cf > cb)) break;
         }
     }
-    cf = wblock_sum(cf, red);
-    cb = wblock_sum(cb, red);
-    nf = wblock_sum(nf, red);
-    nb = wblock_sum(nb, red);
     if (threadIdx.x != 0) return;
     P.out_len = os1 - os0;
     P.in_len = it1 - it0;
-    const bool fwd = cf <= cb;
+    const bool fwd = fdone && (!bdone || cf <= cb);
     P.dir = fwd ? 1u : 0u;
     P.list_beg = fwd ? os0 : it0;
     P.list_len = fwd ? P.out_len : P.in_len;
@@ -522,84 +550,86 @@ __global__ __launch_bounds__(kWBlock) void wide_plan_kernel(WArgs A, const uint3
     A.plans[q] = P;
     A.gthr[q] = 0;
     A.qtotal[q] = 0;
-    atomicAdd(&A.tot->front, static_cast<unsigned long long>(P.out_len) + P.in_len);
+    A.qmatch[q] = 0;
     atomicAdd(&A.tot->nd, static_cast<unsigned long long>(P.nd));
     atomicAdd(&A.tot->tiles, static_cast<unsigned long long>(P.ntiles));
 }
 
-// Offsets of each query's frontier weights, distinct table and tiles.
+// Offsets of each query's distinct table and tiles.
 __global__ __launch_bounds__(kWBlock) void wide_offsets_kernel(WArgs A) {
     __shared__ unsigned long long red[kWBlock / kWave];
-    unsigned long long cf = 0, cn = 0, ct = 0;
+    unsigned long long cn = 0, ct = 0;
     for (uint32_t b = 0; b < A.nq; b += kWBlock) {
         const uint32_t q = b + threadIdx.x;
         WPlan P{};
         if (q < A.nq) P = A.plans[q];
-        unsigned long long tf, tn, tt;
-        const unsigned long long ef = wblock_excl<unsigned long long>(q < A.nq ? P.out_len + P.in_len : 0, red, &tf);
+        unsigned long long tn, tt;
         const unsigned long long en = wblock_excl<unsigned long long>(q < A.nq ? P.nd : 0, red, &tn);
         const unsigned long long et = wblock_excl<unsigned long long>(q < A.nq ? P.ntiles : 0, red, &tt);
         if (q < A.nq) {
-            A.plans[q].front_off = cf + ef;
             A.plans[q].tab_off = cn + en;
             A.plans[q].tile_base = static_cast<uint32_t>(ct + et);
         }
-        cf += tf;
         cn += tn;
         ct += tt;
     }
     if (threadIdx.x == 0) A.tot->ctr = 0;
 }
 
-// Frontier weights, the distinct table of the list side, the tile map.
-template <bool BF16>
-__global__ __launch_bounds__(kWBlock) void wide_front_kernel(WArgs A) {
+// The distinct table of the list side and the tile map.
+__global__ __launch_bounds__(kWBlock) void wide_table_kernel(WArgs A) {
     __shared__ unsigned long long red[kWBlock / kWave];
     const uint32_t q = blockIdx.x;
     const WPlan P = A.plans[q];
     if (P.status != 0) return;
-    double *w = A.front + P.front_off;
-    for (uint32_t i = threadIdx.x; i < P.out_len; i += kWBlock) {
-        const uint32_t e = A.out_rp[P.s] + i;
-        w[i] = wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, P.s, A.out_rel[e], A.out_col[e]);
-    }
-    for (uint32_t j = threadIdx.x; j < P.in_len; j += kWBlock) {
-        const uint32_t e = A.in_rp[P.t] + j;
-        w[P.out_len + j] = wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, A.in_col[e], A.in_rel[e], P.t);
-    }
     for (uint32_t j = threadIdx.x; j < P.ntiles; j += kWBlock) A.tile_q[P.tile_base + j] = q;
     if (P.cost == 0) return;
     const bool fwd = P.dir != 0;
-    const uint32_t *Lcol = fwd ? A.out_col : A.in_col;
+    const uint32_t *Lcol = (fwd ? A.out_col : A.in_col) + P.list_beg;
     const uint32_t *Srp = fwd ? A.out_rp : A.in_rp;   // the scanned rows live in the list CSR
     WRow *tab = A.tab + P.tab_off;
     unsigned long long rank0 = 0, pre0 = 0;
-    for (uint32_t b = 0; b < P.list_len; b += kWBlock) {
-        const uint32_t i = b + threadIdx.x;
-        uint32_t x = 0, dg = 0, flag = 0;
-        if (i < P.list_len) {
-            x = Lcol[P.list_beg + i];
-            if (i == 0 || Lcol[P.list_beg + i - 1] != x) {
-                dg = Srp[x + 1] - Srp[x];
-                flag = dg ? 1u : 0u;
+    for (uint32_t c = 0; c < P.list_len; c += kWChunk) {
+        // this thread's segment: its run starts with nonempty scan rows
+        const uint32_t i0 = c + threadIdx.x * kWSeg;
+        uint32_t xs[kWSeg + 1], lo[kWSeg], dg[kWSeg];
+        xs[0] = (i0 > 0 && i0 < P.list_len) ? Lcol[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t j = 0; j < kWSeg; ++j) xs[j + 1] = (i0 + j < P.list_len) ? Lcol[i0 + j] : 0xFFFFFFFFu;
+        unsigned long long cnt = 0, sum = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kWSeg; ++j) {
+            const bool first = i0 + j < P.list_len && xs[j + 1] != xs[j];
+            lo[j] = first ? Srp[xs[j + 1]] : 0u;
+            dg[j] = first ? Srp[xs[j + 1] + 1] - lo[j] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kWSeg; ++j) {
+            cnt += dg[j] ? 1 : 0;
+            sum += dg[j];
+        }
+        unsigned long long tc, ts;
+        const unsigned long long rc = wblock_excl<unsigned long long>(cnt, red, &tc);
+        const unsigned long long pc = wblock_excl<unsigned long long>(sum, red, &ts);
+        unsigned long long rank = rank0 + rc, pre = pre0 + pc;
+#pragma unroll
+        for (uint32_t j = 0; j < kWSeg; ++j) {
+            if (dg[j]) {
+                const uint32_t i = i0 + j;
+                uint32_t len = 1;   // the run of x: its relations to the list anchor
+                while (i + len < P.list_len && Lcol[i + len] == xs[j + 1]) ++len;
+                WRow R;
+                R.prefix = pre;
+                R.x = xs[j + 1];
+                R.scan_beg = lo[j];
+                R.run_beg = i;
+                R.run_len = len;
+                tab[rank++] = R;
+                pre += dg[j];
             }
         }
-        unsigned long long tr, tp;
-        const unsigned long long r = wblock_excl<unsigned long long>(flag, red, &tr);
-        const unsigned long long pf = wblock_excl<unsigned long long>(dg, red, &tp);
-        if (flag) {
-            uint32_t len = 1;
-            while (i + len < P.list_len && Lcol[P.list_beg + i + len] == x) ++len;
-            WRow R;
-            R.prefix = pre0 + pf;
-            R.x = x;
-            R.scan_beg = Srp[x];
-            R.run_beg = i;
-            R.run_len = len;
-            tab[rank0 + r] = R;
-        }
-        rank0 += tr;
-        pre0 += tp;
+        rank0 += tc;
+        pre0 += ts;
     }
 }
 
@@ -644,6 +674,28 @@ __device__ inline void wmerge(const WArgs &A, WCand *c, uint32_t N, uint32_t k, 
     __syncthreads();
     const uint32_t staged = min(sh->stage_n, N - k);
     const uint32_t listed = sh->list_n;
+    if (listed + staged <= k) {
+        // everything fits the list: move the staged candidates behind it and
+        // sort only the next power of two above their count
+        for (uint32_t i = threadIdx.x; i < staged; i += blockDim.x) c[listed + i] = c[k + i];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < staged; i += blockDim.x) c[k + i] = wcand_sentinel();
+        __syncthreads();
+        uint32_t n2 = 2;
+        while (n2 < listed + staged) n2 <<= 1;
+        wbitonic(c, n2);
+        if (threadIdx.x == 0) {
+            sh->list_n = listed + staged;
+            sh->stage_n = 0;
+            if (listed + staged == k) {
+                sh->thr = c[k - 1];
+                atomicMax(reinterpret_cast<unsigned long long *>(&A.gthr[q]),
+                          static_cast<unsigned long long>(dkey(c[k - 1].s)));
+            }
+        }
+        __syncthreads();
+        return;
+    }
     wbitonic(c, N);
     const uint32_t nl = min(k, listed + staged);
     for (uint32_t i = k + threadIdx.x; i < N; i += blockDim.x) c[i] = wcand_sentinel();
@@ -687,11 +739,17 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
         const uint16_t *Lrel = fwd ? A.out_rel : A.in_rel;
         const uint32_t *Pcol = fwd ? A.in_col : A.out_col;
         const uint16_t *Prel = fwd ? A.in_rel : A.out_rel;
-        const double *wl = A.front + P.front_off + (fwd ? 0u : P.out_len);
-        const double *wp = A.front + P.front_off + (fwd ? P.out_len : 0u);
+        // Long probe rows are not searched: the probe edge between a scanned
+        // neighbour y and the probe anchor is found in y's own row instead
+        // (forward: t in out(y); backward: s in in(y)), usually a few entries.
+        const uint32_t *Qrp = fwd ? A.out_rp : A.in_rp;
+        const uint32_t *Qcol = fwd ? A.out_col : A.in_col;
+        const uint16_t *Qrel = fwd ? A.out_rel : A.in_rel;
+        const uint32_t anchor_p = fwd ? P.t : P.s;
         const WRow *tab = A.tab + P.tab_off;
-        const bool plds = P.probe_len <= kWProbeLds;
-        const uint32_t *probe = plds ? pid : Pcol + P.probe_beg;
+        // the probe row is copied to LDS when it is short and the query scans
+        // at least half as many entries (else each lookup uses y's own row)
+        const bool plds = P.probe_len <= kWProbeLds && P.probe_len <= 2 * min<uint64_t>(P.cost, kWTile);
         if (plds)
             for (uint32_t i = threadIdx.x; i < P.probe_len; i += kWBlock) pid[i] = Pcol[P.probe_beg + i];
         for (uint32_t i = threadIdx.x; i < N; i += kWBlock) cand[i] = wcand_sentinel();
@@ -701,12 +759,12 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
         }
         const uint64_t t0 = static_cast<uint64_t>(tile - P.tile_base) * kWTile;
         const uint64_t t1 = min(P.cost, t0 + kWTile);
-        unsigned long long mypaths = 0;
+        unsigned long long mypaths = 0, mymatch = 0;
         for (uint64_t sb = t0; sb < t1; sb += kWSub) {
             const uint64_t se = min(t1, sb + kWSub);
             __syncthreads();
             if (threadIdx.x == 0) {   // last table row with prefix <= sb
-                uint32_t lo = 0, hi = P.nd;
+                uint32_t lo = 0, hi = sb == 0 ? 1u : P.nd;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
                     if (tab[mid].prefix <= sb) lo = mid; else hi = mid;
@@ -733,7 +791,8 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
             const uint32_t nrows = static_cast<uint32_t>(wblock_sum<unsigned long long>(valid, red));
             for (uint64_t base = sb; base < se; base += kWBlock) {
                 const uint64_t p = base + threadIdx.x;
-                uint32_t ncombo = 0, nl = 0, ix = 0, x = 0, y = 0, r2 = 0, rb = 0;
+                uint32_t ncombo = 0, nl = 0, x = 0, y = 0, r2 = 0, rb = 0;
+                const uint16_t *prr = nullptr;   // relations of the probe run
                 double w2 = 0.0;
                 if (p < se) {
                     // the staged row holding p: the last with prefix <= p
@@ -748,9 +807,17 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
                     nl = rrl[lo];
                     y = Lcol[e];
                     r2 = Lrel[e];
-                    ix = wlower(probe, P.probe_len, y);
                     uint32_t np = 0;
-                    while (ix + np < P.probe_len && probe[ix + np] == y) ++np;
+                    if (plds) {
+                        const uint32_t ix = wlower(pid, P.probe_len, y);
+                        while (ix + np < P.probe_len && pid[ix + np] == y) ++np;
+                        prr = Prel + P.probe_beg + ix;
+                    } else {
+                        const uint32_t b0 = Qrp[y], b1 = Qrp[y + 1];
+                        const uint32_t ix = b0 + wlower(Qcol + b0, b1 - b0, anchor_p);
+                        while (ix + np < b1 && Qcol[ix + np] == anchor_p) ++np;
+                        prr = Qrel + ix;
+                    }
                     if (np) {
                         ncombo = nl * np;
                         w2 = fwd ? wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, x, r2, y)
@@ -758,16 +825,22 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
                     }
                 }
                 mypaths += ncombo;
+                mymatch += ncombo ? 1u : 0u;
                 const uint64_t gk = A.gthr[q];   // best known K-th score of the query (0: none yet)
                 const double floor_s = gk ? dkey_inv(gk) : -INFINITY;
                 uint32_t combo = 0;
                 for (;;) {
                     while (combo < ncombo) {
                         const uint32_t li = combo % nl, pi = combo / nl;
-                        const double wL = wl[rb + li], wP = wp[ix + pi];
+                        const uint16_t rl = Lrel[P.list_beg + rb + li], rp = prr[pi];
+                        // list edge s -rl-> x (forward) or x -rl-> t; probe edge
+                        // y -rp-> t (forward) or s -rp-> y
+                        const double wL = fwd ? wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, P.s, rl, x)
+                                              : wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, x, rl, P.t);
+                        const double wP = fwd ? wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, y, rp, P.t)
+                                              : wide_weight<BF16>(A.X, A.Y, A.d, A.gamma, P.s, rp, y);
                         WCand c;
                         c.s = fwd ? sum3_rn(wL, w2, wP) : sum3_rn(wP, w2, wL);
-                        const uint16_t rl = Lrel[P.list_beg + rb + li], rp = Prel[P.probe_beg + ix + pi];
                         c.a = fwd ? x : y;
                         c.b = fwd ? y : x;
                         c.r1 = fwd ? rl : rp;
@@ -787,7 +860,8 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
                 }
             }
         }
-        unsigned long long bp = wblock_sum<unsigned long long>(mypaths, red);
+        const unsigned long long bp = wblock_sum<unsigned long long>(mypaths, red);
+        const unsigned long long bm = wblock_sum<unsigned long long>(mymatch, red);
         if (sh.stage_n > 0) wmerge(A, cand, N, k, &sh, q);
         __syncthreads();
         const uint32_t nl = sh.list_n;
@@ -796,13 +870,15 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
             A.tile_n[tile] = nl;
             A.head[tile] = 0;
             atomicAdd(reinterpret_cast<unsigned long long *>(&A.qtotal[q]), bp);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&A.qmatch[q]), bm);
         }
     }
 }
 
 // One wave per query: K-way merge of the tiles' sorted lists.
 __global__ __launch_bounds__(kWBlock) void wide_merge_kernel(WArgs A, mhr_wide_path *out, uint32_t *out_count,
-                                                             uint64_t *out_total, uint32_t *out_status) {
+                                                             uint64_t *out_total, uint32_t *out_status,
+                                                             mhr_wide_work *out_work) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t q = blockIdx.x * (kWBlock / kWave) + threadIdx.x / kWave;
     if (q >= A.nq) return;
@@ -873,16 +949,28 @@ __global__ __launch_bounds__(kWBlock) void wide_merge_kernel(WArgs A, mhr_wide_p
         out_count[q] = cnt;
         if (out_total) out_total[q] = total;
         if (out_status) out_status[q] = P.status;
+        if (out_work) {
+            mhr_wide_work w;
+            w.scanned = P.cost;
+            w.matches = P.status ? 0ull : A.qmatch[q];
+            w.paths = total;
+            w.frontier = static_cast<uint64_t>(P.out_len) + P.in_len;
+            w.distinct = P.nd;
+            w.probe_len = P.probe_len;
+            w.tiles = P.ntiles;
+            w.forward = P.dir;
+            out_work[q] = w;
+        }
     }
 }
 
 // Workspace: a fixed part sized by the batch, then the parts sized by the
 // plan's totals.
 struct WLayout {
-    size_t plans, tot, gthr, qtotal, fixed, front, tab, tile_q, tile_n, head, slots, total;
+    size_t plans, tot, gthr, qtotal, qmatch, fixed, tab, tile_q, tile_n, head, slots, total;
 };
 
-WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t front, uint64_t nd, uint64_t tiles) {
+WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t nd, uint64_t tiles) {
     WLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -894,8 +982,8 @@ WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t front, uint64_t nd, ui
     L.tot = take(sizeof(WTotals));
     L.gthr = take(size_t(nq) * 8);
     L.qtotal = take(size_t(nq) * 8);
+    L.qmatch = take(size_t(nq) * 8);
     L.fixed = o;
-    L.front = take(front * 8);
     L.tab = take(nd * sizeof(WRow));
     L.tile_q = take(tiles * 4);
     L.tile_n = take(tiles * 4);
@@ -934,7 +1022,7 @@ WArgs wide_args(const mhr_wide_graph *g, uint32_t nq, uint32_t k_max, char *ws, 
     A.tot = reinterpret_cast<WTotals *>(ws + L.tot);
     A.gthr = reinterpret_cast<uint64_t *>(ws + L.gthr);
     A.qtotal = reinterpret_cast<uint64_t *>(ws + L.qtotal);
-    A.front = reinterpret_cast<double *>(ws + L.front);
+    A.qmatch = reinterpret_cast<uint64_t *>(ws + L.qmatch);
     A.tab = reinterpret_cast<WRow *>(ws + L.tab);
     A.tile_q = reinterpret_cast<uint32_t *>(ws + L.tile_q);
     A.tile_n = reinterpret_cast<uint32_t *>(ws + L.tile_n);
@@ -959,7 +1047,7 @@ mhr_status wide_check(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src,
 // stream is synchronised).
 mhr_status wide_plan(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                      const uint32_t *k, uint32_t k_max, char *ws, WTotals *tot, hipStream_t st) {
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
     WArgs A = wide_args(g, nq, k_max, ws, L0);
     MHR_HIP_TRY(hipMemsetAsync(A.tot, 0, sizeof(WTotals), st));
     hipLaunchKernelGGL(wide_plan_kernel, dim3(nq), dim3(kWBlock), 0, st, A, src, dst, k);
@@ -1060,34 +1148,37 @@ extern "C" mhr_status mhr_wide_workspace_size(const mhr_wide_graph *g, uint32_t 
     if (rc != MHR_OK) return rc;
     MHR_ARG_CHECK(bytes != nullptr, "mhr_wide_workspace_size: null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
     WBuf tmp;
     MHR_HIP_TRY(tmp.alloc(L0.fixed));
     WTotals tot{};
     rc = wide_plan(g, nq, src, dst, k, k_max, tmp.as<char>(), &tot, st);
     if (rc != MHR_OK) return rc;
-    *bytes = wide_layout(nq, k_max, tot.front, tot.nd, tot.tiles).total;
+    *bytes = wide_layout(nq, k_max, tot.nd, tot.tiles).total;
     return MHR_OK;
 }
 
 extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src,
                                           const uint32_t *dst, const uint32_t *k, uint32_t k_max, mhr_wide_path *out,
                                           uint32_t *out_count, uint64_t *out_total, uint32_t *out_status,
-                                          void *workspace, size_t ws_bytes, void *stream) {
+                                          mhr_wide_work *out_work, void *workspace, size_t ws_bytes, void *stream,
+                                          const mhr_phase_events *ev) {
     mhr_status rc = wide_check(g, nq, src, dst, k_max);
     if (rc != MHR_OK) return rc;
     MHR_ARG_CHECK(out && out_count && workspace, "mhr_wide_topk_paths: null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
     if (ws_bytes < L0.fixed) {
         set_error("mhr_wide_topk_paths: workspace too small for the batch's plans");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
     }
     char *ws = static_cast<char *>(workspace);
+    auto mark = [&](void *e) -> hipError_t { return e ? hipEventRecord(static_cast<hipEvent_t>(e), st) : hipSuccess; };
+    MHR_HIP_TRY(mark(ev ? ev->begin : nullptr));
     WTotals tot{};
     rc = wide_plan(g, nq, src, dst, k, k_max, ws, &tot, st);
     if (rc != MHR_OK) return rc;
-    const WLayout L = wide_layout(nq, k_max, tot.front, tot.nd, tot.tiles);
+    const WLayout L = wide_layout(nq, k_max, tot.nd, tot.tiles);
     if (ws_bytes < L.total) {
         set_error("mhr_wide_topk_paths: workspace too small: need " + std::to_string(L.total) + " bytes");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
@@ -1098,10 +1189,10 @@ extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, 
     }
     const WArgs A = wide_args(g, nq, k_max, ws, L);
     const bool bf = g->dtype == MHR_DTYPE_BF16;
-    if (bf) hipLaunchKernelGGL(wide_front_kernel<true>, dim3(nq), dim3(kWBlock), 0, st, A);
-    else hipLaunchKernelGGL(wide_front_kernel<false>, dim3(nq), dim3(kWBlock), 0, st, A);
+    hipLaunchKernelGGL(wide_table_kernel, dim3(nq), dim3(kWBlock), 0, st, A);
     MHR_HIP_TRY(hipGetLastError());
     const uint32_t tiles = static_cast<uint32_t>(tot.tiles);
+    MHR_HIP_TRY(mark(ev ? ev->gather_begin : nullptr));
     if (tiles) {
         int cus = 0;
         MHR_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
@@ -1112,8 +1203,10 @@ extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, 
         else hipLaunchKernelGGL(wide_gather_kernel<false>, dim3(grid), dim3(kWBlock), lds, st, A, tiles, N);
         MHR_HIP_TRY(hipGetLastError());
     }
+    MHR_HIP_TRY(mark(ev ? ev->gather_end : nullptr));
     hipLaunchKernelGGL(wide_merge_kernel, dim3(wcdiv(nq, kWBlock / kWave)), dim3(kWBlock), 0, st, A, out, out_count,
-                       out_total, out_status);
+                       out_total, out_status, out_work);
     MHR_HIP_TRY(hipGetLastError());
+    MHR_HIP_TRY(mark(ev ? ev->end : nullptr));
     return MHR_OK;
 }

@@ -116,7 +116,7 @@ def test_wide_bf16_tables():
 
 def test_wide_hubs_many_tiles_and_long_probe_rows():
     """Hub sources and targets: scans of many tiles per query and probe
-    rows longer than the LDS copy (searched in global memory)."""
+    rows longer than the LDS copy (looked up through the neighbour's own row)."""
     sp, (h, r, t), (X, Y) = _wide("wide_hub")
     say("case wide hubs")
     g = _gpu_graph(sp, h, r, t, X, Y)
