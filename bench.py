@@ -463,7 +463,25 @@ def run_pruner(args, cfg, g, h, s, d):
         res, st = lp.search(s, d, K, keep_permille=100, scores=sc, fallback=False)
         torch.cuda.synchronize()
         out[f"recall_{kind}_no_fallback"] = round(topk_recall(exn, res.to_numpy()), 4)
-    for tau in (0.0, 0.25):
+    # the confidence threshold: the smallest tau on a grid whose recall on a
+    # validation split (queries disjoint from training and held-out, same
+    # law) reaches 0.95; then the held-out batch at that tau
+    s_va, d_va, _ = kgsynth.queries(h, cfg.graph.n, kgsynth.QuerySpec(2048, "degree", K, seed=16))
+    ex_va = g.topk(s_va, d_va, K).to_numpy()
+    c_va = mhr.candidates(g, s_va, d_va)
+    sc_va = lp.logits(c_va)
+    sweep = {}
+    tau_star = 1.0
+    for tau in (0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99, 1.0):
+        res, st = lp.search(s_va, d_va, K, keep_permille=100, tau=tau, scores=sc_va)
+        rec = topk_recall(ex_va, res.to_numpy())
+        sweep[str(tau)] = {"recall": round(rec, 4), "fallback": st["fallback"]}
+        if rec >= 0.95:
+            tau_star = tau
+            break
+    out["tau_sweep_validation"] = sweep
+    out["tau_selected"] = tau_star
+    for tau in sorted({0.0, tau_star}):
         (res, st), t_pr = timed(lambda: lp.search(s, d, K, keep_permille=100, tau=tau), args.steps)
         out[f"tau_{tau}"] = {"recall": round(topk_recall(exn, res.to_numpy()), 4), "fallback": st["fallback"],
                              "queries_per_s": len(s) / t_pr}
@@ -619,7 +637,8 @@ def main():
         for i in range(args.steps):
             g.topk(sd, dd, kk, k_max=k_max, out=res, opts=qo)
         ticks, rate = mhr.phase_ticks()
-        phases = {"ticks": ticks, "rate_hz": rate}
+        dticks, ntiles = mhr.phase_ticks_directory()
+        phases = {"ticks": ticks, "rate_hz": rate, "dir_ticks": dticks, "tiles": ntiles}
     p, cnt, tot, st = res.to_numpy()
     paths = int(tot.sum())
     exact_pass = int(np.sum((st & mhr.Q_EXACT_PASS) != 0))
@@ -664,8 +683,16 @@ def main():
                 out_ph[k]["bytes"] = int(b)
                 if per_launch_s[k] > 0:
                     out_ph[k]["GB_s"] = round(b / per_launch_s[k] / 1e9, 1)
+        # the same split for the tiles whose probe side is too long for the
+        # LDS table (probes through the row directory)
+        dirs = {k: {"ms_per_launch": round(1e3 * v / rate / nblocks / args.steps, 4)}
+                for k, v in phases["dir_ticks"].items()}
         log(f"gather phases: {json.dumps(out_ph)}")
-        print(json.dumps({"phases": out_ph, "config": args.config, "steps": args.steps,
+        log(f"directory-probe tiles: {json.dumps(dirs)}; tiles per launch (table, directory): "
+            f"{[x // args.steps for x in phases['tiles']]}")
+        print(json.dumps({"phases": out_ph, "directory_tiles": dirs,
+                          "tiles_table_directory": [x // args.steps for x in phases["tiles"]],
+                          "config": args.config, "steps": args.steps,
                           "note": "phase-clock build; wall time of the average workgroup per launch"}), flush=True)
         return
 

@@ -139,6 +139,31 @@ typedef struct mhr_graph_stats {
  * of range), OUT_OF_MEMORY, DEVICE. */
 mhr_status mhr_graph_create(const mhr_graph_desc *desc, void *stream, mhr_graph **out);
 
+/* Device bytes the caller provides to mhr_graph_create_in for a graph of
+ * num_vertices vertices and num_edges triples (section 3.1: the graph G the
+ * paths are searched in):
+ *   csr_buffer_bytes  storage of both CSRs and their directories, kept by the
+ *                     handle until mhr_graph_destroy; sized for the worst
+ *                     case (every triple a distinct pair, every row long);
+ *   tmp_buffer_bytes  scratch of the build (sort keys, scans), free again
+ *                     when mhr_graph_create_in returns.
+ * Host only; enqueues nothing.  Errors: INVALID_ARGUMENT (the shape checks
+ * of mhr_graph_create). */
+mhr_status mhr_graph_buffer_sizes(uint32_t num_vertices, uint32_t num_relations, uint64_t num_edges,
+                                  size_t *csr_buffer_bytes, size_t *tmp_buffer_bytes);
+
+/* mhr_graph_create with every device byte supplied by the caller: the
+ * library calls no hipMalloc.  csr_buffer (device, 256-byte aligned, at least
+ * csr_buffer_bytes of mhr_graph_buffer_sizes) is BORROWED for the handle's
+ * lifetime and must not be written while the handle lives; tmp_buffer
+ * (device, 256-byte aligned, at least tmp_buffer_bytes) is used during the
+ * call only.  Results and synchronisation as mhr_graph_create; the stats'
+ * device_bytes is the part of csr_buffer the CSRs occupy.  Errors: as
+ * mhr_graph_create, plus WORKSPACE_TOO_SMALL when a buffer is smaller than
+ * its size (nothing enqueued). */
+mhr_status mhr_graph_create_in(const mhr_graph_desc *desc, void *csr_buffer, size_t csr_buffer_bytes,
+                               void *tmp_buffer, size_t tmp_buffer_bytes, void *stream, mhr_graph **out);
+
 /* Attaches the embeddings that define the edge weights (section 3.1: the
  * weight of an edge is computed from its head, relation and tail vectors):
  * entity[num_vertices][dim] and relation[num_relations][dim],
@@ -491,6 +516,20 @@ size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden);
  * with mhr_pruner_set_params).  Allocates device memory (hipMalloc). */
 mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_pruner **out);
 mhr_status mhr_pruner_destroy(mhr_pruner *p);
+
+/* Device bytes of a pruner's state for mhr_pruner_create_in: FP32 master
+ * weights, gradient and both Adam moments (param_count each), and the
+ * bfloat16 copies of the three weight matrices.  Host only.  Errors:
+ * INVALID_ARGUMENT (dim or hidden outside the ranges of mhr_pruner_create). */
+mhr_status mhr_pruner_buffer_bytes(uint32_t dim, uint32_t hidden, size_t *bytes);
+
+/* mhr_pruner_create with its state in the caller's device buffer (256-byte
+ * aligned, at least mhr_pruner_buffer_bytes): the library calls no
+ * hipMalloc.  The buffer is BORROWED until mhr_pruner_destroy.  Zeroes the
+ * state on `stream` and synchronises it.  Errors: INVALID_ARGUMENT,
+ * WORKSPACE_TOO_SMALL (nothing enqueued), DEVICE. */
+mhr_status mhr_pruner_create_in(uint32_t dim, uint32_t hidden, void *buffer, size_t bytes, void *stream,
+                                mhr_pruner **out);
 
 /* Copies params (device FP32 [param_count]) in and resets the Adam state. */
 mhr_status mhr_pruner_set_params(mhr_pruner *p, const float *params, void *stream);

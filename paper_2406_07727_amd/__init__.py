@@ -90,6 +90,12 @@ class QueryOpts(ctypes.Structure):
 _vp, _u32, _u64, _i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 _lib.mhr_graph_create.restype = _i
 _lib.mhr_graph_create.argtypes = [ctypes.POINTER(_GraphDesc), _vp, ctypes.POINTER(_vp)]
+_lib.mhr_graph_buffer_sizes.restype = _i
+_lib.mhr_graph_buffer_sizes.argtypes = [_u32, _u32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t),
+                                        ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_graph_create_in.restype = _i
+_lib.mhr_graph_create_in.argtypes = [ctypes.POINTER(_GraphDesc), _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
+                                     ctypes.POINTER(_vp)]
 _lib.mhr_graph_set_embeddings.restype = _i
 _lib.mhr_graph_set_embeddings.argtypes = [_vp, _i, _u32, _vp, _vp, _vp]
 _lib.mhr_graph_set_scorer.restype = _i
@@ -130,6 +136,10 @@ _lib.mhr_pruner_param_count.restype = ctypes.c_size_t
 _lib.mhr_pruner_param_count.argtypes = [_u32, _u32]
 _lib.mhr_pruner_create.restype = _i
 _lib.mhr_pruner_create.argtypes = [_u32, _u32, ctypes.POINTER(_vp)]
+_lib.mhr_pruner_buffer_bytes.restype = _i
+_lib.mhr_pruner_buffer_bytes.argtypes = [_u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_pruner_create_in.restype = _i
+_lib.mhr_pruner_create_in.argtypes = [_u32, _u32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
 _lib.mhr_pruner_destroy.restype = _i
 _lib.mhr_pruner_destroy.argtypes = [_vp]
 _lib.mhr_pruner_set_params.restype = _i
@@ -277,14 +287,25 @@ class TopK:
                 self.status.cpu().numpy().view(np.uint32))
 
 
+def graph_buffer_sizes(num_vertices: int, num_relations: int, num_edges: int) -> tuple:
+    """(csr_bytes, tmp_bytes) that mhr_graph_create_in needs."""
+    c, t = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.mhr_graph_buffer_sizes(int(num_vertices), int(num_relations), int(num_edges), ctypes.byref(c),
+                                       ctypes.byref(t)), "mhr_graph_buffer_sizes")
+    return int(c.value), int(t.value)
+
+
 class Graph:
     """A typed directed graph resident on the current HIP device.
 
     head, rel, tail: integer device tensors (or host arrays) of one edge
-    list (h, r, t).  Identical triples are merged.  The device memory of the
-    handle is freed by ``close()`` or on garbage collection."""
+    list (h, r, t).  Identical triples are merged.  caller_buffers: give the
+    library torch-allocated buffers (mhr_graph_create_in) instead of letting
+    it allocate its own.  The device memory of the handle is freed by
+    ``close()`` or on garbage collection."""
 
-    def __init__(self, head, rel, tail, num_vertices: int, num_relations: int, stream=None):
+    def __init__(self, head, rel, tail, num_vertices: int, num_relations: int, stream=None,
+                 caller_buffers: bool = False):
         torch = _torch()
         h, r, t = _dev_u32(head), _dev_u32(rel), _dev_u32(tail)
         if not (h.numel() == r.numel() == t.numel()):
@@ -293,8 +314,19 @@ class Graph:
                           h.data_ptr(), r.data_ptr(), t.data_ptr())
         handle = ctypes.c_void_p()
         torch.cuda.synchronize()
-        _check(_lib.mhr_graph_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(handle)),
-               "mhr_graph_create")
+        self._csr_buf = None
+        if caller_buffers:
+            cb, tb = graph_buffer_sizes(num_vertices, num_relations, h.numel())
+            csr = torch.empty(cb + 256, dtype=torch.uint8, device="cuda")
+            tmp = torch.empty(tb + 256, dtype=torch.uint8, device="cuda")
+            co, to = (-csr.data_ptr()) % 256, (-tmp.data_ptr()) % 256   # 256-byte aligned views
+            _check(_lib.mhr_graph_create_in(ctypes.byref(desc), csr.data_ptr() + co, cb, tmp.data_ptr() + to, tb,
+                                            _stream_ptr(stream), ctypes.byref(handle)), "mhr_graph_create_in")
+            self._csr_buf = csr   # borrowed by the handle until close()
+            del tmp
+        else:
+            _check(_lib.mhr_graph_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(handle)),
+                   "mhr_graph_create")
         self._h = handle
         self.n = int(num_vertices)
         self.R = int(num_relations)
@@ -305,6 +337,7 @@ class Graph:
         if getattr(self, "_h", None) and self._h.value:
             _lib.mhr_graph_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._csr_buf = None
 
     def __del__(self):
         try:
@@ -583,9 +616,23 @@ class Pruner:
     """The learned frontier pruner's network on the device (see
     include/mhr.h): FP32 master parameters, bfloat16 MFMA products."""
 
-    def __init__(self, dim: int, hidden: int):
+    def __init__(self, dim: int, hidden: int, caller_buffer: bool = False):
+        """caller_buffer: keep the state in a torch-allocated buffer
+        (mhr_pruner_create_in) instead of library allocations."""
         h = ctypes.c_void_p()
-        _check(_lib.mhr_pruner_create(int(dim), int(hidden), ctypes.byref(h)), "mhr_pruner_create")
+        self._buf = None
+        if caller_buffer:
+            torch = _torch()
+            nb = ctypes.c_size_t()
+            _check(_lib.mhr_pruner_buffer_bytes(int(dim), int(hidden), ctypes.byref(nb)), "mhr_pruner_buffer_bytes")
+            buf = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+            off = (-buf.data_ptr()) % 256
+            torch.cuda.synchronize()
+            _check(_lib.mhr_pruner_create_in(int(dim), int(hidden), buf.data_ptr() + off, nb.value, None,
+                                             ctypes.byref(h)), "mhr_pruner_create_in")
+            self._buf = buf   # borrowed by the handle until close()
+        else:
+            _check(_lib.mhr_pruner_create(int(dim), int(hidden), ctypes.byref(h)), "mhr_pruner_create")
         self._h = h
         self.dim, self.hidden = int(dim), int(hidden)
         self.n_params = int(_lib.mhr_pruner_param_count(self.dim, self.hidden))
@@ -599,6 +646,7 @@ class Pruner:
         if getattr(self, "_h", None):
             _lib.mhr_pruner_destroy(self._h)
             self._h = None
+        self._buf = None
 
     def __del__(self):
         try:
@@ -840,10 +888,23 @@ def phase_ticks(reset: bool = False):
     """The gather kernel's per-phase wall-clock ticks summed over workgroups
     (phase-clock build only; see mhr_debug_phase_ticks) as {phase: ticks},
     and the clock rate in Hz."""
-    buf = (ctypes.c_uint64 * 16)()
+    npz = len(GATHER_PHASES)
+    buf = (ctypes.c_uint64 * (2 * npz + 2))()
     rate = ctypes.c_double()
-    _check(_lib.mhr_debug_phase_ticks(buf, 16, ctypes.byref(rate), 1 if reset else 0), "mhr_debug_phase_ticks")
+    _check(_lib.mhr_debug_phase_ticks(buf, 2 * npz + 2, ctypes.byref(rate), 1 if reset else 0),
+           "mhr_debug_phase_ticks")
     return {p: int(buf[i]) for i, p in enumerate(GATHER_PHASES)}, float(rate.value)
+
+
+def phase_ticks_directory():
+    """Of the phase ticks since the last reset, those of tiles probing
+    through the row directory ({phase: ticks}), and the tile counts
+    (table kind, directory kind).  Does not reset."""
+    npz = len(GATHER_PHASES)
+    buf = (ctypes.c_uint64 * (2 * npz + 2))()
+    rate = ctypes.c_double()
+    _check(_lib.mhr_debug_phase_ticks(buf, 2 * npz + 2, ctypes.byref(rate), 0), "mhr_debug_phase_ticks")
+    return {p: int(buf[npz + i]) for i, p in enumerate(GATHER_PHASES)}, (int(buf[2 * npz]), int(buf[2 * npz + 1]))
 
 
 def _table(t, dtype):

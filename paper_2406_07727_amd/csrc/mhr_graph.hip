@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "mhr_device.h"
@@ -272,31 +273,115 @@ mhr_status device_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t n, 
 
 namespace {
 
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
-    template <class T>
-    T *as() const { return static_cast<T *>(p); }
+// Device memory of one graph build.  Every buffer comes from one of two
+// places: the caller's buffers (bump allocation in 256-byte pieces, in the
+// order of the calls below, which is the order mhr_graph_buffer_sizes
+// counts), or hipMalloc when the caller gave none.  Temporaries allocated
+// with hipMalloc are freed when the build ends; CSR arrays allocated with
+// hipMalloc belong to the handle.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
 };
 
-mhr_status radix_sort(uint64_t *&keys, uint64_t *&tmp, uint64_t n, int bits, hipStream_t st) {
+constexpr size_t kPiece = 256;
+inline size_t piece(size_t bytes) { return (std::max<size_t>(bytes, 1) + kPiece - 1) / kPiece * kPiece; }
+
+struct BuildMem {
+    Arena *tmp = nullptr;   // null: temporaries by hipMalloc
+    Arena *csr = nullptr;   // null: CSR arrays by hipMalloc (owned by the handle)
+    std::vector<void *> tmp_owned;
+    ~BuildMem() {
+        for (void *p : tmp_owned) (void)hipFree(p);
+    }
+    static hipError_t take(Arena *a, void **p, size_t bytes) {
+        const size_t b = piece(bytes);
+        if (a->used + b > a->cap) return hipErrorOutOfMemory;
+        *p = a->base + a->used;
+        a->used += b;
+        return hipSuccess;
+    }
+    template <class T>
+    hipError_t temp(T **p, size_t count) {
+        void *v = nullptr;
+        hipError_t e;
+        if (tmp) {
+            e = take(tmp, &v, count * sizeof(T));
+        } else {
+            e = hipMalloc(&v, piece(count * sizeof(T)));
+            if (e == hipSuccess) tmp_owned.push_back(v);
+        }
+        *p = static_cast<T *>(v);
+        return e;
+    }
+    template <class T>
+    hipError_t keep(T **p, size_t count) {
+        void *v = nullptr;
+        hipError_t e = csr ? take(csr, &v, count * sizeof(T)) : hipMalloc(&v, piece(count * sizeof(T)));
+        *p = static_cast<T *>(v);
+        return e;
+    }
+};
+
+// Element counts of the temporaries of one direction's build, in allocation
+// order (both directions reuse the same temporaries).
+struct TempCounts {
+    uint64_t keys, tmp, err, counts, sort_scratch, newpair, newtriple, pexcl, scratch, totals, sizes, sexcl, heavy,
+        hn, maxdeg, tot, scratch2;
+};
+
+TempCounts temp_counts(uint32_t n, uint64_t m) {
+    TempCounts c{};
+    const uint64_t nc = static_cast<uint64_t>(cdiv(m, kSortTile)) * kBins;
+    c.keys = m;            // uint64
+    c.tmp = m;             // uint64
+    c.err = 1;
+    c.counts = nc;
+    c.sort_scratch = cdiv(nc, kScanChunk) + 1;
+    c.newpair = m;
+    c.newtriple = m;
+    c.pexcl = m;
+    c.scratch = cdiv(m, kScanChunk) + 1;
+    c.totals = 2;
+    c.sizes = n;
+    c.sexcl = n;
+    c.heavy = n;
+    c.hn = c.maxdeg = c.tot = 1;
+    c.scratch2 = cdiv(n, kScanChunk) + 1;
+    return c;
+}
+
+size_t temp_bytes(uint32_t n, uint64_t m) {
+    const TempCounts c = temp_counts(n, m);
+    return piece(c.keys * 8) + piece(c.tmp * 8) + piece(c.err * 4) + piece(c.counts * 4) +
+           piece(c.sort_scratch * 4) + piece(c.newpair * 4) + piece(c.newtriple * 4) + piece(c.pexcl * 4) +
+           piece(c.scratch * 4) + piece(c.totals * 4) + piece(c.sizes * 4) + piece(c.sexcl * 4) +
+           piece(c.heavy * 4) + piece(c.hn * 4) + piece(c.maxdeg * 4) + piece(c.tot * 4) + piece(c.scratch2 * 4);
+}
+
+// Upper bound on the directory pool of one direction: a row of degree deg
+// > kDirMinDegree takes next_pow2(deg) / 2 + 1 <= deg + 1 words.
+uint64_t dir_pool_bound(uint64_t m) { return m + m / (kDirMinDegree + 1) + 1; }
+
+// CSR bytes of one direction when the pair count and pool length are known
+// (the caller-buffer form uses the bounds num_pairs <= m and
+// dir_pool_bound(m)).
+size_t csr_bytes(uint32_t n, uint64_t pairs, uint64_t pool) {
+    return piece((static_cast<uint64_t>(n) + 1) * 4) + 2 * piece(pairs * 4) + piece(static_cast<uint64_t>(n) * 4) +
+           piece(pool * 4);
+}
+
+mhr_status radix_sort(uint64_t *&keys, uint64_t *&tmp, uint64_t n, int bits, uint32_t *counts,
+                      uint32_t *scratch, hipStream_t st) {
     if (n <= 1) return MHR_OK;
     uint32_t ntiles = cdiv(n, kSortTile);
     uint64_t nc = static_cast<uint64_t>(ntiles) * kBins;
-    DevBuf counts, scratch;
-    MHR_HIP_TRY(counts.alloc(nc * sizeof(uint32_t)));
-    MHR_HIP_TRY(scratch.alloc((cdiv(nc, kScanChunk) + 1) * sizeof(uint32_t)));
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortBlock), 0, st, keys, n, shift, ntiles,
-                           counts.as<uint32_t>());
-        mhr_status s = device_exclusive_scan(counts.as<uint32_t>(), counts.as<uint32_t>(), nc, nullptr,
-                                             scratch.as<uint32_t>(), st);
+        hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortBlock), 0, st, keys, n, shift, ntiles, counts);
+        mhr_status s = device_exclusive_scan(counts, counts, nc, nullptr, scratch, st);
         if (s != MHR_OK) return s;
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortBlock), 0, st, keys, tmp, n, shift, ntiles,
-                           counts.as<uint32_t>());
+                           counts);
         MHR_HIP_TRY(hipGetLastError());
         std::swap(keys, tmp);
     }
@@ -304,109 +389,125 @@ mhr_status radix_sort(uint64_t *&keys, uint64_t *&tmp, uint64_t n, int bits, hip
     return MHR_OK;
 }
 
-// Builds one direction.  keys (length m) is consumed.
-mhr_status build_direction(mhr_graph *g, const mhr_graph_desc *d, int reverse, Csr &csr, hipStream_t st) {
+// Builds one direction.  Temporaries come from mem (the same pieces for
+// both directions: `t` is reused), the CSR arrays too; when the CSR lives in
+// the caller's buffer its arrays take the bounds (m pairs, dir_pool_bound).
+struct Temps {
+    uint64_t *keys = nullptr, *tmp = nullptr;
+    uint32_t *err = nullptr, *counts = nullptr, *sort_scratch = nullptr, *newpair = nullptr, *newtriple = nullptr,
+             *pexcl = nullptr, *scratch = nullptr, *totals = nullptr, *sizes = nullptr, *sexcl = nullptr,
+             *heavy = nullptr, *hn = nullptr, *maxdeg = nullptr, *tot = nullptr, *scratch2 = nullptr;
+};
+
+mhr_status alloc_temps(BuildMem &mem, uint32_t n, uint64_t m, Temps &t) {
+    const TempCounts c = temp_counts(n, m);
+    MHR_HIP_TRY(mem.temp(&t.keys, c.keys));
+    MHR_HIP_TRY(mem.temp(&t.tmp, c.tmp));
+    MHR_HIP_TRY(mem.temp(&t.err, c.err));
+    MHR_HIP_TRY(mem.temp(&t.counts, c.counts));
+    MHR_HIP_TRY(mem.temp(&t.sort_scratch, c.sort_scratch));
+    MHR_HIP_TRY(mem.temp(&t.newpair, c.newpair));
+    MHR_HIP_TRY(mem.temp(&t.newtriple, c.newtriple));
+    MHR_HIP_TRY(mem.temp(&t.pexcl, c.pexcl));
+    MHR_HIP_TRY(mem.temp(&t.scratch, c.scratch));
+    MHR_HIP_TRY(mem.temp(&t.totals, c.totals));
+    MHR_HIP_TRY(mem.temp(&t.sizes, c.sizes));
+    MHR_HIP_TRY(mem.temp(&t.sexcl, c.sexcl));
+    MHR_HIP_TRY(mem.temp(&t.heavy, c.heavy));
+    MHR_HIP_TRY(mem.temp(&t.hn, c.hn));
+    MHR_HIP_TRY(mem.temp(&t.maxdeg, c.maxdeg));
+    MHR_HIP_TRY(mem.temp(&t.tot, c.tot));
+    MHR_HIP_TRY(mem.temp(&t.scratch2, c.scratch2));
+    return MHR_OK;
+}
+
+mhr_status build_direction(mhr_graph *g, const mhr_graph_desc *d, int reverse, Csr &csr, BuildMem &mem,
+                           const Temps &t, hipStream_t st) {
     const uint64_t m = d->num_edges;
     const uint32_t n = g->n;
-    DevBuf kb, tb, err;
-    MHR_HIP_TRY(kb.alloc(m * sizeof(uint64_t)));
-    MHR_HIP_TRY(tb.alloc(m * sizeof(uint64_t)));
-    MHR_HIP_TRY(err.alloc(sizeof(uint32_t)));
-    MHR_HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(uint32_t), st));
-    uint64_t *keys = kb.as<uint64_t>(), *tmp = tb.as<uint64_t>();
+    MHR_HIP_TRY(hipMemsetAsync(t.err, 0, sizeof(uint32_t), st));
+    uint64_t *keys = t.keys, *tmp = t.tmp;
     if (m) {
         hipLaunchKernelGGL(make_keys_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, d->head, d->rel, d->tail, m, n,
-                           g->R, static_cast<int>(g->id_bits), reverse, keys, err.as<uint32_t>());
+                           g->R, static_cast<int>(g->id_bits), reverse, keys, t.err);
         MHR_HIP_TRY(hipGetLastError());
     }
     uint32_t herr = 0;
-    MHR_HIP_TRY(hipMemcpyAsync(&herr, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMemcpyAsync(&herr, t.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     MHR_HIP_TRY(hipStreamSynchronize(st));
     if (herr) {
         set_error("edge list holds a vertex id >= num_vertices or a relation id >= num_relations");
         return MHR_ERR_BAD_EDGE;
     }
-    mhr_status s = radix_sort(keys, tmp, m, 2 * static_cast<int>(g->id_bits) + 5, st);
+    mhr_status s = radix_sort(keys, tmp, m, 2 * static_cast<int>(g->id_bits) + 5, t.counts, t.sort_scratch, st);
     if (s != MHR_OK) return s;
 
-    DevBuf newpair, newtriple, pexcl, scratch, totals;
-    MHR_HIP_TRY(newpair.alloc(m * sizeof(uint32_t)));
-    MHR_HIP_TRY(newtriple.alloc(m * sizeof(uint32_t)));
-    MHR_HIP_TRY(pexcl.alloc(m * sizeof(uint32_t)));
-    MHR_HIP_TRY(scratch.alloc((cdiv(m, kScanChunk) + 1) * sizeof(uint32_t)));
-    MHR_HIP_TRY(totals.alloc(2 * sizeof(uint32_t)));
     if (m) {
-        hipLaunchKernelGGL(pair_flags_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, keys, m,
-                           newpair.as<uint32_t>(), newtriple.as<uint32_t>());
+        hipLaunchKernelGGL(pair_flags_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, keys, m, t.newpair, t.newtriple);
         MHR_HIP_TRY(hipGetLastError());
     }
-    s = device_exclusive_scan(newpair.as<uint32_t>(), pexcl.as<uint32_t>(), m, totals.as<uint32_t>(),
-                              scratch.as<uint32_t>(), st);
+    s = device_exclusive_scan(t.newpair, t.pexcl, m, t.totals, t.scratch, st);
     if (s != MHR_OK) return s;
     // triples: reuse newtriple as its own scan output; only the total matters
-    s = device_exclusive_scan(newtriple.as<uint32_t>(), newtriple.as<uint32_t>(), m, totals.as<uint32_t>() + 1,
-                              scratch.as<uint32_t>(), st);
+    s = device_exclusive_scan(t.newtriple, t.newtriple, m, t.totals + 1, t.scratch, st);
     if (s != MHR_OK) return s;
     uint32_t ht[2] = {0, 0};
-    MHR_HIP_TRY(hipMemcpyAsync(ht, totals.p, sizeof(ht), hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMemcpyAsync(ht, t.totals, sizeof(ht), hipMemcpyDeviceToHost, st));
     MHR_HIP_TRY(hipStreamSynchronize(st));
     const uint32_t num_pairs = ht[0];
     g->num_pairs = num_pairs;
     g->num_triples = ht[1];
 
-    MHR_HIP_TRY(hipMalloc(&csr.row_ptr, (static_cast<size_t>(n) + 1) * sizeof(uint32_t)));
-    MHR_HIP_TRY(hipMalloc(&csr.col, std::max<size_t>(num_pairs, 1) * sizeof(uint32_t)));
-    MHR_HIP_TRY(hipMalloc(&csr.rmask, std::max<size_t>(num_pairs, 1) * sizeof(uint32_t)));
-    g->device_bytes += (static_cast<uint64_t>(n) + 1 + 2ull * num_pairs) * sizeof(uint32_t);
+    const uint64_t cap_pairs = mem.csr ? m : num_pairs;   // caller buffer: sized before the pair count is known
+    const size_t used0 = mem.csr ? mem.csr->used : 0;
+    MHR_HIP_TRY(mem.keep(&csr.row_ptr, static_cast<size_t>(n) + 1));
+    MHR_HIP_TRY(mem.keep(&csr.col, cap_pairs));
+    MHR_HIP_TRY(mem.keep(&csr.rmask, cap_pairs));
     MHR_HIP_TRY(hipMemsetAsync(csr.rmask, 0, std::max<size_t>(num_pairs, 1) * sizeof(uint32_t), st));
     MHR_HIP_TRY(hipMemsetAsync(csr.row_ptr, 0, (static_cast<size_t>(n) + 1) * sizeof(uint32_t), st));
     if (m) {
-        hipLaunchKernelGGL(fill_csr_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, keys, m, newpair.as<uint32_t>(),
-                           pexcl.as<uint32_t>(), static_cast<int>(g->id_bits), n, num_pairs, csr.row_ptr, csr.col,
-                           csr.rmask);
+        hipLaunchKernelGGL(fill_csr_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, keys, m, t.newpair, t.pexcl,
+                           static_cast<int>(g->id_bits), n, num_pairs, csr.row_ptr, csr.col, csr.rmask);
         MHR_HIP_TRY(hipGetLastError());
     }
 
     // directories of long rows
-    DevBuf sizes, sexcl, heavy, hn, maxdeg, tot;
-    MHR_HIP_TRY(sizes.alloc(static_cast<size_t>(n) * sizeof(uint32_t)));
-    MHR_HIP_TRY(sexcl.alloc(static_cast<size_t>(n) * sizeof(uint32_t)));
-    MHR_HIP_TRY(heavy.alloc(static_cast<size_t>(n) * sizeof(uint32_t)));
-    MHR_HIP_TRY(hn.alloc(sizeof(uint32_t)));
-    MHR_HIP_TRY(maxdeg.alloc(sizeof(uint32_t)));
-    MHR_HIP_TRY(tot.alloc(sizeof(uint32_t)));
-    MHR_HIP_TRY(hipMemsetAsync(hn.p, 0, sizeof(uint32_t), st));
-    MHR_HIP_TRY(hipMemsetAsync(maxdeg.p, 0, sizeof(uint32_t), st));
-    hipLaunchKernelGGL(dir_sizes_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, csr.row_ptr, n,
-                       sizes.as<uint32_t>(), maxdeg.as<uint32_t>(), heavy.as<uint32_t>(), hn.as<uint32_t>());
+    MHR_HIP_TRY(hipMemsetAsync(t.hn, 0, sizeof(uint32_t), st));
+    MHR_HIP_TRY(hipMemsetAsync(t.maxdeg, 0, sizeof(uint32_t), st));
+    hipLaunchKernelGGL(dir_sizes_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, csr.row_ptr, n, t.sizes, t.maxdeg,
+                       t.heavy, t.hn);
     MHR_HIP_TRY(hipGetLastError());
-    DevBuf scratch2;
-    MHR_HIP_TRY(scratch2.alloc((cdiv(n, kScanChunk) + 1) * sizeof(uint32_t)));
-    s = device_exclusive_scan(sizes.as<uint32_t>(), sexcl.as<uint32_t>(), n, tot.as<uint32_t>(),
-                              scratch2.as<uint32_t>(), st);
+    s = device_exclusive_scan(t.sizes, t.sexcl, n, t.tot, t.scratch2, st);
     if (s != MHR_OK) return s;
     uint32_t hv[3] = {0, 0, 0};
-    MHR_HIP_TRY(hipMemcpyAsync(&hv[0], hn.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    MHR_HIP_TRY(hipMemcpyAsync(&hv[1], maxdeg.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    MHR_HIP_TRY(hipMemcpyAsync(&hv[2], tot.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMemcpyAsync(&hv[0], t.hn, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMemcpyAsync(&hv[1], t.maxdeg, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMemcpyAsync(&hv[2], t.tot, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     MHR_HIP_TRY(hipStreamSynchronize(st));
     csr.heavy_rows = hv[0];
     csr.max_degree = hv[1];
     csr.dir_pool_len = hv[2];
-    MHR_HIP_TRY(hipMalloc(&csr.dir_off, std::max<size_t>(n, 1) * sizeof(uint32_t)));
-    MHR_HIP_TRY(hipMalloc(&csr.dir_pool, std::max<size_t>(csr.dir_pool_len, 1) * sizeof(uint32_t)));
-    g->device_bytes += (static_cast<uint64_t>(n) + csr.dir_pool_len) * sizeof(uint32_t);
-    hipLaunchKernelGGL(dir_off_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, sizes.as<uint32_t>(),
-                       sexcl.as<uint32_t>(), n, csr.dir_off);
+    if (mem.csr && csr.dir_pool_len > dir_pool_bound(m)) {   // cannot happen (each row takes <= deg + 1 words)
+        set_error("directory pool exceeds its bound");
+        return MHR_ERR_DEVICE;
+    }
+    MHR_HIP_TRY(mem.keep(&csr.dir_off, n));
+    MHR_HIP_TRY(mem.keep(&csr.dir_pool, mem.csr ? dir_pool_bound(m) : csr.dir_pool_len));
+    g->device_bytes += mem.csr ? mem.csr->used - used0 : csr_bytes(n, num_pairs, csr.dir_pool_len);
+    hipLaunchKernelGGL(dir_off_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, t.sizes, t.sexcl, n, csr.dir_off);
     if (csr.heavy_rows)
-        hipLaunchKernelGGL(dir_fill_kernel, dim3(csr.heavy_rows), dim3(256), 0, st, heavy.as<uint32_t>(),
-                           csr.row_ptr, csr.col, csr.dir_off, static_cast<int>(g->id_bits), csr.dir_pool);
+        hipLaunchKernelGGL(dir_fill_kernel, dim3(csr.heavy_rows), dim3(256), 0, st, t.heavy, csr.row_ptr, csr.col,
+                           csr.dir_off, static_cast<int>(g->id_bits), csr.dir_pool);
     MHR_HIP_TRY(hipGetLastError());
     MHR_HIP_TRY(hipStreamSynchronize(st));
     return MHR_OK;
 }
 
-void free_csr(mhr::Csr &c) {
+void free_csr(mhr::Csr &c, bool owned) {
+    if (!owned) {
+        c = mhr::Csr();
+        return;
+    }
     if (c.row_ptr) (void)hipFree(c.row_ptr);
     if (c.col) (void)hipFree(c.col);
     if (c.rmask) (void)hipFree(c.rmask);
@@ -420,13 +521,25 @@ void free_csr(mhr::Csr &c) {
 
 using namespace mhr;
 
-extern "C" mhr_status mhr_graph_create(const mhr_graph_desc *d, void *stream, mhr_graph **out) {
-    MHR_ARG_CHECK(d != nullptr && out != nullptr, "mhr_graph_create: null argument");
+namespace {
+
+mhr_status check_desc(const mhr_graph_desc *d) {
+    MHR_ARG_CHECK(d != nullptr, "graph descriptor is null");
     MHR_ARG_CHECK(d->num_vertices >= 1 && d->num_vertices < 0xFFFFFFFFu, "num_vertices must be in [1, 2^32-2]");
     MHR_ARG_CHECK(d->num_relations >= 1 && d->num_relations <= MHR_MAX_RELATIONS, "num_relations must be in [1, 32]");
     MHR_ARG_CHECK(d->num_edges < 0xFFFFFFFFull, "num_edges must be < 2^32");
     MHR_ARG_CHECK(d->num_edges == 0 || (d->head && d->rel && d->tail), "edge arrays must not be null");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return MHR_OK;
+}
+
+uint32_t id_bits_for(uint32_t n) {
+    uint32_t bits = 1;
+    while (bits < 32 && (1ull << bits) < n) ++bits;
+    return bits;
+}
+
+// Both directions of the build; mem says where the memory comes from.
+mhr_status create_graph(const mhr_graph_desc *d, BuildMem &mem, hipStream_t st, mhr_graph **out) {
     mhr_graph *g = new (std::nothrow) mhr_graph();
     if (!g) {
         set_error("host allocation failed");
@@ -434,20 +547,21 @@ extern "C" mhr_status mhr_graph_create(const mhr_graph_desc *d, void *stream, mh
     }
     g->n = d->num_vertices;
     g->R = d->num_relations;
-    uint32_t bits = 1;
-    while (bits < 32 && (1ull << bits) < g->n) ++bits;
-    g->id_bits = bits;
-    if (2 * bits + 5 > 64) {
+    g->id_bits = id_bits_for(g->n);
+    g->owns_csr = mem.csr == nullptr;
+    if (2 * g->id_bits + 5 > 64) {
         delete g;
         set_error("too many vertices for the 64-bit sort key");
         return MHR_ERR_UNSUPPORTED;
     }
     (void)hipGetDevice(&g->device);
-    mhr_status s = build_direction(g, d, 0, g->out, st);
-    if (s == MHR_OK) s = build_direction(g, d, 1, g->in, st);
+    Temps t;
+    mhr_status s = alloc_temps(mem, g->n, d->num_edges, t);
+    if (s == MHR_OK) s = build_direction(g, d, 0, g->out, mem, t, st);
+    if (s == MHR_OK) s = build_direction(g, d, 1, g->in, mem, t, st);
     if (s != MHR_OK) {
-        free_csr(g->out);
-        free_csr(g->in);
+        free_csr(g->out, g->owns_csr);
+        free_csr(g->in, g->owns_csr);
         delete g;
         return s;
     }
@@ -455,10 +569,61 @@ extern "C" mhr_status mhr_graph_create(const mhr_graph_desc *d, void *stream, mh
     return MHR_OK;
 }
 
+}  // namespace
+
+extern "C" mhr_status mhr_graph_buffer_sizes(uint32_t num_vertices, uint32_t num_relations, uint64_t num_edges,
+                                             size_t *csr_buffer_bytes, size_t *tmp_buffer_bytes) {
+    MHR_ARG_CHECK(csr_buffer_bytes && tmp_buffer_bytes, "mhr_graph_buffer_sizes: null argument");
+    mhr_graph_desc d{};
+    d.num_vertices = num_vertices;
+    d.num_relations = num_relations;
+    d.num_edges = num_edges;
+    d.head = d.rel = d.tail = reinterpret_cast<const uint32_t *>(kPiece);   // shape check only
+    mhr_status s = check_desc(&d);
+    if (s != MHR_OK) return s;
+    *csr_buffer_bytes = 2 * csr_bytes(num_vertices, num_edges, dir_pool_bound(num_edges));
+    *tmp_buffer_bytes = temp_bytes(num_vertices, num_edges);
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_graph_create(const mhr_graph_desc *d, void *stream, mhr_graph **out) {
+    MHR_ARG_CHECK(out != nullptr, "mhr_graph_create: null argument");
+    mhr_status s = check_desc(d);
+    if (s != MHR_OK) return s;
+    BuildMem mem;
+    return create_graph(d, mem, static_cast<hipStream_t>(stream), out);
+}
+
+extern "C" mhr_status mhr_graph_create_in(const mhr_graph_desc *d, void *csr_buffer, size_t csr_buffer_bytes,
+                                          void *tmp_buffer, size_t tmp_buffer_bytes, void *stream, mhr_graph **out) {
+    MHR_ARG_CHECK(out != nullptr && csr_buffer != nullptr && tmp_buffer != nullptr,
+                  "mhr_graph_create_in: null argument");
+    mhr_status s = check_desc(d);
+    if (s != MHR_OK) return s;
+    MHR_ARG_CHECK((reinterpret_cast<uintptr_t>(csr_buffer) % kPiece) == 0 &&
+                      (reinterpret_cast<uintptr_t>(tmp_buffer) % kPiece) == 0,
+                  "graph buffers must be 256-byte aligned");
+    size_t need_csr = 0, need_tmp = 0;
+    s = mhr_graph_buffer_sizes(d->num_vertices, d->num_relations, d->num_edges, &need_csr, &need_tmp);
+    if (s != MHR_OK) return s;
+    if (csr_buffer_bytes < need_csr || tmp_buffer_bytes < need_tmp) {
+        set_error("graph buffers smaller than mhr_graph_buffer_sizes: csr " + std::to_string(csr_buffer_bytes) +
+                  " < " + std::to_string(need_csr) + " or tmp " + std::to_string(tmp_buffer_bytes) + " < " +
+                  std::to_string(need_tmp));
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    Arena csr{static_cast<char *>(csr_buffer), csr_buffer_bytes, 0};
+    Arena tmp{static_cast<char *>(tmp_buffer), tmp_buffer_bytes, 0};
+    BuildMem mem;
+    mem.csr = &csr;
+    mem.tmp = &tmp;
+    return create_graph(d, mem, static_cast<hipStream_t>(stream), out);
+}
+
 extern "C" mhr_status mhr_graph_destroy(mhr_graph *g) {
     if (!g) return MHR_OK;
-    free_csr(g->out);
-    free_csr(g->in);
+    free_csr(g->out, g->owns_csr);
+    free_csr(g->in, g->owns_csr);
     delete g;
     return MHR_OK;
 }

@@ -77,6 +77,7 @@ struct mhr_graph {
     float gamma = 1.0f;           // TransE-L1 constant
     uint64_t device_bytes = 0;
     int device = 0;
+    bool owns_csr = true;         // false: the CSR arrays live in the caller's buffer
 };
 
 namespace mhr {

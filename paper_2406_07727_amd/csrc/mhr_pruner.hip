@@ -851,11 +851,31 @@ using namespace mhr;
 
 extern "C" size_t mhr_pruner_param_count(uint32_t dim, uint32_t hidden) { return play(dim, hidden).n; }
 
-extern "C" mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_pruner **out) {
-    MHR_ARG_CHECK(out != nullptr, "mhr_pruner_create: null output");
-    MHR_ARG_CHECK(dim >= 8 && dim <= 512 && dim % 8 == 0, "mhr_pruner_create: dim must be a multiple of 8 in [8, 512]");
+namespace {
+
+constexpr size_t kPrunerPiece = 256;
+inline size_t prpiece(size_t b) { return (std::max<size_t>(b, 1) + kPrunerPiece - 1) / kPrunerPiece * kPrunerPiece; }
+
+// Byte sizes of the handle's arrays, in buffer order: theta, grad, m, v
+// (FP32), then the bfloat16 copies of W1, W2 and w3.
+void pruner_pieces(uint32_t dim, uint32_t hidden, size_t (&b)[7]) {
+    const PLayout L = play(dim, hidden);
+    b[0] = b[1] = b[2] = b[3] = L.n * 4;
+    b[4] = (L.b1 - L.W1) * 2;
+    b[5] = (L.b2 - L.W2) * 2;
+    b[6] = size_t(hidden) * 2;
+}
+
+mhr_status check_shape(uint32_t dim, uint32_t hidden) {
+    MHR_ARG_CHECK(dim >= 8 && dim <= 512 && dim % 8 == 0, "pruner: dim must be a multiple of 8 in [8, 512]");
     MHR_ARG_CHECK(hidden >= 16 && hidden <= 4096 && hidden % 16 == 0,
-                  "mhr_pruner_create: hidden must be a multiple of 16 in [16, 4096]");
+                  "pruner: hidden must be a multiple of 16 in [16, 4096]");
+    return MHR_OK;
+}
+
+// buffer: the caller's (bytes from mhr_pruner_buffer_bytes), or null to
+// allocate the arrays here.
+mhr_status create_pruner(uint32_t dim, uint32_t hidden, void *buffer, hipStream_t st, mhr_pruner **out) {
     mhr_pruner *p = new (std::nothrow) mhr_pruner;
     if (!p) {
         set_error("mhr_pruner_create: out of host memory");
@@ -865,20 +885,37 @@ extern "C" mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_prune
     p->H = hidden;
     const PLayout L = play(dim, hidden);
     p->np = L.n;
-    bool ok = hipMalloc(&p->theta, L.n * 4) == hipSuccess && hipMalloc(&p->grad, L.n * 4) == hipSuccess &&
-              hipMalloc(&p->m, L.n * 4) == hipSuccess && hipMalloc(&p->v, L.n * 4) == hipSuccess &&
-              hipMalloc(&p->W1b, (L.b1 - L.W1) * 2) == hipSuccess &&
-              hipMalloc(&p->W2b, (L.b2 - L.W2) * 2) == hipSuccess && hipMalloc(&p->w3b, size_t(hidden) * 2) == hipSuccess;
+    p->owns = buffer == nullptr;
+    size_t b[7];
+    pruner_pieces(dim, hidden, b);
+    void *ptr[7] = {};
+    bool ok = true;
+    char *at = static_cast<char *>(buffer);
+    for (int i = 0; i < 7; ++i) {
+        if (buffer) {
+            ptr[i] = at;
+            at += prpiece(b[i]);
+        } else {
+            ok = ok && hipMalloc(&ptr[i], prpiece(b[i])) == hipSuccess;
+        }
+    }
+    p->theta = static_cast<float *>(ptr[0]);
+    p->grad = static_cast<float *>(ptr[1]);
+    p->m = static_cast<float *>(ptr[2]);
+    p->v = static_cast<float *>(ptr[3]);
+    p->W1b = static_cast<uint16_t *>(ptr[4]);
+    p->W2b = static_cast<uint16_t *>(ptr[5]);
+    p->w3b = static_cast<uint16_t *>(ptr[6]);
     if (!ok) {
         mhr_pruner_destroy(p);
         set_error("mhr_pruner_create: device allocation failed");
         return MHR_ERR_OUT_OF_MEMORY;
     }
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->theta, L.n, 0.0f);
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->grad, L.n, 0.0f);
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->m, L.n, 0.0f);
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, nullptr, p->v, L.n, 0.0f);
-    if (refresh_bf16(p, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, st, p->theta, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, st, p->grad, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, st, p->m, L.n, 0.0f);
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(L.n)), dim3(256), 0, st, p->v, L.n, 0.0f);
+    if (refresh_bf16(p, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
         mhr_pruner_destroy(p);
         set_error("mhr_pruner_create: initialisation failed");
         return MHR_ERR_DEVICE;
@@ -887,15 +924,53 @@ extern "C" mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_prune
     return MHR_OK;
 }
 
+}  // namespace
+
+extern "C" mhr_status mhr_pruner_buffer_bytes(uint32_t dim, uint32_t hidden, size_t *bytes) {
+    MHR_ARG_CHECK(bytes != nullptr, "mhr_pruner_buffer_bytes: null output");
+    mhr_status s = check_shape(dim, hidden);
+    if (s != MHR_OK) return s;
+    size_t b[7], t = 0;
+    pruner_pieces(dim, hidden, b);
+    for (size_t x : b) t += prpiece(x);
+    *bytes = t;
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_create(uint32_t dim, uint32_t hidden, mhr_pruner **out) {
+    MHR_ARG_CHECK(out != nullptr, "mhr_pruner_create: null output");
+    mhr_status s = check_shape(dim, hidden);
+    if (s != MHR_OK) return s;
+    return create_pruner(dim, hidden, nullptr, nullptr, out);
+}
+
+extern "C" mhr_status mhr_pruner_create_in(uint32_t dim, uint32_t hidden, void *buffer, size_t bytes, void *stream,
+                                           mhr_pruner **out) {
+    MHR_ARG_CHECK(out != nullptr && buffer != nullptr, "mhr_pruner_create_in: null argument");
+    MHR_ARG_CHECK(reinterpret_cast<uintptr_t>(buffer) % kPrunerPiece == 0,
+                  "mhr_pruner_create_in: buffer must be 256-byte aligned");
+    size_t need = 0;
+    mhr_status s = mhr_pruner_buffer_bytes(dim, hidden, &need);
+    if (s != MHR_OK) return s;
+    if (bytes < need) {
+        set_error("mhr_pruner_create_in: buffer of " + std::to_string(bytes) + " bytes, " + std::to_string(need) +
+                  " needed");
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    return create_pruner(dim, hidden, buffer, static_cast<hipStream_t>(stream), out);
+}
+
 extern "C" mhr_status mhr_pruner_destroy(mhr_pruner *p) {
     if (!p) return MHR_OK;
-    (void)hipFree(p->theta);
-    (void)hipFree(p->grad);
-    (void)hipFree(p->m);
-    (void)hipFree(p->v);
-    (void)hipFree(p->W1b);
-    (void)hipFree(p->W2b);
-    (void)hipFree(p->w3b);
+    if (p->owns) {
+        (void)hipFree(p->theta);
+        (void)hipFree(p->grad);
+        (void)hipFree(p->m);
+        (void)hipFree(p->v);
+        (void)hipFree(p->W1b);
+        (void)hipFree(p->W2b);
+        (void)hipFree(p->w3b);
+    }
     delete p;
     return MHR_OK;
 }

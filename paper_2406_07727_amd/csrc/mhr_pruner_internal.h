@@ -13,6 +13,7 @@ struct mhr_pruner {
     float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // FP32 master weights, gradient, Adam moments
     uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;                 // bfloat16 copies for the products
     uint32_t step = 0;                  // Adam step count
+    bool owns = true;                   // false: the arrays live in the caller's buffer
 };
 
 namespace mhr {

@@ -48,9 +48,9 @@ constexpr int kBlock = 512;
 constexpr int kEPT = 8;                   // scan entries per thread per chunk
 constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
-constexpr int kSlab = 2560;               // scored edge values per sub-batch
+constexpr int kSlab = 5 * kBlock;               // scored edge values per sub-batch
 constexpr int kQueue = kChunk + kBlock;    // queued matches: a partial sub-batch plus one chunk's hits
-constexpr int kStage = 768;               // staged candidates before a merge
+constexpr int kStage = 3 * kBlock / 2;               // staged candidates before a merge
 constexpr uint32_t kMaxQuota = 8;         // candidates a thread stages per round
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kDefaultTileEdges = 32768;
@@ -1070,14 +1070,17 @@ enum GatherPhase {
     kNumPhases
 };
 #ifdef MHR_PHASE_CLOCKS
-__device__ unsigned long long g_phase_ticks[kNumPhases];
-#define MHR_PHASE(p)                                           \
-    do {                                                       \
-        if (tid == 0) {                                        \
-            const unsigned long long now_ = wall_clock64();    \
-            ph_acc[p] += now_ - ph_t;                          \
-            ph_t = now_;                                       \
-        }                                                      \
+// [0, kNumPhases): tiles whose probe side is in the LDS table;
+// [kNumPhases, 2 kNumPhases): tiles probing through the row directory;
+// then the number of tiles of each kind.
+__device__ unsigned long long g_phase_ticks[2 * kNumPhases + 2];
+#define MHR_PHASE(p)                                                      \
+    do {                                                                  \
+        if (tid == 0) {                                                   \
+            const unsigned long long now_ = wall_clock64();               \
+            ph_acc[(p) + (ph_heavy ? kNumPhases : 0)] += now_ - ph_t;     \
+            ph_t = now_;                                                  \
+        }                                                                 \
     } while (0)
 #else
 #define MHR_PHASE(p) \
@@ -1089,9 +1092,10 @@ __device__ unsigned long long g_phase_ticks[kNumPhases];
 template <bool BF16, bool EXACT, int KC, bool TE>
 __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
 #ifdef MHR_PHASE_CLOCKS
-    __shared__ unsigned long long ph_acc[kNumPhases];
+    __shared__ unsigned long long ph_acc[2 * kNumPhases + 2];
     __shared__ unsigned long long ph_t;
-    if (threadIdx.x < kNumPhases) ph_acc[threadIdx.x] = 0;
+    bool ph_heavy = false;   // the current tile probes through the directory (thread 0's copy)
+    if (threadIdx.x < 2 * kNumPhases + 2) ph_acc[threadIdx.x] = 0;
     if (threadIdx.x == 0) ph_t = wall_clock64();
 #endif
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1192,6 +1196,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         const uint32_t anchor_p = fwd ? P.t : P.s;
         const bool heavy = P.probe_len > hcap;
         const float thr_exact = P.thr;
+#ifdef MHR_PHASE_CLOCKS
+        ph_heavy = heavy;
+        if (tid == 0) ph_acc[2 * kNumPhases + (heavy ? 1 : 0)] += 1;
+#endif
 
         // ---- tile setup
         for (uint32_t i = tid; i < d; i += kBlock) {
@@ -1927,7 +1935,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     }
 #ifdef MHR_PHASE_CLOCKS
     __syncthreads();
-    if (threadIdx.x < kNumPhases) atomicAdd(&g_phase_ticks[threadIdx.x], ph_acc[threadIdx.x]);
+    if (threadIdx.x < 2 * kNumPhases + 2) atomicAdd(&g_phase_ticks[threadIdx.x], ph_acc[threadIdx.x]);
 #endif
 }
 // ---------------------------------------------------------------------------
@@ -2658,16 +2666,21 @@ extern "C" mhr_status mhr_topk_paths_noalloc(const mhr_graph *g, const mhr_query
 
 // Phase clocks of the gather kernel (see GatherPhase): copies the summed
 // per-workgroup wall-clock ticks of every phase since the last reset to out
-// (host, n entries), the clock's rate in Hz to *rate_hz, and resets them if
-// reset != 0.  Synchronises the device.  Only a build with MHR_PHASE_CLOCKS
-// records them; other builds return MHR_ERR_UNSUPPORTED.
+// (host, n entries: out[i] for phase i over all tiles; when n >= 2 *
+// kNumPhases + 2 also out[kNumPhases + i] for the tiles that probe through
+// the row directory alone, then the tile counts of the table and directory
+// kinds), the clock's rate in Hz to *rate_hz, and resets them if reset !=
+// 0.  Synchronises the device.  Only a build with MHR_PHASE_CLOCKS records
+// them; other builds return MHR_ERR_UNSUPPORTED.
 extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *rate_hz, int reset) {
 #ifdef MHR_PHASE_CLOCKS
     MHR_ARG_CHECK(out != nullptr && n >= static_cast<uint32_t>(kNumPhases), "mhr_debug_phase_ticks: bad output");
     MHR_HIP_TRY(hipDeviceSynchronize());
-    unsigned long long h[kNumPhases];
+    unsigned long long h[2 * kNumPhases + 2];
     MHR_HIP_TRY(hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase_ticks), sizeof(h)));
-    for (int i = 0; i < kNumPhases; ++i) out[i] = h[i];
+    for (int i = 0; i < kNumPhases; ++i) out[i] = h[i] + h[kNumPhases + i];
+    if (n >= static_cast<uint32_t>(2 * kNumPhases + 2))
+        for (int i = kNumPhases; i < 2 * kNumPhases + 2; ++i) out[i] = h[i];
     if (rate_hz) {
         int dev = 0, khz = 0;
         MHR_HIP_TRY(hipGetDevice(&dev));
@@ -2675,7 +2688,7 @@ extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *r
         *rate_hz = 1e3 * static_cast<double>(khz);
     }
     if (reset) {
-        const unsigned long long z[kNumPhases] = {};
+        const unsigned long long z[2 * kNumPhases + 2] = {};
         MHR_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), z, sizeof(z)));
         MHR_HIP_TRY(hipDeviceSynchronize());
     }

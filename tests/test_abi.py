@@ -79,3 +79,70 @@ def test_binding_record_layout():
     for name, _ in fields:
         assert getattr(CPath, name).offset == dt.fields[name][1], name
     assert dt["score"] == np.float32 and dt["err_bound"] == np.float32
+
+
+def test_graph_buffer_sizes_and_host_checks(lib):
+    """mhr_graph_buffer_sizes covers both CSRs at their worst case; the
+    caller-buffer constructor rejects null, misaligned and short buffers on
+    the host, before any device call."""
+    sz = ctypes.c_size_t
+    lib.mhr_graph_buffer_sizes.restype = ctypes.c_int
+    lib.mhr_graph_buffer_sizes.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                           ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    c, t = sz(), sz()
+    n, m = 1000, 20000
+    assert lib.mhr_graph_buffer_sizes(n, 4, m, ctypes.byref(c), ctypes.byref(t)) == 0
+    # per direction: row_ptr, col and mask of every triple, dir_off, and the pool bound
+    assert c.value >= 2 * 4 * ((n + 1) + 2 * m + n + m)
+    assert t.value >= 8 * 2 * m + 4 * 3 * m + 4 * 3 * n     # sort keys, pair flags and scans, directory sizes
+    c2, t2 = sz(), sz()
+    assert lib.mhr_graph_buffer_sizes(n, 4, 2 * m, ctypes.byref(c2), ctypes.byref(t2)) == 0
+    assert c2.value > c.value and t2.value > t.value
+    assert lib.mhr_graph_buffer_sizes(n, 33, m, ctypes.byref(c), ctypes.byref(t)) == 1    # R > 32
+    assert lib.mhr_graph_buffer_sizes(0, 4, m, ctypes.byref(c), ctypes.byref(t)) == 1     # no vertices
+
+    class Desc(ctypes.Structure):
+        _fields_ = [("num_vertices", ctypes.c_uint32), ("num_relations", ctypes.c_uint32),
+                    ("num_edges", ctypes.c_uint64), ("head", ctypes.c_void_p), ("rel", ctypes.c_void_p),
+                    ("tail", ctypes.c_void_p)]
+
+    lib.mhr_graph_create_in.restype = ctypes.c_int
+    lib.mhr_graph_create_in.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, sz, ctypes.c_void_p, sz,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.mhr_graph_buffer_sizes(n, 4, m, ctypes.byref(c), ctypes.byref(t)) == 0
+    d = Desc(n, 4, m, 4096, 8192, 12288)       # never dereferenced: every check below is on the host
+    out = ctypes.c_void_p()
+    assert lib.mhr_graph_create_in(ctypes.byref(d), 1 << 20, c.value - 1, 2 << 20, t.value, None,
+                                   ctypes.byref(out)) == 2            # WORKSPACE_TOO_SMALL
+    assert lib.mhr_graph_create_in(ctypes.byref(d), 1 << 20, c.value, 2 << 20, t.value - 1, None,
+                                   ctypes.byref(out)) == 2
+    assert lib.mhr_graph_create_in(ctypes.byref(d), (1 << 20) + 16, c.value, 2 << 20, t.value, None,
+                                   ctypes.byref(out)) == 1            # not 256-byte aligned
+    assert lib.mhr_graph_create_in(ctypes.byref(d), None, c.value, 2 << 20, t.value, None, ctypes.byref(out)) == 1
+    assert out.value is None
+
+
+def test_pruner_buffer_bytes_and_host_checks(lib):
+    """The pruner's caller buffer holds four FP32 parameter-sized arrays and
+    the three bfloat16 weight copies; short or misaligned buffers are refused
+    on the host."""
+    sz = ctypes.c_size_t
+    lib.mhr_pruner_buffer_bytes.restype = ctypes.c_int
+    lib.mhr_pruner_buffer_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(sz)]
+    lib.mhr_pruner_param_count.restype = ctypes.c_size_t
+    lib.mhr_pruner_param_count.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    b = sz()
+    assert lib.mhr_pruner_buffer_bytes(256, 512, ctypes.byref(b)) == 0
+    npar = lib.mhr_pruner_param_count(256, 512)
+    weights = 4 * 256 * 512 + 512 * 512 + 512     # W1, W2, w3 (biases stay FP32 only)
+    assert b.value >= 16 * npar + 2 * weights
+    assert b.value < 16 * npar + 2 * weights + 7 * 256
+    assert lib.mhr_pruner_buffer_bytes(7, 512, ctypes.byref(b)) == 1
+    lib.mhr_pruner_create_in.restype = ctypes.c_int
+    lib.mhr_pruner_create_in.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, sz, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.mhr_pruner_buffer_bytes(64, 64, ctypes.byref(b)) == 0
+    out = ctypes.c_void_p()
+    assert lib.mhr_pruner_create_in(64, 64, 1 << 20, b.value - 1, None, ctypes.byref(out)) == 2
+    assert lib.mhr_pruner_create_in(64, 64, (1 << 20) + 8, b.value, None, ctypes.byref(out)) == 1
+    assert out.value is None

@@ -1,7 +1,8 @@
 """Checkpoint and tuning-cache files on the GPU: a pruner saved after some
 Adam steps and loaded into a fresh handle resumes training identically (the
 same parameters after further steps); a damaged checkpoint is refused before
-anything is copied; tuned settings saved for a graph and batch come back
+anything is copied (the resumed handle keeps its state in a caller-owned
+buffer); tuned settings saved for a graph and batch come back
 for that key only."""
 
 import numpy as np
@@ -42,7 +43,7 @@ def test_pruner_checkpoint_resume(tmp_path):
     path = str(tmp_path / "pruner.ckpt")
     a.save(path)
     assert mhr.pruner_file_info(path) == (dim, H, 3)
-    b = mhr.Pruner(dim, H)
+    b = mhr.Pruner(dim, H, caller_buffer=True)   # resumed in caller-owned memory (mhr_pruner_create_in)
     b.load(path)
     assert np.array_equal(a.params().cpu().numpy(), b.params().cpu().numpy())
     for _ in range(2):

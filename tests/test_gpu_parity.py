@@ -287,6 +287,45 @@ def test_csr_matches_numpy_construction():
     assert st["num_triples"] == len(np.unique((h.astype(np.int64) * n + t) * R + r))
 
 
+def test_caller_buffer_graph_matches_library_allocation():
+    """A graph built in caller buffers (mhr_graph_create_in) holds the same
+    CSRs as one the library allocates itself, long rows and their
+    directories included, and answers queries identically."""
+    import torch
+    import paper_2406_07727_amd as mhr
+    cfg, (h, r, t), (X, Y), (s, d, k) = workload("hub_tiny")
+    n, R = cfg.graph.n, cfg.graph.R
+    # two hubs of 1,500 out- and in-neighbours: rows long enough for directories
+    rng = np.random.Generator(np.random.PCG64(21))
+    hub_out = rng.choice(n, 1500, replace=False).astype(np.uint32)
+    hub_in = rng.choice(n, 1500, replace=False).astype(np.uint32)
+    H = np.concatenate([h, np.full(1500, 3, np.uint32), hub_in]).astype(np.uint32)
+    T = np.concatenate([t, hub_out, np.full(1500, 5, np.uint32)]).astype(np.uint32)
+    Rr = np.concatenate([r, rng.integers(0, R, 3000).astype(np.uint32)]).astype(np.uint32)
+    say("case caller-buffer graph")
+    own = mhr.Graph(H, Rr, T, n, R)
+    cal = mhr.Graph(H, Rr, T, n, R, caller_buffers=True)
+    so, sc = own.stats(), cal.stats()
+    for f in ("num_triples", "num_pairs", "max_out_degree", "max_in_degree", "heavy_rows_out", "heavy_rows_in"):
+        assert so[f] == sc[f], f
+    assert sc["heavy_rows_out"] >= 1 and sc["heavy_rows_in"] >= 1
+    assert 0 < sc["device_bytes"] <= mhr.graph_buffer_sizes(n, R, len(H))[0]
+    for rev in (False, True):
+        for a, b in zip(own.export_csr(reverse=rev), cal.export_csr(reverse=rev)):
+            assert torch.equal(a, b)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    own.set_embeddings(Xd, Yd)
+    cal.set_embeddings(Xd, Yd)
+    qs = np.concatenate([s, np.array([3, 3, 7], np.uint32)]).astype(np.uint32)
+    qd = np.concatenate([d, np.array([5, 9, 5], np.uint32)]).astype(np.uint32)
+    ro = own.topk(qs, qd, 16).to_numpy()
+    rc = cal.topk(qs, qd, 16).to_numpy()
+    for a, b in zip(ro, rc):
+        assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+    cal.close()
+    own.close()
+
+
 @pytest.mark.parametrize("name", ["tiny", "hub_tiny"])
 def test_edge_weights_against_oracle(name):
     cfg, (h, r, t), (X, Y), _ = workload(name)
