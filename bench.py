@@ -458,6 +458,16 @@ def run_pruner(args, cfg, g, h, s, d):
            "loss_last": round(float(np.mean(losses[-20:])), 4), "keep_permille": 100,
            "exact_queries_per_s": len(s) / t_exact}
     c = mhr.candidates(g, s, d)
+    # the network over every frontier candidate of the held-out batch
+    # (mhr_pruner_score); algorithmic flops: the candidate's share of the
+    # first layer, the second layer and the output per candidate, the
+    # endpoints' share per query and hop, the relations' share once
+    dim, H = cfg.emb.d, args.hidden
+    _, t_score = timed(lambda: lp.logits(c), args.steps)
+    flops = c.n * 2 * (dim * H + H * H + H) + len(s) * 2 * 2 * (2 * dim) * H + cfg.graph.R * 2 * dim * H
+    out["scoring"] = {"candidates": c.n, "ms": round(1e3 * t_score, 3), "candidates_per_s": c.n / t_score,
+                      "tflop_per_s": round(flops / t_score / 1e12, 1),
+                      "frac_bf16_peak": round(flops / t_score / 1e12 / 2500.0, 4)}
     for kind in ("net", "random", "beam"):
         sc = None if kind == "net" else lp.baseline_scores(c, kind, seed=5)
         res, st = lp.search(s, d, K, keep_permille=100, scores=sc, fallback=False)
@@ -636,9 +646,9 @@ def main():
         mhr.phase_ticks(reset=True)
         for i in range(args.steps):
             g.topk(sd, dd, kk, k_max=k_max, out=res, opts=qo)
-        ticks, rate = mhr.phase_ticks()
-        dticks, ntiles = mhr.phase_ticks_directory()
-        phases = {"ticks": ticks, "rate_hz": rate, "dir_ticks": dticks, "tiles": ntiles}
+        (tab, dirk), rate = mhr.phase_ticks(by_kind=True)
+        ticks = {p: tab[p] + dirk[p] for p in mhr.GATHER_PHASES}
+        phases = {"ticks": ticks, "rate_hz": rate, "kinds": (tab, dirk)}
     p, cnt, tot, st = res.to_numpy()
     paths = int(tot.sum())
     exact_pass = int(np.sum((st & mhr.Q_EXACT_PASS) != 0))
@@ -683,16 +693,16 @@ def main():
                 out_ph[k]["bytes"] = int(b)
                 if per_launch_s[k] > 0:
                     out_ph[k]["GB_s"] = round(b / per_launch_s[k] / 1e9, 1)
-        # the same split for the tiles whose probe side is too long for the
-        # LDS table (probes through the row directory)
-        dirs = {k: {"ms_per_launch": round(1e3 * v / rate / nblocks / args.steps, 4)}
-                for k, v in phases["dir_ticks"].items()}
+        # per tile kind (probe side in the LDS table, or probing through the
+        # row directory): phase times and the work counts per launch
+        kinds = {}
+        for name, kd in zip(("table", "directory"), phases["kinds"]):
+            kinds[name] = {"ms_per_launch": {p: round(1e3 * kd[p] / rate / nblocks / args.steps, 4)
+                                             for p in mhr.GATHER_PHASES},
+                           "counts_per_launch": {c: kd[c] // args.steps for c in mhr.GATHER_COUNTS}}
         log(f"gather phases: {json.dumps(out_ph)}")
-        log(f"directory-probe tiles: {json.dumps(dirs)}; tiles per launch (table, directory): "
-            f"{[x // args.steps for x in phases['tiles']]}")
-        print(json.dumps({"phases": out_ph, "directory_tiles": dirs,
-                          "tiles_table_directory": [x // args.steps for x in phases["tiles"]],
-                          "config": args.config, "steps": args.steps,
+        log(f"per tile kind: {json.dumps(kinds)}")
+        print(json.dumps({"phases": out_ph, "tile_kinds": kinds, "config": args.config, "steps": args.steps,
                           "note": "phase-clock build; wall time of the average workgroup per launch"}), flush=True)
         return
 

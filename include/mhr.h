@@ -549,6 +549,29 @@ mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint32_t n, con
                               const uint32_t *src, const uint32_t *dst, const uint32_t *v,
                               const uint32_t *r, float *logits, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes of mhr_pruner_score for nq queries of graph g, scoring
+ * `chunk` candidates per pass (chunk >= 1, at most 8,388,480). */
+mhr_status mhr_pruner_score_workspace_size(const mhr_pruner *p, const mhr_graph *g, uint32_t nq, uint32_t chunk,
+                                           size_t *bytes);
+
+/* Logits of ncand frontier candidates of a batch of nq queries (the network
+ * that ranks the frontier in place of the per-parent top-K of the generic
+ * search, section 5): candidate i is (v[i], r[i]) of query q[i] &
+ * ~MHR_PRUNER_HOP2 (second hop when bit 31 is set), endpoints src[...],
+ * dst[...].  The same network as mhr_pruner_forward, with the first layer
+ * split by input block: the endpoints' part once per (query, hop), the
+ * relation's part once per relation, the candidate's part per candidate,
+ * then the second layer and the output fused into one product per chunk of
+ * `chunk` candidates.  Requires q[i] & ~MHR_PRUNER_HOP2 < nq, v[i] <
+ * num_vertices and r[i] < num_relations (the candidates of
+ * mhr_pruner_enumerate do); an out-of-range v reads as a zero row and an
+ * out-of-range q or r gives a NaN logit.  Asynchronous on `stream`.
+ * Errors: INVALID_ARGUMENT, WORKSPACE_TOO_SMALL, DEVICE. */
+mhr_status mhr_pruner_score(mhr_pruner *p, const mhr_graph *g, uint32_t nq, const uint32_t *src,
+                            const uint32_t *dst, uint64_t ncand, const uint32_t *q, const uint32_t *v,
+                            const uint32_t *r, float *logits, uint32_t chunk, void *ws, size_t ws_bytes,
+                            void *stream);
+
 /* One training step on n labelled samples (label: device FP32 0/1 [n]):
  * forward, the mean binary cross-entropy with positive-class weight
  * pos_weight (written to *loss, device, if not NULL), the gradient (kept in
@@ -784,12 +807,16 @@ mhr_status mhr_scan_pipeline(mhr_dtype dtype, uint32_t dim, const void *entity, 
                              void *workspace, size_t ws_bytes, void *stream);
 
 /* Profiling aid: the gather kernel's per-phase wall-clock ticks, summed over
- * its workgroups since the last reset (phases: tile fetch, setup, list rows,
- * probe, sub-batch formation, scoring, log-sigmoids, bounds, enumeration,
- * stage merges, tile end; n >= 11), and the clock rate (Hz).  Recorded only
- * by the library's phase-clock build (paper_2406_07727_amd/build.py
- * --phase-clocks); the regular build returns MHR_ERR_UNSUPPORTED.
- * Synchronises the device. */
+ * its workgroups since the last reset, and its work counts, for each of two
+ * tile kinds (probe side in the LDS table; probing through the row
+ * directory).  out (host, n >= 42) receives per kind 11 phase sums (tile
+ * fetch, setup, list rows, probe, sub-batch formation, scoring,
+ * log-sigmoids, bounds, enumeration, stage merges, tile end) then 10 counts
+ * (tiles, row batches, chunks, scanned entries, sub-batches, matches, edge
+ * values, enumeration items, staged candidates, stage merges).  *rate_hz:
+ * the clock rate.  Recorded only by the library's phase-clock build
+ * (paper_2406_07727_amd/build.py --phase-clocks); the regular build returns
+ * MHR_ERR_UNSUPPORTED.  Synchronises the device. */
 mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *rate_hz, int reset);
 
 const char *mhr_status_string(mhr_status s);

@@ -136,6 +136,11 @@ _lib.mhr_pruner_param_count.restype = ctypes.c_size_t
 _lib.mhr_pruner_param_count.argtypes = [_u32, _u32]
 _lib.mhr_pruner_create.restype = _i
 _lib.mhr_pruner_create.argtypes = [_u32, _u32, ctypes.POINTER(_vp)]
+_lib.mhr_pruner_score_workspace_size.restype = _i
+_lib.mhr_pruner_score_workspace_size.argtypes = [_vp, _vp, _u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.mhr_pruner_score.restype = _i
+_lib.mhr_pruner_score.argtypes = [_vp, _vp, _u32, _vp, _vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _u32, _vp,
+                                  ctypes.c_size_t, _vp]
 _lib.mhr_pruner_buffer_bytes.restype = _i
 _lib.mhr_pruner_buffer_bytes.argtypes = [_u32, _u32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.mhr_pruner_create_in.restype = _i
@@ -709,6 +714,27 @@ class Pruner:
                                        _ptr(ws), ws.numel(), _stream_ptr(stream)), "mhr_pruner_forward")
         return out[:n]
 
+    def score(self, graph: Graph, src, dst, q, v, r, chunk: int = 1 << 18, stream=None):
+        """Logits (float32 [n]) of frontier candidates (q[i], v[i], r[i]) of
+        the queries (src, dst), through mhr_pruner_score (first layer split
+        by input block, output fused)."""
+        torch = _torch()
+        s, d, q, v, r = (_dev_u32(x) for x in (src, dst, q, v, r))
+        nq, n = s.numel(), q.numel()
+        out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        if n == 0:
+            return out[:0]
+        chunk = int(max(1, min(chunk, n)))
+        nb = ctypes.c_size_t()
+        _check(_lib.mhr_pruner_score_workspace_size(self._h, graph._h, nq, chunk, ctypes.byref(nb)),
+               "mhr_pruner_score_workspace_size")
+        if getattr(self, "_sws", None) is None or self._sws.numel() < nb.value:
+            self._sws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+        _check(_lib.mhr_pruner_score(self._h, graph._h, nq, _ptr(s), _ptr(d), n, _ptr(q), _ptr(v), _ptr(r),
+                                     _ptr(out), chunk, _ptr(self._sws), self._sws.numel(), _stream_ptr(stream)),
+               "mhr_pruner_score")
+        return out[:n]
+
     def train_step(self, graph: Graph, q, src, dst, v, r, label, pos_weight=1.0, lr=1e-3, beta1=0.9,
                    beta2=0.999, eps=1e-8, update=True, stream=None):
         """One step (forward, loss, gradient, Adam if update); returns the
@@ -884,27 +910,31 @@ def tuning_file_records(path: str) -> int:
 GATHER_PHASES = ("fetch", "setup", "rows", "probe", "form", "score", "logsig", "bounds", "enum", "merge", "end")
 
 
-def phase_ticks(reset: bool = False):
+GATHER_COUNTS = ("tiles", "row_batches", "chunks", "scanned", "sub_batches", "matches", "values", "items", "staged",
+                 "merges")
+
+
+def phase_ticks(reset: bool = False, by_kind: bool = False):
     """The gather kernel's per-phase wall-clock ticks summed over workgroups
     (phase-clock build only; see mhr_debug_phase_ticks) as {phase: ticks},
-    and the clock rate in Hz."""
-    npz = len(GATHER_PHASES)
-    buf = (ctypes.c_uint64 * (2 * npz + 2))()
+    and the clock rate in Hz.  by_kind: instead a pair of dicts (tiles with
+    the probe side in the LDS table, tiles probing through the row
+    directory), each holding the phase ticks and the work counts."""
+    npz, nct = len(GATHER_PHASES), len(GATHER_COUNTS)
+    slots = npz + nct
+    buf = (ctypes.c_uint64 * (2 * slots))()
     rate = ctypes.c_double()
-    _check(_lib.mhr_debug_phase_ticks(buf, 2 * npz + 2, ctypes.byref(rate), 1 if reset else 0),
+    _check(_lib.mhr_debug_phase_ticks(buf, 2 * slots, ctypes.byref(rate), 1 if reset else 0),
            "mhr_debug_phase_ticks")
-    return {p: int(buf[i]) for i, p in enumerate(GATHER_PHASES)}, float(rate.value)
-
-
-def phase_ticks_directory():
-    """Of the phase ticks since the last reset, those of tiles probing
-    through the row directory ({phase: ticks}), and the tile counts
-    (table kind, directory kind).  Does not reset."""
-    npz = len(GATHER_PHASES)
-    buf = (ctypes.c_uint64 * (2 * npz + 2))()
-    rate = ctypes.c_double()
-    _check(_lib.mhr_debug_phase_ticks(buf, 2 * npz + 2, ctypes.byref(rate), 0), "mhr_debug_phase_ticks")
-    return {p: int(buf[npz + i]) for i, p in enumerate(GATHER_PHASES)}, (int(buf[2 * npz]), int(buf[2 * npz + 1]))
+    kinds = []
+    for k in range(2):
+        b = k * slots
+        d = {p: int(buf[b + i]) for i, p in enumerate(GATHER_PHASES)}
+        d.update({c: int(buf[b + npz + i]) for i, c in enumerate(GATHER_COUNTS)})
+        kinds.append(d)
+    if by_kind:
+        return tuple(kinds), float(rate.value)
+    return {p: kinds[0][p] + kinds[1][p] for p in GATHER_PHASES}, float(rate.value)
 
 
 def _table(t, dtype):

@@ -63,15 +63,19 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 // A matrix operand: up to four column segments, each a table whose rows may
 // be gathered through an index array.  Element (row, col) lies in segment
 // g = col / seg at table row idx[g][row] (or row), column col - g * seg.
+// lim[g] (when nonzero) bounds the gathered row ids of segment g: a row id
+// at or above it reads as zeros.
 struct Mat {
     const void *p[4];
     const uint32_t *idx[4];
+    uint32_t lim[4];
     uint32_t seg, ld, nseg, f32, vec;   // vec: 8-column chunks may load as one 16-byte vector
 };
 
 __device__ __forceinline__ uint16_t mat_elem(const Mat &M, uint32_t row, uint32_t col) {
     const uint32_t g = col / M.seg, c = col - g * M.seg;
     const uint32_t r = M.idx[g] ? M.idx[g][row] : row;
+    if (M.lim[g] && r >= M.lim[g]) return 0;
     const size_t o = static_cast<size_t>(r) * M.ld + c;
     return M.f32 ? to_bf16(static_cast<const float *>(M.p[g])[o]) : static_cast<const uint16_t *>(M.p[g])[o];
 }
@@ -88,6 +92,11 @@ __device__ __forceinline__ void mat_row8(const Mat &M, uint32_t row, uint32_t co
     if (M.vec && col + 8 <= cend) {
         const uint32_t g = col / M.seg, c = col - g * M.seg;
         const uint32_t r = M.idx[g] ? M.idx[g][row] : row;
+        if (M.lim[g] && r >= M.lim[g]) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[e] = 0;
+            return;
+        }
         const size_t o = static_cast<size_t>(r) * M.ld + c;
         if (M.f32) {
             const float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(M.p[g]) + o);
@@ -179,6 +188,166 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Mat A, Mat B, float 
                     else C[static_cast<size_t>(m) * ldc + n] = acc[i][j][e];
                 }
             }
+}
+
+// ---- forward products: C[m][n] = sum_k A(m, k) B(n, k) -----------------------
+//
+// Both operands are rows contiguous along k (A: gathered feature or
+// activation rows; B: a weight matrix [N][K] read as stored).  Block tile
+// 128 x 128, four waves of 64 x 64 (4 x 4 MFMA tiles of 16 x 16), 32 k per
+// step.  The next step's tiles are loaded into registers while the current
+// one is multiplied out of LDS, and written to the other of two LDS buffers,
+// so one barrier separates the steps.  The epilogue is fused:
+//   kEpiF32        C[m][n] = acc                      (FP32 out, ldc)
+//   kEpiBiasRelu   h[m][n] = bf16(relu(((acc + T1[i1(m)][n]) + T2[i2(m)][n]) + bias[n]))
+//                  (the T terms only when given; the hoisted first layer)
+//   kEpiBiasReluDot as kEpiBiasRelu, h optional, and zpart[blockIdx.x][m] =
+//                  the tile's sum over n of h[m][n] w3[n] (the output layer)
+constexpr int kNtM = 128, kNtN = 128, kNtK = 32, kNtKP = kNtK + 8, kNtThreads = 256;
+enum NtEpi { kEpiF32 = 0, kEpiBiasRelu = 1, kEpiBiasReluDot = 2 };
+
+struct NtEpilogue {
+    float *C;                 // kEpiF32
+    uint32_t ldc;
+    uint16_t *h;              // bf16 activations [M][N] (may be null for kEpiBiasReluDot)
+    const float *bias;        // [N]
+    const float *T1;          // [*][N] rows added before the bias (or null), row T1i(m)
+    const uint32_t *q1;       // per row m: query word (query index | hop flag); T1 row = 2 query + hop
+    uint32_t t1_queries;      // queries of T1 (a query index at or above it reads row 0)
+    const float *T2;          // [*][N] (or null), row r2[m]
+    const uint32_t *r2;
+    uint32_t t2_rows;         // rows of T2 (an id at or above it reads row 0)
+    const uint16_t *w3;       // bf16 [N] (kEpiBiasReluDot)
+    float *zpart;             // [gridDim.x][M]
+};
+
+constexpr uint32_t kHopFlag = 0x80000000u;   // second-hop flag of a sample's query word
+
+template <int EPI>
+__global__ __launch_bounds__(kNtThreads) void gemm_nt_kernel(Mat A, Mat B, uint32_t M, uint32_t N, uint32_t K,
+                                                             NtEpilogue E) {
+    __shared__ __align__(16) uint16_t As[2][kNtM][kNtKP];
+    __shared__ __align__(16) uint16_t Bs[2][kNtN][kNtKP];
+    __shared__ float zred[2][kNtM];
+    const uint32_t m0 = blockIdx.y * kNtM, n0 = blockIdx.x * kNtN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // loader: thread t fills rows t / 4 and t / 4 + 64, k columns 8 (t % 4) .. + 8
+    const int lr = tid >> 2, lc = (tid & 3) * 8;
+    uint4 ra[2], rb[2];
+    auto load = [&](uint32_t k0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            mat_row8(A, m0 + lr + 64 * h, k0 + lc, M, K, reinterpret_cast<uint16_t *>(&ra[h]));
+            mat_row8(B, n0 + lr + 64 * h, k0 + lc, N, K, reinterpret_cast<uint16_t *>(&rb[h]));
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<uint4 *>(&As[buf][lr + 64 * h][lc]) = ra[h];
+            *reinterpret_cast<uint4 *>(&Bs[buf][lr + 64 * h][lc]) = rb[h];
+        }
+    };
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    store(0);
+    __syncthreads();
+    const int row = lane & 15, g = lane >> 4;
+    int buf = 0;
+    for (uint32_t k0 = 0; k0 < K; k0 += kNtK) {
+        const bool more = k0 + kNtK < K;
+        if (more) load(k0 + kNtK);
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 16 * i + row][8 * g]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 16 * j + row][8 * g]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // D[row][col] of a 16 x 16 tile sits in lane col + 16 * (row / 4), element row % 4
+    float zp[4][4];   // kEpiBiasReluDot: per (i, e) this lane's share of the tile's output dot
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) zp[i][e] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t m = m0 + wm + 16 * i + 4 * g + e;
+            if (m >= M) continue;
+            const float *t1 = nullptr, *t2 = nullptr;
+            if (EPI != kEpiF32) {
+                // out-of-range ids read row 0 (the logit is then replaced by
+                // NaN: zpart_reduce_kernel)
+                if (E.T1) {
+                    const uint32_t w = E.q1[m], qq = w & ~kHopFlag;
+                    t1 = E.T1 + (2 * static_cast<size_t>(qq >= E.t1_queries ? 0 : qq) + ((w & kHopFlag) ? 1 : 0)) * N;
+                }
+                if (E.T2) {
+                    const uint32_t rr = E.r2[m];
+                    t2 = E.T2 + static_cast<size_t>(rr >= E.t2_rows ? 0 : rr) * N;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t n = n0 + wn + 16 * j + row;
+                if (n >= N) continue;
+                const float x = acc[i][j][e];
+                if (EPI == kEpiF32) {
+                    E.C[static_cast<size_t>(m) * E.ldc + n] = x;
+                } else {
+                    float zv = x;
+                    if (t1) zv += t1[n];
+                    if (t2) zv += t2[n];
+                    const uint16_t hb = to_bf16(fmaxf(zv + E.bias[n], 0.0f));
+                    if (E.h) E.h[static_cast<size_t>(m) * N + n] = hb;
+                    if (EPI == kEpiBiasReluDot) zp[i][e] += from_bf16(hb) * from_bf16(E.w3[n]);
+                }
+            }
+        }
+    if (EPI == kEpiBiasReluDot) {
+        // sum over the 16 lanes holding one row's columns, then over the two
+        // waves of the row (fixed order)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = zp[i][e];
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+                if (row == 0) zred[wave & 1][wm + 16 * i + 4 * g + e] = v;
+            }
+        __syncthreads();
+        for (int r = tid; r < kNtM; r += kNtThreads) {
+            const uint32_t m = m0 + r;
+            if (m < M) E.zpart[static_cast<size_t>(blockIdx.x) * M + m] = zred[0][r] + zred[1][r];
+        }
+    }
+}
+
+// z[m] = (sum over the column blocks b = 0, 1, ... of zpart[b][m]) + b3;
+// NaN for a sample whose query index (q, when given) is not below nq or
+// whose relation (r, when given) is not below R.
+__global__ void zpart_reduce_kernel(const float *zpart, uint32_t nb, uint32_t M, const float *b3, float *z,
+                                    const uint32_t *q, uint32_t nq, const uint32_t *r, uint32_t R) {
+    for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < M; m += gridDim.x * blockDim.x) {
+        float acc = 0.0f;
+        for (uint32_t b = 0; b < nb; ++b) acc += zpart[static_cast<size_t>(b) * M + m];
+        const bool bad = (q && (q[m] & ~kHopFlag) >= nq) || (r && r[m] >= R);
+        z[m] = bad ? __builtin_nanf("") : acc + b3[0];
+    }
 }
 
 // ---- elementwise and reduction kernels -------------------------------------
@@ -357,6 +526,8 @@ Mat features(const mhr_graph *g, const uint32_t *s, const uint32_t *t, const uin
     F.p[1] = g->X; F.idx[1] = t;
     F.p[2] = g->X; F.idx[2] = v;
     F.p[3] = g->Y; F.idx[3] = r;
+    F.lim[0] = F.lim[1] = F.lim[2] = g->n;
+    F.lim[3] = g->R;
     F.seg = g->dim;
     F.ld = g->dim;
     F.nseg = 4;
@@ -393,6 +564,16 @@ hipError_t gemm(const Mat &A, const Mat &B, float *C, uint32_t ldc, uint32_t M, 
     return hipGetLastError();
 }
 
+template <int EPI>
+hipError_t gemm_nt(const Mat &A, const Mat &B, uint32_t M, uint32_t N, uint32_t K, const NtEpilogue &E,
+                   hipStream_t st) {
+    if (M == 0 || N == 0) return hipSuccess;
+    if ((M + kNtM - 1) / kNtM > 65535u) return hipErrorInvalidValue;
+    dim3 grid((N + kNtN - 1) / kNtN, (M + kNtM - 1) / kNtM);
+    hipLaunchKernelGGL((gemm_nt_kernel<EPI>), grid, dim3(kNtThreads), 0, st, A, B, M, N, K, E);
+    return hipGetLastError();
+}
+
 // split count for a reduction over K samples into an M x N output
 uint32_t splits_for(uint32_t M, uint32_t N, uint32_t K) {
     const uint32_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
@@ -411,7 +592,7 @@ size_t split_floats(uint32_t M, uint32_t N, uint32_t K) {
 constexpr uint32_t kColRows = 256;   // rows per column-sum chunk
 
 struct PWs {
-    size_t Z, h1, h2, z, dz, s, t, part, cpart, lpart, total;
+    size_t Z, h1, h2, z, dz, s, t, part, cpart, lpart, zpart, total;
 };
 PWs pws_layout(uint32_t n, uint32_t d, uint32_t H) {
     PWs L{};
@@ -427,6 +608,7 @@ PWs pws_layout(uint32_t n, uint32_t d, uint32_t H) {
     L.part = take(std::max(split_floats(H, H, n), split_floats(H, 4 * d, n)) * 4);
     L.cpart = take(size_t((n + kColRows - 1) / kColRows) * H * 4);
     L.lpart = take(size_t(grid_for(n, kBlock)) * 4);
+    L.zpart = take(size_t((H + kNtN - 1) / kNtN) * n * 4);
     L.total = o;
     return L;
 }
@@ -450,16 +632,22 @@ mhr_status forward_impl(mhr_pruner *p, const mhr_graph *g, uint32_t n, const uin
     float *Z = reinterpret_cast<float *>(ws + W.Z);
     uint16_t *h1 = reinterpret_cast<uint16_t *>(ws + W.h1), *h2 = reinterpret_cast<uint16_t *>(ws + W.h2);
     uint32_t *s = reinterpret_cast<uint32_t *>(ws + W.s), *t = reinterpret_cast<uint32_t *>(ws + W.t);
+    (void)Z;
     hipLaunchKernelGGL(expand_query_kernel, dim3(grid_for(n)), dim3(256), 0, st, q, src, dst, s, t, n);
     const Mat F = features(g, s, t, v, r);
-    MHR_HIP_TRY((gemm<false, true>(F, plain(p->W1b, 4 * d), Z, H, n, H, 4 * d, 1, nullptr, st)));
-    hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b1, h1,
-                       size_t(n) * H, H);
-    MHR_HIP_TRY((gemm<false, true>(plain(h1, H), plain(p->W2b, H), Z, H, n, H, H, 1, nullptr, st)));
-    hipLaunchKernelGGL(bias_relu_kernel, dim3(grid_for(size_t(n) * H)), dim3(256), 0, st, Z, p->theta + L.b2, h2,
-                       size_t(n) * H, H);
-    hipLaunchKernelGGL(output_kernel, dim3((n + 3) / 4), dim3(256), 0, st, h2, p->w3b, p->theta + L.b3,
-                       reinterpret_cast<float *>(ws + W.z), n, H);
+    NtEpilogue E1{};
+    E1.h = h1;
+    E1.bias = p->theta + L.b1;
+    MHR_HIP_TRY(gemm_nt<kEpiBiasRelu>(F, plain(p->W1b, 4 * d), n, H, 4 * d, E1, st));
+    NtEpilogue E2{};
+    E2.h = h2;
+    E2.bias = p->theta + L.b2;
+    E2.w3 = p->w3b;
+    E2.zpart = reinterpret_cast<float *>(ws + W.zpart);
+    MHR_HIP_TRY(gemm_nt<kEpiBiasReluDot>(plain(h1, H), plain(p->W2b, H), n, H, H, E2, st));
+    hipLaunchKernelGGL(zpart_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, E2.zpart, (H + kNtN - 1) / kNtN, n,
+                       p->theta + L.b3, reinterpret_cast<float *>(ws + W.z), static_cast<const uint32_t *>(nullptr),
+                       0u, static_cast<const uint32_t *>(nullptr), 0u);
     MHR_HIP_TRY(hipGetLastError());
     return MHR_OK;
 }
@@ -1026,6 +1214,125 @@ extern "C" mhr_status mhr_pruner_forward(mhr_pruner *p, const mhr_graph *g, uint
     rc = forward_impl(p, g, n, q, src, dst, v, r, w, st);
     if (rc != MHR_OK) return rc;
     MHR_HIP_TRY(hipMemcpyAsync(logits, w + pws_layout(n, p->d, p->H).z, size_t(n) * 4, hipMemcpyDeviceToDevice, st));
+    return MHR_OK;
+}
+
+namespace mhr {
+namespace {
+
+// Per (query, hop) row j = 2 q + hop: the endpoint the candidate edge
+// touches and the other one (hop 2 swaps them, as expand_query_kernel does).
+__global__ void query_rows_kernel(const uint32_t *src, const uint32_t *dst, uint32_t nq, uint32_t *qs, uint32_t *qt) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < 2 * nq; j += gridDim.x * blockDim.x) {
+        const uint32_t q = j >> 1;
+        const bool hop2 = j & 1u;
+        qs[j] = hop2 ? dst[q] : src[q];
+        qt[j] = hop2 ? src[q] : dst[q];
+    }
+}
+
+struct ScoreWs {
+    size_t Zq, Zr, qs, qt, h1, zpart, total;
+};
+
+ScoreWs score_layout(uint32_t nq, uint32_t R, uint32_t H, uint32_t chunk) {
+    ScoreWs L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = (o + std::max<size_t>(bytes, 1) + 255) & ~size_t(255); return r; };
+    L.Zq = take(size_t(2) * nq * H * 4);
+    L.Zr = take(size_t(R) * H * 4);
+    L.qs = take(size_t(2) * nq * 4);
+    L.qt = take(size_t(2) * nq * 4);
+    L.h1 = take(size_t(chunk) * H * 2);
+    L.zpart = take(size_t((H + kNtN - 1) / kNtN) * chunk * 4);
+    L.total = o;
+    return L;
+}
+
+// Column block [c0, c0 + K) of W1 (bf16 [H][4d]) as a B operand.
+Mat w1_block(const mhr_pruner *p, uint32_t c0, uint32_t K) {
+    Mat B{};
+    B.p[0] = p->W1b + c0;
+    B.seg = K;
+    B.ld = 4 * p->d;
+    B.nseg = 1;
+    B.vec = 1;
+    return B;
+}
+
+}  // namespace
+}  // namespace mhr
+
+extern "C" mhr_status mhr_pruner_score_workspace_size(const mhr_pruner *p, const mhr_graph *g, uint32_t nq,
+                                                      uint32_t chunk, size_t *bytes) {
+    MHR_ARG_CHECK(p && g && bytes, "mhr_pruner_score_workspace_size: null argument");
+    MHR_ARG_CHECK(chunk >= 1 && (chunk + kNtM - 1) / kNtM <= 65535u, "mhr_pruner_score_workspace_size: bad chunk");
+    *bytes = score_layout(nq, g->R, p->H, chunk).total;
+    return MHR_OK;
+}
+
+extern "C" mhr_status mhr_pruner_score(mhr_pruner *p, const mhr_graph *g, uint32_t nq, const uint32_t *src,
+                                       const uint32_t *dst, uint64_t ncand, const uint32_t *q, const uint32_t *v,
+                                       const uint32_t *r, float *logits, uint32_t chunk, void *ws, size_t ws_bytes,
+                                       void *stream) {
+    MHR_ARG_CHECK(p && g, "mhr_pruner_score: null handle");
+    MHR_ARG_CHECK(g->X && g->Y && g->dim == p->d, "mhr_pruner_score: graph embeddings missing or of another dimension");
+    MHR_ARG_CHECK(chunk >= 1 && (chunk + kNtM - 1) / kNtM <= 65535u, "mhr_pruner_score: bad chunk");
+    if (ncand == 0) return MHR_OK;
+    MHR_ARG_CHECK(nq >= 1 && src && dst && q && v && r && logits && ws, "mhr_pruner_score: null pointer");
+    const ScoreWs W = score_layout(nq, g->R, p->H, chunk);
+    if (ws_bytes < W.total) {
+        set_error("mhr_pruner_score: workspace of " + std::to_string(ws_bytes) + " bytes, " +
+                  std::to_string(W.total) + " needed");
+        return MHR_ERR_WORKSPACE_TOO_SMALL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const uint32_t d = p->d, H = p->H;
+    const PLayout L = play(d, H);
+    float *Zq = reinterpret_cast<float *>(w + W.Zq), *Zr = reinterpret_cast<float *>(w + W.Zr);
+    uint32_t *qs = reinterpret_cast<uint32_t *>(w + W.qs), *qt = reinterpret_cast<uint32_t *>(w + W.qt);
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(w + W.h1);
+    float *zpart = reinterpret_cast<float *>(w + W.zpart);
+    const uint32_t f32 = g->dtype == MHR_DTYPE_F32 ? 1u : 0u;
+    // the query endpoints' share of the first layer, once per (query, hop)
+    hipLaunchKernelGGL(query_rows_kernel, dim3(grid_for(size_t(2) * nq)), dim3(256), 0, st, src, dst, nq, qs, qt);
+    Mat Aq{};
+    Aq.p[0] = g->X; Aq.idx[0] = qs; Aq.lim[0] = g->n;
+    Aq.p[1] = g->X; Aq.idx[1] = qt; Aq.lim[1] = g->n;
+    Aq.seg = d; Aq.ld = d; Aq.nseg = 2; Aq.f32 = f32; Aq.vec = 1;
+    NtEpilogue Eq{};
+    Eq.C = Zq;
+    Eq.ldc = H;
+    MHR_HIP_TRY(gemm_nt<kEpiF32>(Aq, w1_block(p, 0, 2 * d), 2 * nq, H, 2 * d, Eq, st));
+    // the relations' share, once per relation
+    Mat Ar = plain(g->Y, d, f32 != 0);
+    NtEpilogue Er{};
+    Er.C = Zr;
+    Er.ldc = H;
+    MHR_HIP_TRY(gemm_nt<kEpiF32>(Ar, w1_block(p, 3 * d, d), g->R, H, d, Er, st));
+    // per candidate: its own share, then the second layer and the output
+    const uint32_t nb = (H + kNtN - 1) / kNtN;
+    for (uint64_t c0 = 0; c0 < ncand; c0 += chunk) {
+        const uint32_t m = static_cast<uint32_t>(std::min<uint64_t>(chunk, ncand - c0));
+        Mat Ac{};
+        Ac.p[0] = g->X; Ac.idx[0] = v + c0; Ac.lim[0] = g->n;
+        Ac.seg = d; Ac.ld = d; Ac.nseg = 1; Ac.f32 = f32; Ac.vec = 1;
+        NtEpilogue E1{};
+        E1.h = h1;
+        E1.bias = p->theta + L.b1;
+        E1.T1 = Zq; E1.q1 = q + c0; E1.t1_queries = nq;
+        E1.T2 = Zr; E1.r2 = r + c0; E1.t2_rows = g->R;
+        MHR_HIP_TRY(gemm_nt<kEpiBiasRelu>(Ac, w1_block(p, 2 * d, d), m, H, d, E1, st));
+        NtEpilogue E2{};
+        E2.bias = p->theta + L.b2;
+        E2.w3 = p->w3b;
+        E2.zpart = zpart;
+        MHR_HIP_TRY(gemm_nt<kEpiBiasReluDot>(plain(h1, H), plain(p->W2b, H), m, H, H, E2, st));
+        hipLaunchKernelGGL(zpart_reduce_kernel, dim3(grid_for(m)), dim3(256), 0, st, zpart, nb, m, p->theta + L.b3,
+                           logits + c0, q + c0, nq, r + c0, g->R);
+    }
+    MHR_HIP_TRY(hipGetLastError());
     return MHR_OK;
 }
 

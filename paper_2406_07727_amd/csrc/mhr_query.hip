@@ -1069,22 +1069,43 @@ enum GatherPhase {
     kPhEnd,          // final merge, tile list and header out
     kNumPhases
 };
+// Work counts of the phase-clock build, per tile kind (see g_phase_ticks).
+enum GatherCount {
+    kCtTiles = 0,     // tiles taken
+    kCtRowBatches,    // list-row batches
+    kCtChunks,        // chunks of scanned entries
+    kCtScanned,       // scanned entries
+    kCtSubBatches,    // scoring sub-batches
+    kCtMatches,       // matched middle edges scored
+    kCtValues,        // edge values scored (probe and middle edges, per relation)
+    kCtItems,         // enumeration items (match, probe value, middle value)
+    kCtStaged,        // candidates staged
+    kCtMerges,        // stage merges
+    kNumCounts
+};
+constexpr int kPhSlots = kNumPhases + kNumCounts;
 #ifdef MHR_PHASE_CLOCKS
-// [0, kNumPhases): tiles whose probe side is in the LDS table;
-// [kNumPhases, 2 kNumPhases): tiles probing through the row directory;
-// then the number of tiles of each kind.
-__device__ unsigned long long g_phase_ticks[2 * kNumPhases + 2];
+// Per tile kind (0: probe side in the LDS table, 1: probing through the row
+// directory): the phases' summed ticks, then the work counts.
+__device__ unsigned long long g_phase_ticks[2 * kPhSlots];
 #define MHR_PHASE(p)                                                      \
     do {                                                                  \
         if (tid == 0) {                                                   \
             const unsigned long long now_ = wall_clock64();               \
-            ph_acc[(p) + (ph_heavy ? kNumPhases : 0)] += now_ - ph_t;     \
+            ph_acc[(p) + (ph_heavy ? kPhSlots : 0)] += now_ - ph_t;       \
             ph_t = now_;                                                  \
         }                                                                 \
+    } while (0)
+#define MHR_COUNT(c, v)                                                                   \
+    do {                                                                                  \
+        if (tid == 0) ph_acc[kNumPhases + (c) + (ph_heavy ? kPhSlots : 0)] += (v);       \
     } while (0)
 #else
 #define MHR_PHASE(p) \
     do {             \
+    } while (0)
+#define MHR_COUNT(c, v) \
+    do {                \
     } while (0)
 #endif
 
@@ -1092,10 +1113,10 @@ __device__ unsigned long long g_phase_ticks[2 * kNumPhases + 2];
 template <bool BF16, bool EXACT, int KC, bool TE>
 __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
 #ifdef MHR_PHASE_CLOCKS
-    __shared__ unsigned long long ph_acc[2 * kNumPhases + 2];
+    __shared__ unsigned long long ph_acc[2 * kPhSlots];
     __shared__ unsigned long long ph_t;
-    bool ph_heavy = false;   // the current tile probes through the directory (thread 0's copy)
-    if (threadIdx.x < 2 * kNumPhases + 2) ph_acc[threadIdx.x] = 0;
+    bool ph_heavy = false;   // the current tile probes through the directory
+    if (threadIdx.x < 2 * kPhSlots) ph_acc[threadIdx.x] = 0;
     if (threadIdx.x == 0) ph_t = wall_clock64();
 #endif
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1198,8 +1219,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         const float thr_exact = P.thr;
 #ifdef MHR_PHASE_CLOCKS
         ph_heavy = heavy;
-        if (tid == 0) ph_acc[2 * kNumPhases + (heavy ? 1 : 0)] += 1;
 #endif
+        MHR_COUNT(kCtTiles, 1);
 
         // ---- tile setup
         for (uint32_t i = tid; i < d; i += kBlock) {
@@ -1321,6 +1342,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
             __syncthreads();
             const uint32_t E = sh->E;
             MHR_PHASE(kPhRows);
+            MHR_COUNT(kCtRowBatches, 1);
+            MHR_COUNT(kCtScanned, E);
 
             // ---- chunks of scanned entries.  Matches queue up across chunks
             // until a full sub-batch is ready (all of them after the last
@@ -1458,6 +1481,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 }
                 __syncthreads();
                 MHR_PHASE(kPhProbe);
+                MHR_COUNT(kCtChunks, 1);
                 const uint32_t nmatch = sh->qcount;
 
                 // ---- sub-batches of at most kBlock matches (value slab permitting)
@@ -1495,6 +1519,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     }
                     __syncthreads();
                     MHR_PHASE(kPhForm);
+                    MHR_COUNT(kCtSubBatches, 1);
+                    MHR_COUNT(kCtMatches, ncnt);
+                    MHR_COUNT(kCtValues, sh->vn);
                     // scoring on the matrix cores: a wave takes 16 matches at a time.
                     // Lane (row m = lane & 15, k-quarter kq = lane >> 4) holds the
                     // d/4 elements [kq*d/4, (kq+1)*d/4) of match m's vectors
@@ -1785,6 +1812,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         sub_item[tid] = iincl - nitems;
                         __syncthreads();
                         MHR_PHASE(kPhBounds);
+                        MHR_COUNT(kCtItems, ntot);
                         // Each thread walks the items tid, tid + kBlock, ...; its cursor
                         // (item, list position) survives the rounds, so a round ends
                         // only when the stage quota is used up or the items run out.
@@ -1800,6 +1828,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                             // walking (at least one each)
                             if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) {
                                 MHR_PHASE(kPhEnum);
+                                MHR_COUNT(kCtStaged, sh->stage_n);
+                                MHR_COUNT(kCtMerges, 1);
                                 merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
                                 MHR_PHASE(kPhMerge);
                             }
@@ -1917,6 +1947,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
         }
         // ---- tile end: final merge and output
         __syncthreads();
+        MHR_COUNT(kCtStaged, sh->stage_n);
+        MHR_COUNT(kCtMerges, sh->stage_n > 0 ? 1 : 0);
         if (sh->stage_n > 0) merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
         float em = block_max<>(eps_local, sh->redf);
         uint64_t npt = block_sum<uint64_t>(npaths, sh->red64);
@@ -1935,7 +1967,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
     }
 #ifdef MHR_PHASE_CLOCKS
     __syncthreads();
-    if (threadIdx.x < 2 * kNumPhases + 2) atomicAdd(&g_phase_ticks[threadIdx.x], ph_acc[threadIdx.x]);
+    if (threadIdx.x < 2 * kPhSlots) atomicAdd(&g_phase_ticks[threadIdx.x], ph_acc[threadIdx.x]);
 #endif
 }
 // ---------------------------------------------------------------------------
@@ -2664,23 +2696,20 @@ extern "C" mhr_status mhr_topk_paths_noalloc(const mhr_graph *g, const mhr_query
                      MHR_NOALLOC_SCRATCH_BYTES, stream, nullptr, nullptr, nullptr);
 }
 
-// Phase clocks of the gather kernel (see GatherPhase): copies the summed
-// per-workgroup wall-clock ticks of every phase since the last reset to out
-// (host, n entries: out[i] for phase i over all tiles; when n >= 2 *
-// kNumPhases + 2 also out[kNumPhases + i] for the tiles that probe through
-// the row directory alone, then the tile counts of the table and directory
-// kinds), the clock's rate in Hz to *rate_hz, and resets them if reset !=
-// 0.  Synchronises the device.  Only a build with MHR_PHASE_CLOCKS records
-// them; other builds return MHR_ERR_UNSUPPORTED.
+// Phase clocks of the gather kernel (see GatherPhase, GatherCount): copies,
+// per tile kind (0: probe side in the LDS table, 1: probing through the row
+// directory), the summed per-workgroup wall-clock ticks of every phase since
+// the last reset and then the work counts, to out (host, n >= 2 (kNumPhases
+// + kNumCounts) entries), the clock's rate in Hz to *rate_hz, and resets
+// them if reset != 0.  Synchronises the device.  Only a build with
+// MHR_PHASE_CLOCKS records them; other builds return MHR_ERR_UNSUPPORTED.
 extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *rate_hz, int reset) {
 #ifdef MHR_PHASE_CLOCKS
-    MHR_ARG_CHECK(out != nullptr && n >= static_cast<uint32_t>(kNumPhases), "mhr_debug_phase_ticks: bad output");
+    MHR_ARG_CHECK(out != nullptr && n >= static_cast<uint32_t>(2 * kPhSlots), "mhr_debug_phase_ticks: bad output");
     MHR_HIP_TRY(hipDeviceSynchronize());
-    unsigned long long h[2 * kNumPhases + 2];
+    unsigned long long h[2 * kPhSlots];
     MHR_HIP_TRY(hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase_ticks), sizeof(h)));
-    for (int i = 0; i < kNumPhases; ++i) out[i] = h[i] + h[kNumPhases + i];
-    if (n >= static_cast<uint32_t>(2 * kNumPhases + 2))
-        for (int i = kNumPhases; i < 2 * kNumPhases + 2; ++i) out[i] = h[i];
+    for (int i = 0; i < 2 * kPhSlots; ++i) out[i] = h[i];
     if (rate_hz) {
         int dev = 0, khz = 0;
         MHR_HIP_TRY(hipGetDevice(&dev));
@@ -2688,7 +2717,7 @@ extern "C" mhr_status mhr_debug_phase_ticks(uint64_t *out, uint32_t n, double *r
         *rate_hz = 1e3 * static_cast<double>(khz);
     }
     if (reset) {
-        const unsigned long long z[2 * kNumPhases + 2] = {};
+        const unsigned long long z[2 * kPhSlots] = {};
         MHR_HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), z, sizeof(z)));
         MHR_HIP_TRY(hipDeviceSynchronize());
     }

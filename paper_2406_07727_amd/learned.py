@@ -91,13 +91,9 @@ class LearnedPruner:
         return losses
 
     # ---- inference ----------------------------------------------------------
-    def logits(self, c, chunk: int = 1 << 20):
-        torch = _torch()
-        out = torch.empty(max(c.n, 1), dtype=torch.float32, device="cuda")
-        for i in range(0, c.n, chunk):
-            j = min(c.n, i + chunk)
-            out[i:j] = self.net.forward(self.graph, c.q[i:j], c.src, c.dst, c.v[i:j], c.r[i:j])
-        return out[:c.n]
+    def logits(self, c, chunk: int = 1 << 18):
+        """The network's logits of every candidate of c (mhr_pruner_score)."""
+        return self.net.score(self.graph, c.src, c.dst, c.q[:c.n], c.v[:c.n], c.r[:c.n], chunk=chunk)
 
     def search(self, src, dst, K: int, keep_permille: int = 100, tau: float = 0.5, scores=None,
                fallback: bool = True):

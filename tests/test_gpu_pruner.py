@@ -66,6 +66,35 @@ def test_forward_matches_oracle(name, H):
     assert np.std(z64) > 0.05
 
 
+@pytest.mark.parametrize("name,H,chunk", [("hub_tiny", 32, 700), ("hub_r32_bf16", 160, 256),
+                                          ("hub_tiny_bf16", 48, 97)])
+def test_candidate_scoring_matches_oracle(name, H, chunk):
+    """mhr_pruner_score (first layer split into the endpoints' part per
+    query and hop, the relation's part per relation and the candidate's
+    part; second layer and output fused) keeps every logit within the
+    oracle's bound for FP32 accumulation in any order, over several chunks
+    and a hidden width that is not a multiple of the 128-wide tile."""
+    import paper_2406_07727_amd as mhr
+    cfg, g, dim, theta, (s, d), (q, v, rr, y), F = _setup(name, H, 6)
+    say(f"case pruner scoring {name} H={H} chunk={chunk}")
+    pr = mhr.Pruner(dim, H)
+    pr.set_params(theta)
+    z = pr.score(g, s, d, q, v, rr, chunk=chunk).cpu().numpy().astype(np.float64)
+    z64, e_z, _ = OP.forward_bounds(theta, F, dim, H)
+    assert np.all(np.abs(z - z64) <= e_z), np.max(np.abs(z - z64) - e_z)
+    zf = pr.forward(g, q, s, d, v, rr).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(z - zf) <= 2 * e_z)
+    # a query word or relation id out of range gives a NaN logit (nothing is read out of range)
+    q_bad, r_bad = q.copy(), rr.copy()
+    q_bad[3] = np.uint32(len(s) + 5)
+    r_bad[7] = np.uint32(cfg.graph.R)
+    zb = pr.score(g, s, d, q_bad, v, r_bad, chunk=chunk).cpu().numpy()
+    assert np.isnan(zb[3]) and np.isnan(zb[7])
+    keep = np.ones(len(zb), bool)
+    keep[[3, 7]] = False
+    assert np.array_equal(zb[keep], z[keep].astype(np.float32))
+
+
 @pytest.mark.parametrize("name,H", [("hub_tiny", 32), ("hub_r32_bf16", 64)])
 def test_gradient_and_loss_match_oracle(name, H):
     """Every gradient element within its own bound (oracle/pruner.py
