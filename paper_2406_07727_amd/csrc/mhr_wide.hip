@@ -53,6 +53,12 @@ struct mhr_wide_graph {
         uint32_t *row_ptr = nullptr;
         uint32_t *col = nullptr;
         uint16_t *rel = nullptr;
+        // per vertex v: the scan cost of v's row as a frontier (the summed
+        // row lengths, in this CSR, of the distinct neighbours of v) and the
+        // number of those neighbours whose row is nonempty; both < 2^32
+        // since each is at most the entry count
+        uint32_t *cost = nullptr;
+        uint32_t *ndist = nullptr;
         uint32_t max_degree = 0;
     } out, in;
     const void *X = nullptr;
@@ -227,6 +233,9 @@ __global__ void wide_maxdeg_kernel(const uint32_t *row_ptr, uint32_t n, uint32_t
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, mx);
 }
 
+__global__ void wide_cost_kernel(const uint32_t *row_ptr, const uint32_t *col, uint32_t n, uint32_t *cost,
+                                 uint32_t *ndist);
+
 mhr_status wide_build_direction(mhr_wide_graph *g, const mhr_graph_desc *d, int reverse, mhr_wide_graph::Dir &D,
                                 hipStream_t st) {
     const uint64_t m = d->num_edges;
@@ -292,6 +301,12 @@ mhr_status wide_build_direction(mhr_wide_graph *g, const mhr_graph_desc *d, int 
                        n, mx.as<uint32_t>());
     MHR_HIP_TRY(hipGetLastError());
     MHR_HIP_TRY(hipMemcpyAsync(&D.max_degree, mx.p, 4, hipMemcpyDeviceToHost, st));
+    MHR_HIP_TRY(hipMalloc(&D.cost, std::max<size_t>(n, 1) * 4));
+    MHR_HIP_TRY(hipMalloc(&D.ndist, std::max<size_t>(n, 1) * 4));
+    g->device_bytes += static_cast<uint64_t>(n) * 8;
+    hipLaunchKernelGGL(wide_cost_kernel, dim3(std::min<uint32_t>(wcdiv(n, 4), 65535)), dim3(256), 0, st, D.row_ptr,
+                       D.col, n, D.cost, D.ndist);
+    MHR_HIP_TRY(hipGetLastError());
     MHR_HIP_TRY(hipStreamSynchronize(st));
     return MHR_OK;
 }
@@ -300,6 +315,8 @@ void wide_free_dir(mhr_wide_graph::Dir &D) {
     if (D.row_ptr) (void)hipFree(D.row_ptr);
     if (D.col) (void)hipFree(D.col);
     if (D.rel) (void)hipFree(D.rel);
+    if (D.cost) (void)hipFree(D.cost);
+    if (D.ndist) (void)hipFree(D.ndist);
     D = mhr_wide_graph::Dir();
 }
 
@@ -406,10 +423,11 @@ struct WPlan {
     uint32_t ntiles, tile_base;
     uint64_t cost;                  // scan entries
     uint64_t tab_off;
+    uint32_t nchunks, chunk_base;   // kWChunk-entry chunks of the list row (table construction)
 };
 
 struct WTotals {
-    unsigned long long nd, tiles, ctr;
+    unsigned long long nd, tiles, ctr, chunks;
 };
 
 struct WRow {
@@ -419,6 +437,8 @@ struct WRow {
 
 struct WArgs {
     const uint32_t *out_rp, *out_col, *in_rp, *in_col;
+    const uint32_t *out_cost, *out_nd, *in_cost, *in_nd;   // per-vertex frontier scan costs (mhr_wide_graph::Dir)
+    ulonglong2 *cpart;  // per list chunk: (distinct vertices, scan entries), then their exclusive prefix in the query
     const uint16_t *out_rel, *in_rel;
     const void *X, *Y;
     uint32_t n, d, nq, k_max;
@@ -496,140 +516,236 @@ __device__ __forceinline__ void seg_cost(const uint32_t *col, const uint32_t *rp
     }
 }
 
+// One wave per row v: over the runs of equal neighbours x in v's row (16
+// entries per lane per step, as seg_cost reads them), the sum of
+// row_ptr[x + 1] - row_ptr[x] and the count of nonempty ones.
+__global__ void wide_cost_kernel(const uint32_t *row_ptr, const uint32_t *col, uint32_t n, uint32_t *cost,
+                                 uint32_t *ndist) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t v = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; v < n; v += waves) {
+        const uint32_t b = row_ptr[v], e = row_ptr[v + 1];
+        unsigned long long c = 0, nd = 0;
+        for (uint32_t i0 = b + lane * kWSeg; i0 < e; i0 += kWave * kWSeg) seg_cost(col, row_ptr, b, e, i0, c, nd);
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            c += static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(c), o, kWave));
+            nd += static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(nd), o, kWave));
+        }
+        if (lane == 0) {
+            cost[v] = static_cast<uint32_t>(c);
+            ndist[v] = static_cast<uint32_t>(nd);
+        }
+    }
+}
+
+// One thread per query: both rows, the scan cost of each direction from the
+// per-vertex costs computed at ingest, the cheaper direction (forward on a
+// tie) and its tile count.  A query with an empty endpoint row has no path.
 __global__ __launch_bounds__(kWBlock) void wide_plan_kernel(WArgs A, const uint32_t *src, const uint32_t *dst,
                                                             const uint32_t *kq) {
     __shared__ unsigned long long red[kWBlock / kWave];
-    const uint32_t q = blockIdx.x;
-    const uint32_t s = src[q], t = dst[q], k = kq ? kq[q] : A.k_max;
-    WPlan P{};
-    P.s = s;
-    P.t = t;
-    P.k = k;
-    if (s >= A.n || t >= A.n) P.status |= MHR_Q_BAD_ID;
-    if (k == 0 || k > A.k_max) P.status |= MHR_Q_BAD_K;
-    unsigned long long cf = 0, cb = 0, nf = 0, nb = 0;
-    uint32_t os0 = 0, os1 = 0, it0 = 0, it1 = 0;
-    if (P.status == 0) {
-        os0 = A.out_rp[s];
-        os1 = A.out_rp[s + 1];
-        it0 = A.in_rp[t];
-        it1 = A.in_rp[t + 1];
-    }
-    // Both rows are summed in lockstep chunks; once one side is complete and
-    // the other's partial sum has reached it, the other cannot be cheaper and
-    // is not read further (a hub row of millions of entries is then left
-    // after its first chunks).
-    bool fdone = true, bdone = true;
-    if (P.status == 0 && os1 > os0 && it1 > it0) {
-        fdone = bdone = false;
-        for (uint32_t c = 0;; c += kWChunk) {
-            unsigned long long pf = 0, pb = 0, qf = 0, qb = 0;
-            if (!fdone) seg_cost(A.out_col, A.out_rp, os0, os1, os0 + c + threadIdx.x * kWSeg, pf, qf);
-            if (!bdone) seg_cost(A.in_col, A.in_rp, it0, it1, it0 + c + threadIdx.x * kWSeg, pb, qb);
-            cf += wblock_sum(pf, red);
-            cb += wblock_sum(pb, red);
-            nf += wblock_sum(qf, red);
-            nb += wblock_sum(qb, red);
-            fdone = fdone || os0 + c + kWChunk >= os1;
-            bdone = bdone || it0 + c + kWChunk >= it1;
-            if ((fdone && bdone) || (fdone && cb >= cf) || (bdone && cf > cb)) break;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long add_nd = 0, add_tiles = 0;
+    if (q < A.nq) {
+        const uint32_t s = src[q], t = dst[q], k = kq ? kq[q] : A.k_max;
+        WPlan P{};
+        P.s = s;
+        P.t = t;
+        P.k = k;
+        if (s >= A.n || t >= A.n) P.status |= MHR_Q_BAD_ID;
+        if (k == 0 || k > A.k_max) P.status |= MHR_Q_BAD_K;
+        uint32_t os0 = 0, os1 = 0, it0 = 0, it1 = 0;
+        unsigned long long cf = 0, cb = 0, nf = 0, nb = 0;
+        if (P.status == 0) {
+            os0 = A.out_rp[s];
+            os1 = A.out_rp[s + 1];
+            it0 = A.in_rp[t];
+            it1 = A.in_rp[t + 1];
+            if (os1 > os0 && it1 > it0) {
+                cf = A.out_cost[s];
+                nf = A.out_nd[s];
+                cb = A.in_cost[t];
+                nb = A.in_nd[t];
+            }
         }
+        P.out_len = os1 - os0;
+        P.in_len = it1 - it0;
+        const bool fwd = cf <= cb;
+        P.dir = fwd ? 1u : 0u;
+        P.list_beg = fwd ? os0 : it0;
+        P.list_len = fwd ? P.out_len : P.in_len;
+        P.probe_beg = fwd ? it0 : os0;
+        P.probe_len = fwd ? P.in_len : P.out_len;
+        P.cost = fwd ? cf : cb;
+        P.nd = static_cast<uint32_t>(fwd ? nf : nb);
+        P.ntiles = P.cost ? wcdiv(P.cost, kWTile) : 0u;
+        P.nchunks = (P.status == 0 && P.cost) ? wcdiv(P.list_len, kWChunk) : 0u;
+        A.plans[q] = P;
+        A.gthr[q] = 0;
+        A.qtotal[q] = 0;
+        A.qmatch[q] = 0;
+        add_nd = P.nd;
+        add_tiles = P.ntiles;
     }
-    if (threadIdx.x != 0) return;
-    P.out_len = os1 - os0;
-    P.in_len = it1 - it0;
-    const bool fwd = fdone && (!bdone || cf <= cb);
-    P.dir = fwd ? 1u : 0u;
-    P.list_beg = fwd ? os0 : it0;
-    P.list_len = fwd ? P.out_len : P.in_len;
-    P.probe_beg = fwd ? it0 : os0;
-    P.probe_len = fwd ? P.in_len : P.out_len;
-    P.cost = fwd ? cf : cb;
-    P.nd = static_cast<uint32_t>(fwd ? nf : nb);
-    P.ntiles = P.cost ? wcdiv(P.cost, kWTile) : 0u;
-    A.plans[q] = P;
-    A.gthr[q] = 0;
-    A.qtotal[q] = 0;
-    A.qmatch[q] = 0;
-    atomicAdd(&A.tot->nd, static_cast<unsigned long long>(P.nd));
-    atomicAdd(&A.tot->tiles, static_cast<unsigned long long>(P.ntiles));
+    const unsigned long long bn = wblock_sum(add_nd, red);
+    const unsigned long long bt = wblock_sum(add_tiles, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&A.tot->nd, bn);
+        atomicAdd(&A.tot->tiles, bt);
+    }
 }
 
 // Offsets of each query's distinct table and tiles.
 __global__ __launch_bounds__(kWBlock) void wide_offsets_kernel(WArgs A) {
     __shared__ unsigned long long red[kWBlock / kWave];
-    unsigned long long cn = 0, ct = 0;
+    unsigned long long cn = 0, ct = 0, cc = 0;
     for (uint32_t b = 0; b < A.nq; b += kWBlock) {
         const uint32_t q = b + threadIdx.x;
         WPlan P{};
         if (q < A.nq) P = A.plans[q];
-        unsigned long long tn, tt;
+        unsigned long long tn, tt, tc;
         const unsigned long long en = wblock_excl<unsigned long long>(q < A.nq ? P.nd : 0, red, &tn);
         const unsigned long long et = wblock_excl<unsigned long long>(q < A.nq ? P.ntiles : 0, red, &tt);
+        const unsigned long long ec = wblock_excl<unsigned long long>(q < A.nq ? P.nchunks : 0, red, &tc);
         if (q < A.nq) {
             A.plans[q].tab_off = cn + en;
             A.plans[q].tile_base = static_cast<uint32_t>(ct + et);
+            A.plans[q].chunk_base = static_cast<uint32_t>(cc + ec);
         }
         cn += tn;
         ct += tt;
+        cc += tc;
     }
-    if (threadIdx.x == 0) A.tot->ctr = 0;
+    if (threadIdx.x == 0) {
+        A.tot->ctr = 0;
+        A.tot->chunks = cc;
+    }
 }
 
-// The distinct table of the list side and the tile map.
-__global__ __launch_bounds__(kWBlock) void wide_table_kernel(WArgs A) {
+// The distinct table of the list side: for every distinct list vertex x
+// with a nonempty scan row, in list order, its scan-row bounds, its run in
+// the list row and the scan entries of the earlier ones.  Built over chunks
+// of kWChunk list entries spread across the grid (a hub's list row of
+// millions of entries takes many workgroups): the count pass sizes each
+// chunk, the per-query scan turns the sizes into offsets, the fill pass
+// writes the rows.
+
+// The query owning list chunk c: the last query whose chunk_base <= c (a
+// query without chunks shares its base with the next query, and only
+// precedes the owner of that base).
+__device__ inline uint32_t chunk_query(const WArgs &A, uint32_t c) {
+    uint32_t lo = 0, hi = A.nq;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const WPlan &P = A.plans[mid];
+        if (P.chunk_base <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// This thread's segment of chunk cc of query P: the run starts with a
+// nonempty scan row among its kWSeg entries (xs[j + 1], scan row [lo, lo +
+// dg)), their count and their summed lengths.
+struct ChunkSeg {
+    uint32_t i0;
+    uint32_t xs[kWSeg + 1], lo[kWSeg], dg[kWSeg];
+    unsigned long long cnt, sum;
+};
+
+__device__ inline void chunk_segment(const WArgs &A, const WPlan &P, uint32_t cc, ChunkSeg &S) {
+    const bool fwd = P.dir != 0;
+    const uint32_t *Lcol = (fwd ? A.out_col : A.in_col) + P.list_beg;
+    const uint32_t *Srp = fwd ? A.out_rp : A.in_rp;   // the scanned rows live in the list CSR
+    S.i0 = cc * kWChunk + threadIdx.x * kWSeg;
+    const uint32_t i0 = S.i0;
+    S.xs[0] = (i0 > 0 && i0 < P.list_len) ? Lcol[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) S.xs[j + 1] = (i0 + j < P.list_len) ? Lcol[i0 + j] : 0xFFFFFFFFu;
+    S.cnt = S.sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) {
+        const bool first = i0 + j < P.list_len && S.xs[j + 1] != S.xs[j];
+        S.lo[j] = first ? Srp[S.xs[j + 1]] : 0u;
+        S.dg[j] = first ? Srp[S.xs[j + 1] + 1] - S.lo[j] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kWSeg; ++j) {
+        S.cnt += S.dg[j] ? 1 : 0;
+        S.sum += S.dg[j];
+    }
+}
+
+__global__ __launch_bounds__(kWBlock) void wide_chunk_count_kernel(WArgs A, uint32_t nchunks) {
+    __shared__ unsigned long long red[kWBlock / kWave];
+    __shared__ uint32_t sq;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        if (threadIdx.x == 0) sq = chunk_query(A, c);
+        __syncthreads();
+        const WPlan P = A.plans[sq];
+        ChunkSeg S;
+        chunk_segment(A, P, c - P.chunk_base, S);
+        const unsigned long long tc = wblock_sum(S.cnt, red);
+        const unsigned long long ts = wblock_sum(S.sum, red);
+        if (threadIdx.x == 0) A.cpart[c] = make_ulonglong2(tc, ts);
+        __syncthreads();
+    }
+}
+
+// Per query: the chunks' sizes become their exclusive prefixes; and the
+// tile map.
+__global__ __launch_bounds__(kWBlock) void wide_chunk_scan_kernel(WArgs A) {
     __shared__ unsigned long long red[kWBlock / kWave];
     const uint32_t q = blockIdx.x;
     const WPlan P = A.plans[q];
     if (P.status != 0) return;
     for (uint32_t j = threadIdx.x; j < P.ntiles; j += kWBlock) A.tile_q[P.tile_base + j] = q;
-    if (P.cost == 0) return;
-    const bool fwd = P.dir != 0;
-    const uint32_t *Lcol = (fwd ? A.out_col : A.in_col) + P.list_beg;
-    const uint32_t *Srp = fwd ? A.out_rp : A.in_rp;   // the scanned rows live in the list CSR
-    WRow *tab = A.tab + P.tab_off;
-    unsigned long long rank0 = 0, pre0 = 0;
-    for (uint32_t c = 0; c < P.list_len; c += kWChunk) {
-        // this thread's segment: its run starts with nonempty scan rows
-        const uint32_t i0 = c + threadIdx.x * kWSeg;
-        uint32_t xs[kWSeg + 1], lo[kWSeg], dg[kWSeg];
-        xs[0] = (i0 > 0 && i0 < P.list_len) ? Lcol[i0 - 1] : 0xFFFFFFFFu;
-#pragma unroll
-        for (uint32_t j = 0; j < kWSeg; ++j) xs[j + 1] = (i0 + j < P.list_len) ? Lcol[i0 + j] : 0xFFFFFFFFu;
-        unsigned long long cnt = 0, sum = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < kWSeg; ++j) {
-            const bool first = i0 + j < P.list_len && xs[j + 1] != xs[j];
-            lo[j] = first ? Srp[xs[j + 1]] : 0u;
-            dg[j] = first ? Srp[xs[j + 1] + 1] - lo[j] : 0u;
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kWSeg; ++j) {
-            cnt += dg[j] ? 1 : 0;
-            sum += dg[j];
-        }
+    unsigned long long r0 = 0, p0 = 0;
+    for (uint32_t b = 0; b < P.nchunks; b += kWBlock) {
+        const uint32_t j = b + threadIdx.x;
+        const ulonglong2 v = j < P.nchunks ? A.cpart[P.chunk_base + j] : make_ulonglong2(0ull, 0ull);
+        unsigned long long tr, tp;
+        const unsigned long long er = wblock_excl<unsigned long long>(v.x, red, &tr);
+        const unsigned long long ep = wblock_excl<unsigned long long>(v.y, red, &tp);
+        if (j < P.nchunks) A.cpart[P.chunk_base + j] = make_ulonglong2(r0 + er, p0 + ep);
+        r0 += tr;
+        p0 += tp;
+    }
+}
+
+__global__ __launch_bounds__(kWBlock) void wide_chunk_fill_kernel(WArgs A, uint32_t nchunks) {
+    __shared__ unsigned long long red[kWBlock / kWave];
+    __shared__ uint32_t sq;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        if (threadIdx.x == 0) sq = chunk_query(A, c);
+        __syncthreads();
+        const WPlan P = A.plans[sq];
+        const bool fwd = P.dir != 0;
+        const uint32_t *Lcol = (fwd ? A.out_col : A.in_col) + P.list_beg;
+        ChunkSeg S;
+        chunk_segment(A, P, c - P.chunk_base, S);
         unsigned long long tc, ts;
-        const unsigned long long rc = wblock_excl<unsigned long long>(cnt, red, &tc);
-        const unsigned long long pc = wblock_excl<unsigned long long>(sum, red, &ts);
-        unsigned long long rank = rank0 + rc, pre = pre0 + pc;
+        const unsigned long long rc = wblock_excl<unsigned long long>(S.cnt, red, &tc);
+        const unsigned long long pc = wblock_excl<unsigned long long>(S.sum, red, &ts);
+        const ulonglong2 base = A.cpart[c];
+        unsigned long long rank = base.x + rc, pre = base.y + pc;
+        WRow *tab = A.tab + P.tab_off;
 #pragma unroll
         for (uint32_t j = 0; j < kWSeg; ++j) {
-            if (dg[j]) {
-                const uint32_t i = i0 + j;
+            if (S.dg[j]) {
+                const uint32_t i = S.i0 + j;
                 uint32_t len = 1;   // the run of x: its relations to the list anchor
-                while (i + len < P.list_len && Lcol[i + len] == xs[j + 1]) ++len;
+                while (i + len < P.list_len && Lcol[i + len] == S.xs[j + 1]) ++len;
                 WRow R;
                 R.prefix = pre;
-                R.x = xs[j + 1];
-                R.scan_beg = lo[j];
+                R.x = S.xs[j + 1];
+                R.scan_beg = S.lo[j];
                 R.run_beg = i;
                 R.run_len = len;
                 tab[rank++] = R;
-                pre += dg[j];
+                pre += S.dg[j];
             }
         }
-        rank0 += tc;
-        pre0 += ts;
+        __syncthreads();
     }
 }
 
@@ -967,10 +1083,10 @@ __global__ __launch_bounds__(kWBlock) void wide_merge_kernel(WArgs A, mhr_wide_p
 // Workspace: a fixed part sized by the batch, then the parts sized by the
 // plan's totals.
 struct WLayout {
-    size_t plans, tot, gthr, qtotal, qmatch, fixed, tab, tile_q, tile_n, head, slots, total;
+    size_t plans, tot, gthr, qtotal, qmatch, fixed, tab, tile_q, tile_n, head, slots, cpart, total;
 };
 
-WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t nd, uint64_t tiles) {
+WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t nd, uint64_t tiles, uint64_t chunks) {
     WLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -989,6 +1105,7 @@ WLayout wide_layout(uint32_t nq, uint32_t k_max, uint64_t nd, uint64_t tiles) {
     L.tile_n = take(tiles * 4);
     L.head = take(tiles * 4);
     L.slots = take(tiles * k_max * sizeof(WCand));
+    L.cpart = take(chunks * sizeof(ulonglong2));
     L.total = o;
     return L;
 }
@@ -1028,6 +1145,11 @@ WArgs wide_args(const mhr_wide_graph *g, uint32_t nq, uint32_t k_max, char *ws, 
     A.tile_n = reinterpret_cast<uint32_t *>(ws + L.tile_n);
     A.head = reinterpret_cast<uint32_t *>(ws + L.head);
     A.slots = reinterpret_cast<WCand *>(ws + L.slots);
+    A.cpart = reinterpret_cast<ulonglong2 *>(ws + L.cpart);
+    A.out_cost = g->out.cost;
+    A.out_nd = g->out.ndist;
+    A.in_cost = g->in.cost;
+    A.in_nd = g->in.ndist;
     return A;
 }
 
@@ -1047,10 +1169,10 @@ mhr_status wide_check(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src,
 // stream is synchronised).
 mhr_status wide_plan(const mhr_wide_graph *g, uint32_t nq, const uint32_t *src, const uint32_t *dst,
                      const uint32_t *k, uint32_t k_max, char *ws, WTotals *tot, hipStream_t st) {
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
     WArgs A = wide_args(g, nq, k_max, ws, L0);
     MHR_HIP_TRY(hipMemsetAsync(A.tot, 0, sizeof(WTotals), st));
-    hipLaunchKernelGGL(wide_plan_kernel, dim3(nq), dim3(kWBlock), 0, st, A, src, dst, k);
+    hipLaunchKernelGGL(wide_plan_kernel, dim3(wcdiv(nq, kWBlock)), dim3(kWBlock), 0, st, A, src, dst, k);
     hipLaunchKernelGGL(wide_offsets_kernel, dim3(1), dim3(kWBlock), 0, st, A);
     MHR_HIP_TRY(hipGetLastError());
     MHR_HIP_TRY(hipMemcpyAsync(tot, A.tot, sizeof(WTotals), hipMemcpyDeviceToHost, st));
@@ -1148,13 +1270,13 @@ extern "C" mhr_status mhr_wide_workspace_size(const mhr_wide_graph *g, uint32_t 
     if (rc != MHR_OK) return rc;
     MHR_ARG_CHECK(bytes != nullptr, "mhr_wide_workspace_size: null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
     WBuf tmp;
     MHR_HIP_TRY(tmp.alloc(L0.fixed));
     WTotals tot{};
     rc = wide_plan(g, nq, src, dst, k, k_max, tmp.as<char>(), &tot, st);
     if (rc != MHR_OK) return rc;
-    *bytes = wide_layout(nq, k_max, tot.nd, tot.tiles).total;
+    *bytes = wide_layout(nq, k_max, tot.nd, tot.tiles, tot.chunks).total;
     return MHR_OK;
 }
 
@@ -1167,7 +1289,7 @@ extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, 
     if (rc != MHR_OK) return rc;
     MHR_ARG_CHECK(out && out_count && workspace, "mhr_wide_topk_paths: null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WLayout L0 = wide_layout(nq, k_max, 0, 0);
+    const WLayout L0 = wide_layout(nq, k_max, 0, 0, 0);
     if (ws_bytes < L0.fixed) {
         set_error("mhr_wide_topk_paths: workspace too small for the batch's plans");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
@@ -1178,7 +1300,7 @@ extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, 
     WTotals tot{};
     rc = wide_plan(g, nq, src, dst, k, k_max, ws, &tot, st);
     if (rc != MHR_OK) return rc;
-    const WLayout L = wide_layout(nq, k_max, tot.nd, tot.tiles);
+    const WLayout L = wide_layout(nq, k_max, tot.nd, tot.tiles, tot.chunks);
     if (ws_bytes < L.total) {
         set_error("mhr_wide_topk_paths: workspace too small: need " + std::to_string(L.total) + " bytes");
         return MHR_ERR_WORKSPACE_TOO_SMALL;
@@ -1189,7 +1311,19 @@ extern "C" mhr_status mhr_wide_topk_paths(const mhr_wide_graph *g, uint32_t nq, 
     }
     const WArgs A = wide_args(g, nq, k_max, ws, L);
     const bool bf = g->dtype == MHR_DTYPE_BF16;
-    hipLaunchKernelGGL(wide_table_kernel, dim3(nq), dim3(kWBlock), 0, st, A);
+    if (tot.chunks >= 0xFFFFFFFFull) {
+        set_error("mhr_wide_topk_paths: list rows too long for one batch");
+        return MHR_ERR_UNSUPPORTED;
+    }
+    const uint32_t nchunks = static_cast<uint32_t>(tot.chunks);
+    if (nchunks) {
+        const uint32_t cgrid = std::min<uint32_t>(nchunks, 65535u);
+        hipLaunchKernelGGL(wide_chunk_count_kernel, dim3(cgrid), dim3(kWBlock), 0, st, A, nchunks);
+        hipLaunchKernelGGL(wide_chunk_scan_kernel, dim3(nq), dim3(kWBlock), 0, st, A);
+        hipLaunchKernelGGL(wide_chunk_fill_kernel, dim3(cgrid), dim3(kWBlock), 0, st, A, nchunks);
+    } else {
+        hipLaunchKernelGGL(wide_chunk_scan_kernel, dim3(nq), dim3(kWBlock), 0, st, A);   // the tile map
+    }
     MHR_HIP_TRY(hipGetLastError());
     const uint32_t tiles = static_cast<uint32_t>(tot.tiles);
     MHR_HIP_TRY(mark(ev ? ev->gather_begin : nullptr));
