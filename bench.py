@@ -426,6 +426,70 @@ def run_wide(args):
     print(json.dumps(out), flush=True)
 
 
+def run_beam(args, cfg, g, h, r, t, X, Y, s, d):
+    """The generic multi-hop search (section 5: level by level, cycle
+    exclusion, targets recorded early, the best K children of each parent
+    carried to the next level) on the workload's graph and queries, scored
+    in FP64; one step = one mhr_beam_search call over the batch.  A sample of
+    queries is compared with the FP64 oracle's search (same vertex and
+    relation sequences in the same order; DistMult scores to 1e-13, the
+    device and host exp / log1p may differ in the last bit)."""
+    import torch
+    import oracle
+    import paper_2406_07727_amd as mhr
+    H, K = args.beam_hops, args.beam_k
+    sd = torch.from_numpy(s.view(np.int32)).cuda()
+    dd = torch.from_numpy(d.view(np.int32)).cuda()
+    for _ in range(max(1, args.warmup)):
+        res = g.beam(sd, dd, H, K)
+    torch.cuda.synchronize()
+    ev = HipEvents()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    e0, e1 = ev.create(), ev.create()
+    assert ev.hip.hipEventRecord(e0, stream) == 0
+    for _ in range(args.steps):
+        res = g.beam(sd, dd, H, K)
+    assert ev.hip.hipEventRecord(e1, stream) == 0
+    ms = ev.elapsed_ms(e0, e1) / args.steps
+    gp, gc, gr = mhr.beam_to_numpy(*res)
+    log(f"beam H={H} K={K}: {ms:.3f} ms per step, {int(gr.sum())} paths recorded")
+    parity = cpu = None
+    if not args.no_cpu_baseline:
+        oracle.build(force=False)
+        ns = min(args.cpu_sample or 64, len(s))
+        qi = np.linspace(0, len(s) - 1, ns).astype(np.int64)
+        og = oracle.Graph(cfg.graph.n, cfg.graph.R, h, r, t)
+        Xf, Yf = oracle.as_f32_table(X, cfg.emb.dtype), oracle.as_f32_table(Y, cfg.emb.dtype)
+        t0 = time.perf_counter()
+        op, oc, orr = og.beam(Xf, Yf, s[qi], d[qi], H, K, scorer=args.scorer, gamma=1.0)
+        dt = time.perf_counter() - t0
+        bad = 0
+        for j, q in enumerate(qi):
+            n = int(gc[q])
+            same = n == int(oc[j]) and int(gr[q]) == int(orr[j])
+            if same:
+                for a, b in zip(gp[q][:n], op[j][:n]):
+                    L = int(a["len"])
+                    same = same and L == int(b["len"]) and np.array_equal(a["v"][:L], b["v"][:L]) \
+                        and np.array_equal(a["r"][:L], b["r"][:L]) \
+                        and abs(float(a["score"]) - float(b["s"])) <= 1e-13 * max(1.0, abs(float(b["s"])))
+            bad += 0 if same else 1
+        parity = {"checked": int(ns), "mismatches": bad}
+        cpu = {"value": ns / dt, "unit": "queries/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"{ns} of the batch's queries, the oracle's level-by-level search in FP64; {dt:.2f} s",
+               "cpu_model": cpu_model()}
+        log(f"beam parity {parity}; oracle {ns / dt:.1f} queries/s")
+    out = {"metric": f"generic {H}-hop beam search (K={K}): queries/s", "value": len(s) / (ms * 1e-3),
+           "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.config} graph: {cfg.graph.n} vertices, {cfg.graph.R} relations, "
+                                  f"{cfg.graph.m} edges, d={cfg.emb.d} {cfg.emb.dtype}, {len(s)} queries, "
+                                  f"{args.scorer}, H={H}, K={K}",
+                      "paths_recorded": int(gr.sum())},
+           "roofline": None, "cpu_baseline": cpu, "parity": parity}
+    print(json.dumps(out), flush=True)
+
+
 def run_pruner(args, cfg, g, h, s, d):
     """The learned-pruner form: train the network on exact-search labels,
     then answer the held-out batch with the pruned search (and the exact
@@ -517,6 +581,9 @@ def main():
                     help="absolute rescoring band below the K-th score (0: the rigorous band alone)")
     ap.add_argument("--turing-batch", type=int, default=64, help="turing: pipelines per batched call")
     ap.add_argument("--wide-queries", type=int, default=16384, help="paper_kg / paper_kg_16th: queries per batch")
+    ap.add_argument("--beam-hops", type=int, default=0,
+                    help="run the generic multi-hop beam search with this many hops instead of the exact search")
+    ap.add_argument("--beam-k", type=int, default=32, help="beam search: children kept per parent and paths returned")
     ap.add_argument("--phase-clocks", action="store_true",
                     help="load the phase-clock build (libmhr_phase.so) and report the gather kernel's time and "
                          "bytes per phase (timings include the clock reads; not a benchmark line)")
@@ -574,6 +641,9 @@ def main():
     per_query_k = cfg.query.k_choices is not None
     kk = kd if per_query_k else int(k[0])
 
+    if args.beam_hops:
+        run_beam(args, cfg, g, h, r, t, X, Y, s, d)
+        return
     ev = HipEvents()
     if args.config == "pruner":
         pr = run_pruner(args, cfg, g, h, s, d)
