@@ -382,7 +382,9 @@ typedef struct mhr_wide_graph mhr_wide_graph;
  * 1..65535, num_edges < 2^32; head/rel/tail device arrays read during the
  * call only).  Identical triples are merged.  The handle owns the device
  * memory it allocates: per direction (n + 1) * 4 + 6 bytes per distinct
- * triple.  Synchronises `stream`.  Errors: INVALID_ARGUMENT, BAD_EDGE,
+ * triple, plus 8 bytes per vertex (the scan cost of its row as a query's
+ * frontier and its count of distinct neighbours with a nonempty row, which
+ * make query planning a constant-time lookup).  Synchronises `stream`.  Errors: INVALID_ARGUMENT, BAD_EDGE,
  * OUT_OF_MEMORY, DEVICE. */
 mhr_status mhr_wide_graph_create(const mhr_graph_desc *desc, void *stream, mhr_wide_graph **out);
 mhr_status mhr_wide_graph_destroy(mhr_wide_graph *g);

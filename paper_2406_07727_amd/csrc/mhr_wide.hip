@@ -750,7 +750,7 @@ __global__ __launch_bounds__(kWBlock) void wide_chunk_fill_kernel(WArgs A, uint3
 }
 
 struct WShared {
-    uint32_t tile, q, list_n, stage_n, nrows, r0;
+    uint32_t tile, q, list_n, stage_n, nrows;
     unsigned long long paths;
     WCand thr;
 };
@@ -878,17 +878,21 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
         unsigned long long mypaths = 0, mymatch = 0;
         for (uint64_t sb = t0; sb < t1; sb += kWSub) {
             const uint64_t se = min(t1, sb + kWSub);
-            __syncthreads();
-            if (threadIdx.x == 0) {   // last table row with prefix <= sb
-                uint32_t lo = 0, hi = sb == 0 ? 1u : P.nd;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (tab[mid].prefix <= sb) lo = mid; else hi = mid;
-                }
-                sh.r0 = lo;
+            __syncthreads();   // the previous sub-chunk's staged rows are no longer read
+            // the last table row with prefix <= sb, searched by the whole
+            // workgroup: each round tests kWBlock evenly spaced rows of the
+            // remaining range at once (the prefixes ascend, so the rows that
+            // pass are a leading run and their count locates the answer)
+            uint32_t lo = 0, hi = sb == 0 ? 1u : P.nd;
+            while (hi - lo > 1) {
+                const uint32_t stride = (hi - lo + kWBlock - 1) / kWBlock;
+                const uint32_t pos = lo + threadIdx.x * stride;
+                const bool ok = pos < hi && tab[pos].prefix <= sb;   // row lo always passes
+                const uint32_t c = static_cast<uint32_t>(__syncthreads_count(ok));
+                lo += (c - 1) * stride;
+                hi = min(hi, lo + stride);
             }
-            __syncthreads();
-            const uint32_t r0 = sh.r0;
+            const uint32_t r0 = lo;
             uint32_t valid = 0;
             for (uint32_t i = threadIdx.x; i < kWSub; i += kWBlock) {
                 const uint32_t r = r0 + i;
@@ -929,10 +933,19 @@ __global__ __launch_bounds__(kWBlock) void wide_gather_kernel(WArgs A, uint32_t 
                         while (ix + np < P.probe_len && pid[ix + np] == y) ++np;
                         prr = Prel + P.probe_beg + ix;
                     } else {
+                        // the shorter of y's own row (searched for the anchor)
+                        // and the probe row (searched for y)
                         const uint32_t b0 = Qrp[y], b1 = Qrp[y + 1];
-                        const uint32_t ix = b0 + wlower(Qcol + b0, b1 - b0, anchor_p);
-                        while (ix + np < b1 && Qcol[ix + np] == anchor_p) ++np;
-                        prr = Qrel + ix;
+                        if (b1 - b0 <= P.probe_len) {
+                            const uint32_t ix = b0 + wlower(Qcol + b0, b1 - b0, anchor_p);
+                            while (ix + np < b1 && Qcol[ix + np] == anchor_p) ++np;
+                            prr = Qrel + ix;
+                        } else {
+                            const uint32_t *pc = Pcol + P.probe_beg;
+                            const uint32_t ix = wlower(pc, P.probe_len, y);
+                            while (ix + np < P.probe_len && pc[ix + np] == y) ++np;
+                            prr = Prel + P.probe_beg + ix;
+                        }
                     }
                     if (np) {
                         ncombo = nl * np;
