@@ -93,34 +93,54 @@ class HipEvents:
         return float(ms.value)
 
 
-def gather_bytes(csr_out, csr_in, src, dst, d, elem):
-    """Algorithmic bytes of one gather launch (and per-query matched counts).
+def gather_bytes(csr_out, csr_in, src, dst, d, elem, k=None, totals=None):
+    """Algorithmic bytes of one gather launch, two ways, and the matched
+    middle pairs: (layout_bytes, model_bytes, matches).
 
-    Per query, with the plan the library uses (the cheaper of backward and
-    forward meet-in-the-middle): list row L entries (col + mask, 8 B) and the
-    row_ptr pairs of those rows (8 B); probe row P entries (8 B); scanned
-    entries C (col, 4 B); matched entries M (mask, 4 B); one embedding row
-    (d * elem B) per distinct matched list vertex, per distinct matched
-    scanned vertex, and for s and t."""
-    orp, ocol, _ = csr_out
-    irp, icol, _ = csr_in
+    Both follow the plan the library uses (the cheaper of backward and
+    forward meet-in-the-middle) and count one embedding row (d * elem B) per
+    distinct list-side and scan-side vertex on some path, plus s and t.
+
+    layout_bytes, this library's pair layout: list row L entries (col +
+    mask, 8 B) and the row_ptr pairs of those rows (8 B); probe row P
+    entries (8 B); scanned entries C (col, 4 B); matched entries M (mask,
+    4 B).
+
+    model_bytes, the per-query model of the hot-path scope's measurement
+    plan (one 4-byte entry per triple): 8 (2 + L) of row_ptr pairs, 4 bytes
+    per triple of s's out-row, t's in-row and the scanned rows, the
+    embedding rows, and 16 bytes per returned path (min(k, |P|), when k and
+    the path totals are given)."""
+    orp, ocol, omask = csr_out
+    irp, icol, imask = csr_in
     odeg = np.diff(orp).astype(np.int64)
     ideg = np.diff(irp).astype(np.int64)
-    total = 0
+    # triples per row (a pair entry carries one triple per relation bit)
+    ocs = np.concatenate([[0], np.cumsum(np.bitwise_count(omask).astype(np.int64))])
+    ics = np.concatenate([[0], np.cumsum(np.bitwise_count(imask).astype(np.int64))])
+    otrip = ocs[orp[1:].astype(np.int64)] - ocs[orp[:-1].astype(np.int64)]
+    itrip = ics[irp[1:].astype(np.int64)] - ics[irp[:-1].astype(np.int64)]
+    total = model = 0
     matches = 0
-    for s, t in zip(src.tolist(), dst.tolist()):
+    for qi, (s, t) in enumerate(zip(src.tolist(), dst.tolist())):
         bl = icol[irp[t]:irp[t + 1]]
         cost_b = int(ideg[bl].sum())
         al = ocol[orp[s]:orp[s + 1]]
         cost_f = int(odeg[al].sum())
         fwd = cost_f < cost_b
         if fwd:
-            lst, rp, col, probe = al, orp, ocol, icol[irp[t]:irp[t + 1]]
+            lst, rp, col, probe, trip = al, orp, ocol, icol[irp[t]:irp[t + 1]], otrip
         else:
-            lst, rp, col, probe = bl, irp, icol, ocol[orp[s]:orp[s + 1]]
+            lst, rp, col, probe, trip = bl, irp, icol, ocol[orp[s]:orp[s + 1]], itrip
         L, P = len(lst), len(probe)
+        out_paths = 0
+        if k is not None and totals is not None:
+            kq = int(k[qi]) if np.ndim(k) else int(k)
+            out_paths = min(kq, int(totals[qi]))
+        ends_trip = int(otrip[s]) + int(itrip[t])
         if L == 0 or P == 0:
             total += 16 * L + 8 * P
+            model += 8 * (2 + L) + 4 * ends_trip + 16 * out_paths
             continue
         starts, ends = rp[lst].astype(np.int64), rp[lst + 1].astype(np.int64)
         lens = ends - starts
@@ -138,8 +158,10 @@ def gather_bytes(csr_out, csr_in, src, dst, d, elem):
         else:
             M = ystar = xstar = 0
         matches += M
-        total += 16 * L + 8 * P + 4 * C + 4 * M + d * elem * (xstar + ystar + 2)
-    return total, matches
+        emb = d * elem * (xstar + ystar + 2)
+        total += 16 * L + 8 * P + 4 * C + 4 * M + emb
+        model += 8 * (2 + L) + 4 * (ends_trip + int(trip[lst].sum())) + emb + 16 * out_paths
+    return total, model, matches
 
 
 def gather_byte_parts(csr_out, csr_in, src, dst, d, elem):
@@ -732,14 +754,17 @@ def main():
         csr_out = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=False))
         csr_in = tuple(x.cpu().numpy().view(np.uint32) for x in g.export_csr(reverse=True))
         elem = 2 if cfg.emb.dtype == "bf16" else 4
-        nbytes, matches = gather_bytes(csr_out, csr_in, s, d, cfg.emb.d, elem)
-        nbytes += cfg.graph.R * cfg.emb.d * elem
+        layout_b, nbytes, matches = gather_bytes(csr_out, csr_in, s, d, cfg.emb.d, elem, k=k, totals=tot)
+        rel_table = cfg.graph.R * cfg.emb.d * elem   # once per launch
+        nbytes += rel_table
+        layout_b += rel_table
         achieved = nbytes / (gather_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
-                "kernel": "gather_kernel", "bytes_per_launch": int(nbytes), "kernel_ms": round(gather_avg, 4)}
-        log(f"gather algorithmic bytes {nbytes / 1e6:.1f} MB ({matches} matched middle pairs) "
-            f"in {time.perf_counter() - t1:.1f} s")
+                "kernel": "gather_kernel", "bytes_per_launch": int(nbytes), "bytes_per_launch_pair_layout":
+                int(layout_b), "kernel_ms": round(gather_avg, 4)}
+        log(f"gather algorithmic bytes {nbytes / 1e6:.1f} MB per the per-query model, {layout_b / 1e6:.1f} MB in the "
+            f"pair layout ({matches} matched middle pairs) in {time.perf_counter() - t1:.1f} s")
 
     if phases is not None:
         # per phase: the average workgroup's wall time per launch, and the

@@ -51,7 +51,6 @@ constexpr int kRowBatch = 32;             // list rows staged at a time
 constexpr int kSlab = 5 * kBlock;               // scored edge values per sub-batch
 constexpr int kQueue = kChunk + kBlock;    // queued matches: a partial sub-batch plus one chunk's hits
 constexpr int kStage = 3 * kBlock / 2;               // staged candidates before a merge
-constexpr uint32_t kMaxQuota = 8;         // candidates a thread stages per round
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kDefaultTileEdges = 32768;
 constexpr uint32_t kDefaultHashLog2 = 12;
@@ -96,7 +95,9 @@ constexpr int kMergeBlock = 256;            // threads of a per-query merge work
 // Tiles the workspace holds for nq queries.
 __host__ __device__ inline uint32_t tile_capacity(uint32_t nq) { return nq * 4u > 16384u ? nq * 4u : 16384u; }
 
-// Block reductions / scans (blockDim.x == NT, kBlock unless stated).
+// Block reductions / scans (blockDim.x == NT, kBlock unless stated).  The
+// scratch `lds` is written only after a barrier, so a later call may reuse
+// it without one at the end of this call (no other code writes it).
 template <class T, int NT = kBlock>
 __device__ inline T block_sum(T v, T *lds) {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -106,7 +107,6 @@ __device__ inline T block_sum(T v, T *lds) {
     __syncthreads();
     T s = 0;
     for (int w = 0; w < NT / kWave; ++w) s += lds[w];
-    __syncthreads();
     return s;
 }
 
@@ -119,7 +119,6 @@ __device__ inline float block_max(float v, float *lds) {
     __syncthreads();
     float s = lds[0];
     for (int w = 1; w < NT / kWave; ++w) s = fmaxf(s, lds[w]);
-    __syncthreads();
     return s;
 }
 
@@ -140,7 +139,6 @@ __device__ inline T block_incl_scan(T v, T *lds, T *total) {
         if (w < wave) base += x;
         tot += x;
     }
-    __syncthreads();
     *total = tot;
     return v + base;
 }
@@ -1508,7 +1506,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                     uint32_t vtot;
                     const uint32_t vincl = block_incl_scan<uint32_t>(nv2, sh->red32, &vtot);
                     const bool take = (mi < nmatch) && vincl <= static_cast<uint32_t>(kSlab);
-                    const uint32_t ncnt = block_sum<uint32_t>(take ? 1u : 0u, sh->red32);
+                    const uint32_t ncnt = static_cast<uint32_t>(__syncthreads_count(take));
                     if (take) {
                         sub_y[tid] = y;
                         sub_mp[tid] = mp;
@@ -1810,31 +1808,27 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         uint32_t ntot;
                         const uint32_t iincl = block_incl_scan<uint32_t>(nitems, sh->red32, &ntot);
                         sub_item[tid] = iincl - nitems;
+                        // Tiles probing through the directory leave the LDS hash table
+                        // unused: it then maps each item to its match (16-bit ids), so
+                        // the walk below reads the match instead of searching for it.
+                        const bool item_tab = heavy && ntot <= 2 * slots;
+                        uint16_t *item_match = reinterpret_cast<uint16_t *>(hkeys);   // hkeys and hvals: 2 * slots ids
+                        if (item_tab)
+                            for (uint32_t j = 0; j < nitems; ++j) item_match[iincl - nitems + j] = static_cast<uint16_t>(tid);
                         __syncthreads();
                         MHR_PHASE(kPhBounds);
                         MHR_COUNT(kCtItems, ntot);
                         // Each thread walks the items tid, tid + kBlock, ...; its cursor
-                        // (item, list position) survives the rounds, so a round ends
-                        // only when the stage quota is used up or the items run out.
+                        // (item, list position) survives the rounds.  A round runs until
+                        // every thread has walked all its items or some path found the
+                        // stage full; that path is retried after the stage is merged, so
+                        // a round ends with a barrier only when the stage fills.
                         uint32_t it = tid;
                         bool have = false;
                         uint32_t il = 0, nl = 0, lb = 0, sx = 0, sy = 0, rp_ = 0, rm_ = 0;
                         float perr_it = 0.0f;   // fast-score error bound of the current item's paths
                         float fp = 0.0f, fm = 0.0f;
-                        // threads that still hold items (bounds the emitters of a round)
-                        uint32_t nact = ntot < static_cast<uint32_t>(kBlock) ? ntot : static_cast<uint32_t>(kBlock);
-                        while (nact > 0) {
-                            // the free stage slots are shared by the threads still
-                            // walking (at least one each)
-                            if (sh->stage_n + nact > static_cast<uint32_t>(kStage)) {
-                                MHR_PHASE(kPhEnum);
-                                MHR_COUNT(kCtStaged, sh->stage_n);
-                                MHR_COUNT(kCtMerges, 1);
-                                merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
-                                MHR_PHASE(kPhMerge);
-                            }
-                            uint32_t quota = (static_cast<uint32_t>(kStage) - sh->stage_n) / nact;
-                            if (quota > kMaxQuota) quota = kMaxQuota;
+                        for (;;) {
                             const Cand thr = sh->thr;
                             const float tS = EXACT ? thr_exact : thr.s;
                             // exhaustive pass: a path whose fast score plus its error
@@ -1846,16 +1840,20 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                                     : fmaxf(P.kth_low, thr.a != 0xFFFFFFFFu
                                                                             ? thr.s - 1e-6f * fabsf(thr.s)
                                                                             : -__builtin_huge_valf());
-                            uint32_t emitted = 0;
-                            bool dropped = false;
-                            while (emitted < quota) {
+                            bool dropped = false, full = false;
+                            for (;;) {
                                 if (!have) {
                                     if (it >= ntot) break;
                                     // the last match whose items start at or before `it`
-                                    uint32_t lo = 0, hi = ncnt;
-                                    while (hi - lo > 1) {
-                                        const uint32_t mid = (lo + hi) >> 1;
-                                        if (sub_item[mid] <= it) lo = mid; else hi = mid;
+                                    uint32_t lo = 0;
+                                    if (item_tab) {
+                                        lo = item_match[it];
+                                    } else {
+                                        uint32_t hi = ncnt;
+                                        while (hi - lo > 1) {
+                                            const uint32_t mid = (lo + hi) >> 1;
+                                            if (sub_item[mid] <= it) lo = mid; else hi = mid;
+                                        }
                                     }
                                     const uint32_t m = lo;
                                     const uint32_t np = __popc(sub_mp[m]), nm = __popc(sub_mm[m]);
@@ -1894,7 +1892,6 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                     continue;
                                 }
                                 const uint32_t rl_ = rowrel[lb + il];
-                                ++il;
                                 Cand cd;
                                 cd.a = fwd ? sx : sy;
                                 cd.b = fwd ? sy : sx;
@@ -1909,15 +1906,27 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                                 // the stage is merged); fast pass: the total order
                                 const bool keep = EXACT || cand_better(cd, thr);
                                 if (keep) {
-                                    uint32_t slot = atomicAdd(&sh->stage_n, 1u);
+                                    const uint32_t slot = atomicAdd(&sh->stage_n, 1u);
+                                    if (slot >= static_cast<uint32_t>(kStage)) {
+                                        full = true;   // this path again after the merge
+                                        break;
+                                    }
                                     stage[slot] = cd;
-                                    ++emitted;
                                 } else {
                                     dropped = true;
                                 }
+                                ++il;
                             }
                             if (dropped) sh->truncated = 1;
-                            nact = static_cast<uint32_t>(__syncthreads_count(it < ntot));
+                            if (!__syncthreads_or(full)) break;   // every item walked
+                            // the stage is full (the reservations past its end wrote nothing)
+                            if (tid == 0) sh->stage_n = kStage;
+                            __syncthreads();
+                            MHR_PHASE(kPhEnum);
+                            MHR_COUNT(kCtStaged, kStage);
+                            MHR_COUNT(kCtMerges, 1);
+                            merge_stage<KC, EXACT, BF16, TE>(list, stage, sh, mkeys, A, P.s, P.t);
+                            MHR_PHASE(kPhMerge);
                         }
                     }
                     m0 += ncnt;
