@@ -1811,8 +1811,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         // Tiles probing through the directory leave the LDS hash table
                         // unused: it then maps each item to its match (16-bit ids), so
                         // the walk below reads the match instead of searching for it.
-                        const bool item_tab = heavy && ntot <= 2 * slots;
-                        uint16_t *item_match = reinterpret_cast<uint16_t *>(hkeys);   // hkeys and hvals: 2 * slots ids
+                        const bool item_tab = heavy && ntot <= 4 * slots;
+                        uint16_t *item_match = reinterpret_cast<uint16_t *>(hkeys);   // hkeys and hvals: 4 * slots ids
                         if (item_tab)
                             for (uint32_t j = 0; j < nitems; ++j) item_match[iincl - nitems + j] = static_cast<uint16_t>(tid);
                         __syncthreads();
