@@ -200,11 +200,13 @@ typedef struct mhr_query_opts {
     float band_abs;        /* minimum width of the rescoring band below the K-th score:
                               every candidate with fast-pass score >= S_K - max(2 eps, band_abs)
                               that the tile lists hold is rescored in float-float (0 = the
-                              rigorous band 2 eps alone, which already makes the result exact; a
-                              wider band costs time, and a band wider than the tile lists hold
-                              sends the query to the exhaustive pass, which rescores only the
-                              paths that can still be returned).  The result does not depend on
-                              band_abs.  Finite, >= 0. */
+                              rigorous band 2 eps alone, which already makes the result exact).
+                              A candidate below S_K - 2 eps cannot be returned, so one that a
+                              tile list dropped is never looked for again: the exhaustive pass
+                              runs only when a dropped candidate could still be returned, and
+                              that does not depend on band_abs.  A wider band costs only the
+                              extra rescoring.  The result does not depend on band_abs.
+                              Finite, >= 0. */
     uint32_t reserved[7];  /* must be zero */
 } mhr_query_opts;
 

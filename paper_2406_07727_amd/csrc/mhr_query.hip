@@ -19,8 +19,8 @@
 //             lists, takes every
 //             candidate whose score lies within twice the error bound of the
 //             K-th, rescores them in float-float and writes the ranked
-//             result.  If a truncated tile could still hold a band member
-//             the query is marked for the exhaustive pass.
+//             result.  If a truncated tile could still hold a path that
+//             can be returned the query is marked for the exhaustive pass.
 //   exact     gather again for marked queries, scoring in float-float every
 //             path above the band threshold that can still be returned (its
 //             fast score plus error bound reaches both the kept list and a
@@ -2221,11 +2221,18 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *o
     const float theta = c[kk - 1].s;
     // band threshold, rounded down generously
     const float thr = (theta - fmaxf(2.0f * eps, A.band_abs)) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
-    // overflow: a candidate above the threshold was dropped, here or by a tile
-    int over_part = (threadIdx.x == 0 && s_drop >= thr) ? 1 : 0;
+    // K candidates have fast scores >= theta and errors <= eps, so the true
+    // K-th score is at least theta - eps; a path whose fast score is below
+    // theta - 2 eps (rounded down generously) scores strictly less and can
+    // never be returned.  Only such a path may be dropped unseen: the
+    // exhaustive pass is needed when a tile list or this selection dropped a
+    // candidate at or above that line, whatever the band's width (a wider
+    // band only adds kept candidates to the rescoring below).
+    const float thr_ret = (theta - 2.0f * eps) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
+    int over_part = (threadIdx.x == 0 && s_drop >= thr_ret) ? 1 : 0;
     for (uint32_t j = threadIdx.x; j < P.ntiles; j += kMergeBlock) {
         const TileHeader &h = A.hdr[P.tile_base + j];
-        if (h.truncated && h.cutoff >= thr) over_part = 1;
+        if (h.truncated && h.cutoff >= thr_ret) over_part = 1;
     }
     // the band: the sorted prefix at or above the threshold
     const uint32_t nb = static_cast<uint32_t>(__syncthreads_count(threadIdx.x < kept && c[threadIdx.x].s >= thr));
@@ -2233,8 +2240,7 @@ __global__ __launch_bounds__(kMergeBlock) void merge_kernel(GArgs A, mhr_path *o
         if (threadIdx.x == 0) {
             A.plans[q].flags = kNeedExact;
             A.plans[q].thr = thr;
-            // K candidates have fast scores >= theta and errors <= eps, so the
-            // true K-th score is at least theta - eps (rounded down generously)
+            // the lower bound on the true K-th score, rounded down generously
             A.plans[q].kth_low = (theta - eps) - 4.0f * kUnit * fabsf(theta) - 1e-30f;
             A.plans[q].total = tot;
             atomicAdd(&A.ctrl->exact_n, 1u);

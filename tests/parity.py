@@ -57,6 +57,42 @@ def gpu_graph(n, R, h, r, t, X, Y, dtype="f32", scorer="distmult", gamma=1.0):
     return g
 
 
+def tied_tables(X, Y, dtype, zero_frac, seed):
+    """Embedding tables that make many paths tie at the top: entity entries
+    made non-negative and relation entries non-positive, so every DistMult
+    value is <= 0, and the entity rows of a seeded fraction zero_frac of the
+    vertices zeroed.  An edge with a zero endpoint then has value exactly 0,
+    and every path whose three edges all have one ties at -3 ln 2, above all
+    others (the log-sigmoid rises with its argument)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    zero = rng.random(X.shape[0]) < zero_frac
+    if dtype == "bf16":   # bit patterns: the sign is the top bit
+        Xt = np.array(X, dtype=np.uint16, copy=True) & np.uint16(0x7FFF)
+        Yt = np.array(Y, dtype=np.uint16, copy=True) | np.uint16(0x8000)
+    else:
+        Xt = np.abs(np.array(X, dtype=np.float32, copy=True))
+        Yt = -np.abs(np.array(Y, dtype=np.float32, copy=True))
+    Xt[zero] = 0
+    return Xt, Yt
+
+
+def assert_same_result(x, y):
+    """Two GPU results of one batch are identical: counts, totals, statuses,
+    and every path field (the precision-tie flag of a query's last path is
+    left out: it compares that path with the next candidate, which depends
+    on how many candidates were rescored)."""
+    px, cx, tx, sx = x
+    py, cy, ty, sy = y
+    assert np.array_equal(cx, cy) and np.array_equal(tx, ty) and np.array_equal(sx, sy)
+    for f in ("a", "b", "r1", "r2", "r3", "score", "err_bound"):
+        assert np.array_equal(px[f], py[f]), f"field {f} differs"
+    fx, fy = px["flags"].copy(), py["flags"].copy()
+    for q in np.nonzero(cx > 0)[0]:
+        fx[q, cx[q] - 1] &= ~np.uint16(TIE_FLAG)
+        fy[q, cy[q] - 1] &= ~np.uint16(TIE_FLAG)
+    assert np.array_equal(fx, fy), "path flags differ"
+
+
 def run_gpu(g, s, d, k, k_max=None, opts=None):
     import torch
     res = g.topk(s, d, k, k_max=k_max, opts=opts)

@@ -11,7 +11,8 @@ import pytest
 
 import kgsynth
 import oracle
-from tests.parity import OracleResult, compare, gpu_graph, run_gpu, run_oracle, say, workload
+from tests.parity import (OracleResult, assert_same_result, compare, gpu_graph, run_gpu, run_oracle, say,
+                          tied_tables, workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -436,9 +437,10 @@ def _precision_sample():
 def test_precision_full_size_subsample(band):
     """The 4M-vertex / 64M-edge graph with d=256 bfloat16 embeddings and 32
     relations, all 4,096 queries at K=32 in one launch (bfloat16 MFMA
-    scoring), with the rigorous band alone and with the fixed 1e-2 band
-    (about half the queries then take the exhaustive float-float pass); the
-    first 256 queries are checked against the oracle."""
+    scoring), with the rigorous band alone and with the fixed 1e-2 band; the
+    first 256 queries are checked against the oracle.  The wider band
+    rescores more kept candidates but returns the same bytes and sends no
+    more queries to the exhaustive pass."""
     import paper_2406_07727_amd as mhr
     say(f"case precision full batch band={band}")
     cfg, (h, r, t), (X, Y), (s, d), sample, orc = _precision_sample()
@@ -455,7 +457,37 @@ def test_precision_full_size_subsample(band):
     say(f"precision band={band}: {len(sample)} queries equal the oracle; {nx} queries took the exhaustive pass; "
         f"{ties} precision ties")
     if band > 0:
-        assert nx > 0 and np.sum((st[sample] & 4) != 0) > 0
+        assert_same_result(gpu, run_gpu(g, s, d, 32))
+
+
+@pytest.mark.timeout(900)
+def test_precision_full_size_tied_exhaustive():
+    """The precision graph at full size with tables that make the best paths
+    tie (tied_tables: half the entity rows zero, every DistMult value <= 0):
+    the paths of score -3 ln 2 outnumber the tile lists, so queries take the
+    exhaustive float-float pass, which skips the lower paths and ranks the
+    tied ones by ids.  All 4,096 queries in one launch; the first 64 against
+    the oracle."""
+    say("case precision full batch, tied top")
+    cfg, (h, r, t), (X, Y), (s, d, _) = workload("precision")
+    n, R = cfg.graph.n, cfg.graph.R
+    Xt, Yt = tied_tables(X, Y, "bf16", 0.5, seed=5)
+    g = gpu_graph(n, R, h, r, t, Xt, Yt, "bf16")
+    gpu = run_gpu(g, s, d, 32)
+    p, c, tot, st = gpu
+    assert np.all((st & ~np.uint32(4)) == 0)
+    assert np.all(c == np.minimum(32, tot))
+    sample = np.arange(64)
+    orc = _oracle_in_chunks("precision_tied", n, R, h, r, t, Xt, Yt, s[sample], d[sample], 32, "bf16", chunk=32)
+    ties = compare(gpu, orc, queries=list(sample))
+    nx = int(np.sum((st & 4) != 0))
+    say(f"precision tied: {nx} queries took the exhaustive pass, {int(np.sum((st[sample] & 4) != 0))} of the "
+        f"sample; {ties} precision ties")
+    assert nx > 0 and np.sum((st[sample] & 4) != 0) > 0
+    # every value is <= 0, so no path beats -3 ln 2; most queries reach it
+    top = p["score"][c > 0, 0]
+    tie = np.float32(-3 * np.log(2))
+    assert np.all(top <= tie) and np.mean(top == tie) > 0.5
 
 
 def test_plan_replays_match_eager():
@@ -530,13 +562,31 @@ def test_batched_full_size_sample():
 @pytest.mark.parametrize("name", ["dense_tiny", "hub_r32_bf16"])
 def test_wide_rescoring_band_keeps_results(name):
     """A fixed rescoring band of 1e-2 below the K-th score (the precision
-    form's margin): far wider than the rigorous band, so most queries take
-    the exhaustive float-float pass; the results still equal the oracle's."""
+    form's margin), far wider than the rigorous band and, at d = 64, wider
+    than the tile lists: the results equal the oracle's and are the same
+    bytes as with the rigorous band alone."""
     import paper_2406_07727_amd as mhr
-    cfg = kgsynth.CONFIGS[name]
     opts = mhr.QueryOpts()
     opts.band_abs = 1e-2
     gpu, orc = _small(name, opts=opts)
     compare(gpu, orc)
-    if name == "hub_r32_bf16":   # d = 64: the band holds most paths, beyond the tile lists
-        assert np.sum((gpu[3] & 4) != 0) > 0
+    base, _ = _small(name)
+    assert_same_result(gpu, base)
+
+
+@pytest.mark.parametrize("name", ["hub_tiny", "hub_r32_bf16"])
+def test_tied_top_exhaustive_pass(name):
+    """Tables whose best paths tie (tied_tables): the tied paths outnumber
+    the tile lists, so queries take the exhaustive pass; it skips the paths
+    below the tie and ranks the tied ones by (a, b, r1, r2, r3)."""
+    cfg, (h, r, t), (X, Y), (s, d, kk) = workload(name)
+    n, R = cfg.graph.n, cfg.graph.R
+    Xt, Yt = tied_tables(X, Y, cfg.emb.dtype, 0.5, seed=3)
+    say(f"case tied top {name}")
+    g = gpu_graph(n, R, h, r, t, Xt, Yt, cfg.emb.dtype)
+    gpu = run_gpu(g, s, d, kk, k_max=int(kk.max()))
+    orc = run_oracle(n, R, h, r, t, Xt, Yt, s, d, kk, cfg.emb.dtype)
+    compare(gpu, orc)
+    nx = int(np.sum((gpu[3] & 4) != 0))
+    say(f"tied top {name}: {nx} of {len(s)} queries took the exhaustive pass")
+    assert nx > 0
