@@ -51,6 +51,7 @@ constexpr int kRowBatch = 32;             // list rows staged at a time
 constexpr int kSlab = 5 * kBlock;               // scored edge values per sub-batch
 constexpr int kQueue = kChunk + kBlock;    // queued matches: a partial sub-batch plus one chunk's hits
 constexpr int kStage = 3 * kBlock / 2;               // staged candidates before a merge
+constexpr uint32_t kItemRun = 16;           // item ranges longer than this are written by a whole wave
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kDefaultTileEdges = 32768;
 constexpr uint32_t kDefaultHashLog2 = 12;
@@ -1813,8 +1814,22 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                         // the walk below reads the match instead of searching for it.
                         const bool item_tab = heavy && ntot <= 4 * slots;
                         uint16_t *item_match = reinterpret_cast<uint16_t *>(hkeys);   // hkeys and hvals: 4 * slots ids
-                        if (item_tab)
-                            for (uint32_t j = 0; j < nitems; ++j) item_match[iincl - nitems + j] = static_cast<uint16_t>(tid);
+                        if (item_tab) {
+                            // short ranges by their own thread; long ones by the whole
+                            // wave, one range at a time (a match can hold hundreds of
+                            // items, which one thread would write while the rest wait)
+                            const uint32_t beg = iincl - nitems;
+                            const bool longr = nitems > kItemRun;
+                            if (!longr)
+                                for (uint32_t j = 0; j < nitems; ++j) item_match[beg + j] = static_cast<uint16_t>(tid);
+                            const uint32_t lane = tid & (kWave - 1);
+                            for (uint64_t lm = __ballot(longr); lm != 0; lm &= lm - 1) {
+                                const int L = __ffsll(static_cast<unsigned long long>(lm)) - 1;
+                                const uint32_t b = __shfl(beg, L, kWave), n = __shfl(nitems, L, kWave);
+                                const uint16_t owner = static_cast<uint16_t>(tid - lane + static_cast<uint32_t>(L));
+                                for (uint32_t j = lane; j < n; j += kWave) item_match[b + j] = owner;
+                            }
+                        }
                         __syncthreads();
                         MHR_PHASE(kPhBounds);
                         MHR_COUNT(kCtItems, ntot);
