@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # fetched (scale 2.0), WRITE_SIZE read 1048576 KiB (scale 1.0).  Valid only
 # for the kernel sources they were taken on (sha256 over the query sources).
 TRAFFIC = {
-    "sources_sha256": "55ca40f98bf3f0c671b9649a037cd54e77a2b3a6b025c78341925f7538bf5c45",
-    "fetch_kib": 473880.0,
+    "sources_sha256": "0b9007da003a26f479831b45210ce6cceddd52eb1aa1b814942f2af17b7531d3",
+    "fetch_kib": 464367.9,
     "write_kib": 3019.1,
     "fetch_scale": 2.0,
     "write_scale": 1.0,

@@ -48,7 +48,7 @@ constexpr int kBlock = 512;
 constexpr int kEPT = 8;                   // scan entries per thread per chunk
 constexpr int kChunk = kBlock * kEPT;     // scan entries per chunk
 constexpr int kRowBatch = 32;             // list rows staged at a time
-constexpr int kSlab = 5 * kBlock;               // scored edge values per sub-batch
+constexpr int kSlab = 8 * kBlock;               // scored edge values per sub-batch
 constexpr int kQueue = kChunk + kBlock;    // queued matches: a partial sub-batch plus one chunk's hits
 constexpr int kStage = 3 * kBlock / 2;               // staged candidates before a merge
 constexpr uint32_t kItemRun = 16;           // item ranges longer than this are written by a whole wave
