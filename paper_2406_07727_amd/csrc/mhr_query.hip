@@ -1388,40 +1388,27 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GArgs A) {
                 }
                 if (!last) chunk_entries(cb + kChunk, ps_n, ys_n);
                 if (!heavy) {
-                    // first probe of every entry together, then the collision
-                    // chains of all the thread's entries advanced side by side
-                    // (one round of loads per step, not one chain after another)
+                    // first probe of every entry together, then the rare
+                    // collision chains
                     uint32_t slot[kEPT], key[kEPT];
-                    bool act[kEPT];
 #pragma unroll
                     for (int k = 0; k < kEPT; ++k) {
                         slot[k] = (ys[k] * 0x9E3779B1u) >> (32 - A.hash_log2);
                         key[k] = ps[k] != kEmpty ? hkeys[slot[k]] : kEmpty;
                     }
-                    bool any = false;
 #pragma unroll
                     for (int k = 0; k < kEPT; ++k) {
-                        act[k] = key[k] != kEmpty && key[k] != ys[k];
-                        any |= act[k];
-                    }
-                    while (any) {   // ends: the table is at most half full
-#pragma unroll
-                        for (int k = 0; k < kEPT; ++k)
-                            if (act[k]) {
-                                slot[k] = (slot[k] + 1) & smask;
-                                key[k] = hkeys[slot[k]];
-                            }
-                        any = false;
-#pragma unroll
-                        for (int k = 0; k < kEPT; ++k) {
-                            act[k] = act[k] && key[k] != kEmpty && key[k] != ys[k];
-                            any |= act[k];
+                        const uint32_t y = ys[k];
+                        hits[k] = false;
+                        mps[k] = 0;
+                        while (key[k] != kEmpty && key[k] != y) {
+                            slot[k] = (slot[k] + 1) & smask;
+                            key[k] = hkeys[slot[k]];
                         }
-                    }
-#pragma unroll
-                    for (int k = 0; k < kEPT; ++k) {
-                        hits[k] = ps[k] != kEmpty && key[k] == ys[k];
-                        mps[k] = hits[k] ? hvals[slot[k]] : 0u;
+                        if (ps[k] != kEmpty && key[k] == y) {
+                            hits[k] = true;
+                            mps[k] = hvals[slot[k]];
+                        }
                     }
                 } else {
                     // Directory probes in stages, each stage's loads issued
